@@ -1,0 +1,219 @@
+"""Seeded synthetic workloads: parameter records and initial fields.
+
+This module holds no arithmetic of the lattice Boltzmann method itself: it only
+draws seeded random numbers, lays out initial fields on the grid and converts
+the paper's dimensionless parameters to lattice units (dx = dt = 1):
+
+    D_lat = D dt*/dx*^2,  nu_lat = nu dt*/dx*^2,  F_lat = F dt*^2/dx*,
+    S_lat = S dt*  (a source linear in phi scales its rate the same way),
+
+where dx*, dt* are the dimensionless grid spacing and time step.  Both the
+GPU library's binding and the CPU oracle's wrapper consume the same plain
+``dict`` records and arrays produced here.
+
+Record keys: nx, ny, m, model ('linear' | 'chemotaxis'), collision ('bgk' |
+'mrt'), r_kind ('step' | 'smooth'), tau_f, rho0, mrt_s[9], D[m][m], K[m][m],
+F0[2], Fphi[m][2], chi, beta, cstar, eps, fluid_bc[4], scalar_bc[4][m],
+wall[4][m].  Sides are ordered x-, x+, y-, y+.  Fields are phi0[m][ny][nx],
+u0[2][ny][nx], p0[ny][nx]; node (i, j) sits at the cell centre
+((i + 1/2) dx, (j + 1/2) dx), so half-way walls lie on the domain edges.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# MRT rates for the non-hydrodynamic moments (e, eps, q) used by default;
+# the stress rates are overwritten by 1/tau_f, the conserved ones are inert.
+MRT_DEFAULT = [1.0, 1.4, 1.4, 1.0, 1.2, 1.0, 1.2, 1.0, 1.0]
+
+
+def _base(nx, ny, m, tau_f, D, **kw):
+    wl = {
+        "nx": int(nx), "ny": int(ny), "m": int(m), "model": "linear", "collision": "bgk",
+        "r_kind": "step", "tau_f": float(tau_f), "rho0": 1.0, "mrt_s": list(MRT_DEFAULT),
+        "D": np.asarray(D, dtype=np.float64).reshape(m, m).tolist(),
+        "K": np.zeros((m, m)).tolist(), "F0": [0.0, 0.0], "Fphi": np.zeros((m, 2)).tolist(),
+        "chi": 0.0, "beta": 0.0, "cstar": 0.3, "eps": 0.0,
+        "fluid_bc": ["periodic"] * 4, "scalar_bc": [["periodic"] * m for _ in range(4)],
+        "wall": np.zeros((4, m)).tolist(),
+    }
+    wl.update(kw)
+    return wl
+
+
+def cell_centres(nx, ny):
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    return np.meshgrid(x, y)  # X[j, i], Y[j, i]
+
+
+# ---------------------------------------------------------------------------
+# Plain-method case: Taylor-Green flow carrying two cross-diffusing Gaussian blobs
+# ---------------------------------------------------------------------------
+def taylor_green_blobs(n=64, seed=1, steps=1000, tau_f=0.8, U0=0.01, sigma=6.0,
+                       D=((0.01, 0.002), (0.001, 0.01))):
+    """Periodic n x n, D2Q9 BGK (tau_f), m = 2, constant D, no source, no force."""
+    wl = _base(n, n, 2, tau_f, D)
+    X, Y = cell_centres(n, n)
+    k = 2.0 * math.pi / n
+    u0 = np.stack([-U0 * np.cos(k * X) * np.sin(k * Y), U0 * np.sin(k * X) * np.cos(k * Y)])
+    p0 = -(U0 * U0 / 4.0) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = rng.uniform(0.0, n, size=(2, 2))
+    phi0 = np.empty((2, n, n))
+    for a in range(2):
+        dx = (X - centres[a, 0] + n / 2) % n - n / 2  # minimum image
+        dy = (Y - centres[a, 1] + n / 2) % n - n / 2
+        phi0[a] = 1.0 + np.exp(-(dx * dx + dy * dy) / (2 * sigma * sigma))
+    wl["steps"] = steps
+    wl["name"] = f"taylor_green_blobs_{n}x{n}"
+    return wl, phi0, u0, p0
+
+
+# ---------------------------------------------------------------------------
+# Chemotaxis-fluid (Sec. 3.1): bacteria n, oxygen c
+# ---------------------------------------------------------------------------
+def chemotaxis(nx, ny, dx, dt, alpha, beta, delta, gamma, Sc, n0, c0=None,
+               r_kind="step", cstar=0.3, eps=None, top_fluid="freeslip"):
+    """Dimensionless chemotaxis-fluid system (Sec. 3.1) in lattice units.
+
+    D = [[1, -alpha r(c) n], [0, delta]], S = (0, -beta r(c) n), nu = Sc,
+    F = -Sc gamma n z.  Top: no flux of n, c = 1 (Dirichlet), free-slip fluid;
+    bottom: no flux, no-slip; periodic in x.
+    """
+    s = dt / (dx * dx)
+    wl = _base(nx, ny, 2, 3.0 * Sc * s + 0.5, [[1.0 * s, 0.0], [0.0, delta * s]])
+    wl.update({
+        "model": "chemotaxis", "chi": alpha * s, "beta": beta * dt, "cstar": cstar,
+        "r_kind": r_kind, "eps": (dx if eps is None else eps),
+        "Fphi": [[0.0, -Sc * gamma * dt * dt / dx], [0.0, 0.0]],
+        "fluid_bc": ["periodic", "periodic", "noslip", top_fluid],
+        "scalar_bc": [["periodic", "periodic"], ["periodic", "periodic"],
+                      ["noflux", "noflux"], ["noflux", "dirichlet"]],
+        "wall": [[0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [0.0, 1.0]],
+        "dx": dx, "dt": dt,
+    })
+    phi0 = np.empty((2, ny, nx))
+    phi0[0] = n0
+    phi0[1] = 1.0 if c0 is None else c0
+    u0 = np.zeros((2, ny, nx))
+    return wl, phi0, u0, np.zeros((ny, nx))
+
+
+def chemotaxis_plume(nx=512, ny=256, seed=2, ratio=6.25e-4, alpha=10.0, beta=20.0, delta=5.0,
+                     gamma=2000.0, Sc=500.0, amp=0.01):
+    """Plume-formation workload (Sec. 3.1.3 parameters) on [-1, 1] x [0, 1].
+
+    dx = 1/ny, dt = ratio dx^2 (the paper's dt/dx^2 of Sec. 3.1.1);
+    n0 = 1 + amp U(-1, 1) (seeded), c0 = 1, u0 = 0.
+    """
+    dx = 1.0 / ny
+    dt = ratio * dx * dx
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n0 = 1.0 + amp * rng.uniform(-1.0, 1.0, size=(ny, nx))
+    wl, phi0, u0, p0 = chemotaxis(nx, ny, dx, dt, alpha, beta, delta, gamma, Sc, n0)
+    wl["name"] = f"chemotaxis_plume_{nx}x{ny}"
+    return wl, phi0, u0, p0
+
+
+def chemotaxis_steady(ny=50, nx=4, ratio=0.01, alpha=10.0, beta=10.0, delta=5.0, gamma=1000.0,
+                      Sc=500.0):
+    """Steady validation case of Sec. 3.1.1: n0 = pi/40, c0 = 1, u0 = 0 on a
+    strip of the x-homogeneous domain (periodic in x), dx = 1/ny."""
+    dx = 1.0 / ny
+    dt = ratio * dx * dx
+    n0 = np.full((ny, nx), math.pi / 40.0)
+    wl, phi0, u0, p0 = chemotaxis(nx, ny, dx, dt, alpha, beta, delta, gamma, Sc, n0)
+    wl["name"] = f"chemotaxis_steady_{nx}x{ny}"
+    return wl, phi0, u0, p0
+
+
+# ---------------------------------------------------------------------------
+# Double-diffusive convection with Soret and Dufour effects (Sec. 3.2)
+# ---------------------------------------------------------------------------
+def ddc(L, Ra, Pr, Le, Nc, Sr, Df, A=1.0, u_lat=0.05, collision="bgk"):
+    """Dimensionless DDC cavity [0, 1] x [0, A] on L x round(A L) nodes.
+
+    D = [[1, Df], [Sr/Le, 1/Le]], nu = Pr, F = Ra Pr (T + Nc C) z, S = 0.
+    T = C = 1 at x = 0 and 0 at x = 1 (Dirichlet), no flux on y walls, no-slip
+    everywhere; T = C = u = 0 at t = 0.  dt* is fixed by the lattice velocity
+    scale sqrt(Ra Pr) dt*/dx* = u_lat.
+    """
+    nx, ny = int(L), int(round(A * L))
+    dx = 1.0 / L
+    dt = u_lat * dx / math.sqrt(Ra * Pr)
+    s = dt / (dx * dx)
+    D = np.array([[1.0, Df], [Sr / Le, 1.0 / Le]]) * s
+    g = Ra * Pr * dt * dt / dx
+    wl = _base(nx, ny, 2, 3.0 * Pr * s + 0.5, D)
+    wl.update({
+        "collision": collision,
+        "Fphi": [[0.0, g], [0.0, g * Nc]],
+        "fluid_bc": ["noslip"] * 4,
+        "scalar_bc": [["dirichlet", "dirichlet"], ["dirichlet", "dirichlet"],
+                      ["noflux", "noflux"], ["noflux", "noflux"]],
+        "wall": [[1.0, 1.0], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0]],
+        "dx": dx, "dt": dt, "Ra": Ra, "Pr": Pr, "Le": Le, "Nc": Nc, "Sr": Sr, "Df": Df,
+        "A": A, "u_lat": u_lat,
+        "name": f"ddc_{nx}x{ny}_Ra{Ra:g}",
+    })
+    phi0 = np.zeros((2, ny, nx))
+    u0 = np.zeros((2, ny, nx))
+    return wl, phi0, u0, np.zeros((ny, nx))
+
+
+def ddc_cavity(L=256):
+    """Double-diffusive cavity with Soret/Dufour: Ra 1e5, Pr 0.71, Le 2, N 1, Sr = Df = 0.1."""
+    return ddc(L, Ra=1e5, Pr=0.71, Le=2.0, Nc=1.0, Sr=0.1, Df=0.1)
+
+
+def sweep_params(count=256, seed=4, sizes=None):
+    """Parameter law of the batched sweep: L uniform over {64, 96, ..., 256},
+    Ra log-uniform in [1e3, 1e6], Le U[1, 5], Nc U[-2, 2], Sr, Df U[0, 0.5], Pr 0.71."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    choices = np.arange(64, 257, 32) if sizes is None else np.asarray(sizes)
+    out = []
+    for _ in range(count):
+        out.append({
+            "L": int(rng.choice(choices)),
+            "Ra": float(10.0 ** rng.uniform(3.0, 6.0)),
+            "Le": float(rng.uniform(1.0, 5.0)),
+            "Nc": float(rng.uniform(-2.0, 2.0)),
+            "Sr": float(rng.uniform(0.0, 0.5)),
+            "Df": float(rng.uniform(0.0, 0.5)),
+            "Pr": 0.71,
+        })
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Generic seeded cases for parity tests (exercise every boundary kind)
+# ---------------------------------------------------------------------------
+def random_case(nx, ny, m=2, seed=0, fluid_bc=None, scalar_bc=None, model="linear",
+                collision="bgk", force=True, source=False, amp=0.05):
+    """A small random case: smooth-ish random fields, random SPD-dominant D."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    D = np.diag(rng.uniform(0.02, 0.2, size=m))
+    D += 0.2 * np.min(np.diag(D)) * rng.uniform(-1, 1, size=(m, m)) * (1 - np.eye(m))
+    wl = _base(nx, ny, m, float(rng.uniform(0.6, 1.2)), D, collision=collision)
+    if fluid_bc is not None:
+        wl["fluid_bc"] = list(fluid_bc)
+    if scalar_bc is not None:
+        wl["scalar_bc"] = [list(r) for r in scalar_bc]
+    wl["wall"] = rng.uniform(0.5, 1.5, size=(4, m)).tolist()
+    if force:
+        wl["F0"] = rng.uniform(-1e-5, 1e-5, size=2).tolist()
+        wl["Fphi"] = rng.uniform(-1e-5, 1e-5, size=(m, 2)).tolist()
+    if source:
+        wl["K"] = (-rng.uniform(0.0, 2e-3, size=(m, m))).tolist()
+    if model == "chemotaxis":
+        wl.update({"model": "chemotaxis", "chi": float(rng.uniform(0.005, 0.02)),
+                   "beta": float(rng.uniform(1e-4, 1e-3)), "cstar": 0.95})
+        wl["D"] = [[float(D[0, 0]), 0.0], [0.0, float(D[1, 1])]]
+    phi0 = 1.0 + amp * rng.standard_normal(size=(m, ny, nx))
+    u0 = 0.02 * rng.standard_normal(size=(2, ny, nx))
+    p0 = 1e-3 * rng.standard_normal(size=(ny, nx))
+    wl["name"] = f"random_{nx}x{ny}_s{seed}"
+    return wl, phi0, u0, p0
