@@ -1,0 +1,181 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) library for the lattice Boltzmann model
+ * of the coupled cross-diffusion-fluid system (Zhan, Chai & Shi, arXiv
+ * 2101.03055).
+ *
+ * Problem (Sec. 1, Eq. CDF): m scalars phi_a (a = 1..m, m <= 4) transported by
+ * an incompressible flow u,
+ *     d_t phi_a + div(phi_a u) = div(D_ab grad phi_b) + S_a,
+ *     div u = 0,   d_t u + div(uu) = -grad p + div(nu grad u) + F,
+ * solved with one D2Q5 lattice per scalar and one D2Q9 fluid lattice
+ * (Sec. 2, Eqs. evolution12 and evolution3).  The scalar collision is the
+ * matrix relaxation omega_ab = (D/(cs^2 dt) + I/2)^-1 (Eq. omega-D with
+ * lambda = I), whose off-diagonal entries carry the cross-diffusion; the
+ * auxiliary source G of Eq. Gi cancels the numerical diffusion of convection;
+ * the source carries its time-derivative correction (Eq. source, gamma = 0);
+ * the fluid is BGK (Eq. evolution3) with the force term of Eq. force
+ * (varphi = 0) and the pressure scheme of appendix A, or MRT.
+ *
+ * Units: lattice units, dx = dt = 1, cs^2 = 1/3.
+ * Grid: nx * ny nodes, node (x, y) at the cell centre; walls are half-way
+ * between the last node and the next (Sec. 3: half-way bounce-back).
+ * Sides: 0 = x-, 1 = x+, 2 = y-, 3 = y+.
+ *
+ * Host arrays are row-major, x fastest:
+ *   phi[a][y][x] (m planes), u[d][y][x] (2 planes), p[y][x],
+ *   f[a][i][y][x] (m*5 planes, D2Q5 order 0,(1,0),(0,1),(-1,0),(0,-1)),
+ *   h[i][y][x]    (9 planes, D2Q9 order 0,(1,0),(0,1),(-1,0),(0,-1),
+ *                  (1,1),(-1,1),(-1,-1),(1,-1)).
+ *
+ * Ownership: the caller owns the device workspace (any device allocation of
+ * at least lb_workspace_bytes() bytes, 256-byte aligned) and every host
+ * array.  The handle holds no other device memory; lb_free() releases the
+ * handle only, never the workspace.  All work is enqueued on the stream given
+ * to lb_init (a hipStream_t, NULL for the default stream).
+ *
+ * Errors: every call returns an lb_status; nothing throws or aborts across
+ * the ABI.  lb_last_error() returns a thread-local description of the last
+ * failure on the calling thread.
+ */
+#ifndef LBCDF_LB_H
+#define LBCDF_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_MAX_M 4
+
+typedef enum lb_status {
+    LB_OK = 0,
+    LB_EINVAL = -1,      /* invalid argument or parameter set */
+    LB_ENOMEM = -2,      /* workspace too small or host allocation failed */
+    LB_EDEVICE = -3,     /* a HIP call failed */
+    LB_ENONFINITE = -4,  /* a non-finite value was found (inputs or fields) */
+    LB_ESTATE = -5       /* call not valid in the handle's current state */
+} lb_status;
+
+/* closures */
+enum { LB_MODEL_LINEAR = 0,      /* D constant, S = K phi, F = F0 + sum_a Fphi[a] phi_a  (DDC, Sec. 3.2) */
+       LB_MODEL_CHEMOTAXIS = 1 };/* m = 2, (n, c): D = [[D00, D01 - chi r(c) n], [D10, D11]],
+                                    S = (0, -beta r(c) n), F = F0 + sum_a Fphi[a] phi_a  (Sec. 3.1) */
+/* population storage in device memory */
+enum { LB_STORE_F64 = 0,         /* raw populations, FP64 arithmetic */
+       LB_STORE_F32 = 1,         /* deviations f - W_i phi_ref, h - rho0 delta_i0 in FP32, FP32 arithmetic */
+       LB_STORE_F16 = 2 };       /* the same deviations times fp16_scale in binary16, FP32 arithmetic */
+/* fluid collision */
+enum { LB_COLL_BGK = 0, LB_COLL_MRT = 1 };
+/* chemotaxis cut-off r(c) */
+enum { LB_R_STEP = 0,            /* r = 1 if c >= cstar else 0 (Sec. 3.1.3) */
+       LB_R_SMOOTH = 1 };        /* r = (1 + (c - cstar)/sqrt((c - cstar)^2 + eps^2))/2 (Sec. 3.1.2) */
+/* fluid boundary per side */
+enum { LB_BC_PERIODIC = 0, LB_BC_NOSLIP = 1 /* half-way bounce-back */, LB_BC_FREESLIP = 2 /* specular */ };
+/* scalar boundary per side and species */
+enum { LB_SBC_PERIODIC = 0, LB_SBC_NOFLUX = 1 /* half-way bounce-back */,
+       LB_SBC_DIRICHLET = 2 /* anti-bounce-back, value wall[side][a] */ };
+
+typedef struct lb_params {
+    int32_t nx, ny;              /* grid, each >= 2 */
+    int32_t m;                   /* number of scalars, 1..4 (2 for the chemotaxis model) */
+    int32_t model;               /* LB_MODEL_* */
+    int32_t storage;             /* LB_STORE_* */
+    int32_t collision;           /* LB_COLL_* */
+    int32_t r_kind;              /* LB_R_* */
+    int32_t fluid_bc[4];         /* LB_BC_* per side; periodic only in pairs (0,1) / (2,3) */
+    int32_t scalar_bc[4][LB_MAX_M]; /* LB_SBC_* per side and species; periodic must match the fluid */
+    int32_t reserved;            /* must be 0 */
+    double tau_f;                /* fluid relaxation time (> 1/2); nu = (tau_f - 1/2)/3 */
+    double rho0;                 /* constant of the fluid equilibrium (Eq. heq) */
+    double mrt_s[9];             /* MRT rates, moment order rho,e,eps,jx,qx,jy,qy,pxx,pxy;
+                                    the stress rates (7, 8) are replaced by 1/tau_f */
+    double D[LB_MAX_M * LB_MAX_M]; /* diffusion matrix, row-major m x m (constant part) */
+    double K[LB_MAX_M * LB_MAX_M]; /* linear source matrix (LINEAR model), row-major m x m */
+    double F0[2];                /* constant body force */
+    double Fphi[LB_MAX_M][2];    /* buoyancy coefficients: F += Fphi[a] * phi_a */
+    double chi, beta, cstar, eps;/* chemotaxis closure coefficients (lattice units) */
+    double wall[4][LB_MAX_M];    /* Dirichlet wall values [side][species] */
+    double phi_ref[LB_MAX_M];    /* reference level subtracted in reduced-precision storage */
+    double fp16_scale;           /* multiplier of the deviations in LB_STORE_F16 (> 0) */
+} lb_params;
+
+typedef struct lb_handle lb_handle;
+
+/* Bytes of device workspace lb_init needs for these parameters.
+ * Layout (documented for debugging only; opaque to callers): populations as
+ * 9 + 5m planes [plane][ny][nx] of the storage type, the previous-step source
+ * planes, the residual snapshot, a staging area and the reduction scratch. */
+lb_status lb_workspace_bytes(const lb_params* params, size_t* bytes);
+
+/* Validates the parameters (tau_f > 1/2, Re(eig D) > 0 so that eig(omega) lies in
+ * (0, 2), m range, boundary codes, finite inputs), then initialises
+ * f = f^eq(phi0, u0), h = h^eq(p0, u0) and S_old = S(phi0) at t = 0 (reading of
+ * the paper: it does not state the initial populations).  phi0: host [m][ny][nx];
+ * u0: host [2][ny][nx]; p0: host [ny][nx] or NULL (p0 = 0).  Synchronises the
+ * stream before returning.  *out receives a new handle. */
+lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace_bytes,
+                  void* hip_stream, const double* phi0, const double* u0, const double* p0,
+                  lb_handle** out);
+
+/* Advances n >= 0 time steps (Eqs. evolution12 and evolution3 with the boundary
+ * rules of Sec. 3), asynchronously on the handle's stream.  Any n, odd or even. */
+lb_status lb_step(lb_handle* h, int64_t n);
+
+/* Macroscopic fields at the current time (Eq. sum): phi [m][ny][nx], u [2][ny][nx]
+ * (u = sum_i c_i h_i + F/2), p [ny][nx] (appendix A, varphi = 0).  Host arrays;
+ * any may be NULL.  Synchronises the stream. */
+lb_status lb_moments(lb_handle* h, double* phi, double* u, double* p);
+
+/* Same fields written to caller-owned DEVICE buffers (FP64, same layouts),
+ * asynchronously on the handle's stream; any may be NULL. */
+lb_status lb_moments_device(lb_handle* h, double* d_phi, double* d_u, double* d_p);
+
+/* Steady-state residual since the previous call (reading of the criterion of
+ * Sec. 3.1.1 with absolute values): res[q] = sum|q - q_prev| / sum|q| for
+ * q = u_x, u_y, phi_1..phi_m (m + 2 values); res[q] = 0 when both sums vanish.
+ * The first call after lb_init/lb_load stores the snapshot and returns +inf.
+ * Returns LB_ENONFINITE (with res filled) if any field is not finite.
+ * Synchronises the stream. */
+lb_status lb_residual(lb_handle* h, double* res);
+
+/* Totals: mass[a] = sum_x phi_a (a < m), mass[m] = sum_x sum_i h_i (= N rho0 for the
+ * incompressible equilibrium).  FP64, deterministic.  Synchronises the stream. */
+lb_status lb_mass(lb_handle* h, double* mass);
+
+/* Populations at the current time, pre-collision, in canonical order and raw
+ * (un-shifted) FP64: f [m][5][ny][nx], hpop [9][ny][nx]; either may be NULL.
+ * Synchronises the stream. */
+lb_status lb_populations(lb_handle* h, double* f, double* hpop);
+
+/* Time step counter (number of steps taken since lb_init). */
+lb_status lb_time(lb_handle* h, int64_t* t);
+
+/* Checkpoint: size of the blob, save into / restore from a host buffer.
+ * lb_load requires a handle created with identical parameters.  A run of n
+ * steps equals k steps + save + load + (n - k) steps bit for bit. */
+lb_status lb_state_bytes(lb_handle* h, size_t* bytes);
+lb_status lb_save(lb_handle* h, void* host_buf, size_t bytes);
+lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes);
+
+/* Launch shape of the step kernel: tile_x * tile_y threads per workgroup,
+ * tile_x a multiple of 64 (one wavefront per row segment), product <= 1024.
+ * (0, 0) restores the default.  Used by the autotuner. */
+lb_status lb_set_tile(lb_handle* h, int32_t tile_x, int32_t tile_y);
+
+/* Releases the handle (never the workspace).  NULL is accepted. */
+lb_status lb_free(lb_handle* h);
+
+/* Thread-local text of the last error, "" if none. */
+const char* lb_last_error(void);
+
+/* sizeof(lb_params) as compiled into the library (lets bindings check their
+ * mirror of the record). */
+size_t lb_params_bytes(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBCDF_LB_H */

@@ -1,0 +1,528 @@
+// lb_api.hip -- host runtime behind the C ABI of include/lb.h.
+//
+// Owns the handle (parameters, kernel parameter blocks, workspace layout,
+// time counter and AA parity), validates inputs, stages host data through
+// the caller's workspace and enqueues the kernels of lb_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lb_internal.h"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+lb_status fail(lb_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(LB_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                                 \
+    } while (0)
+
+constexpr uint64_t kMagic = 0x4c42434446303031ull;  // "LBCDF001"
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int storage) {
+    return storage == LB_STORE_F64 ? 8 : (storage == LB_STORE_F32 ? 4 : 2);
+}
+size_t arith_bytes(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
+
+int source_mask(const lb_params& p) {
+    if (p.model == LB_MODEL_CHEMOTAXIS) return 2;
+    int mask = 0;
+    for (int a = 0; a < p.m; ++a)
+        for (int b = 0; b < p.m; ++b)
+            if (p.K[a * p.m + b] != 0.0) mask |= 1 << a;
+    return mask;
+}
+
+Layout make_layout(const lb_params& p) {
+    Layout L{};
+    L.N = (size_t)p.nx * (size_t)p.ny;
+    L.elem = elem_bytes(p.storage);
+    // planes padded to 4 KiB plus a 1 KiB stagger so that the 19+ concurrent
+    // plane streams do not start in the same memory channel
+    const size_t pb = round_up(L.N * L.elem, 4096) + 1024;
+    L.plane = pb / L.elem;
+    L.npop = 9 + 5 * (size_t)p.m;
+    L.nsrc = (size_t)__builtin_popcount(source_mask(p));
+    size_t off = 0;
+    L.pop_off = off;
+    off += L.npop * pb;
+    off = round_up(off, 256);
+    L.sold_off = off;
+    off += round_up(L.nsrc * L.N * arith_bytes(p.storage), 256);
+    L.snap_off = off;
+    off += round_up((size_t)(p.m + 2) * L.N * 8, 256);
+    L.stage_off = off;
+    off += round_up((size_t)(p.m + 3) * L.N * 8, 256);
+    L.part_off = off;
+    off += round_up((size_t)kRedBlocks * kRedWidth * 8, 256);
+    L.res_off = off;
+    off += 256 * 8;
+    L.total = off;
+    return L;
+}
+
+bool finite_all(const double* v, size_t n) {
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(v[k])) return false;
+    return true;
+}
+
+// eigenvalues of a small real matrix (m <= 4): characteristic polynomial by
+// Faddeev-LeVerrier, roots by Durand-Kerner iteration
+void eigenvalues(int m, const double* A, std::complex<double>* lam) {
+    double c[LB_MAX_M + 1];  // monic: x^m + c[1] x^{m-1} + ... + c[m]
+    double Mk[LB_MAX_M * LB_MAX_M], AM[LB_MAX_M * LB_MAX_M];
+    c[0] = 1.0;
+    std::memset(Mk, 0, sizeof Mk);
+    for (int k = 1; k <= m; ++k) {
+        // M_k = A M_{k-1} + c_{k-1} I ; c_k = -tr(A M_k)/k
+        double Mn[LB_MAX_M * LB_MAX_M];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                double s = (i == j) ? c[k - 1] : 0.0;
+                for (int l = 0; l < m; ++l) s += A[i * m + l] * Mk[l * m + j];
+                Mn[i * m + j] = s;
+            }
+        std::memcpy(Mk, Mn, sizeof Mn);
+        double tr = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int l = 0; l < m; ++l) tr += A[i * m + l] * Mk[l * m + i];
+        (void)AM;
+        c[k] = -tr / k;
+    }
+    std::complex<double> z[LB_MAX_M];
+    const std::complex<double> seed(0.4, 0.9);
+    double scale = 0.0;
+    for (int k = 0; k < m * m; ++k) scale = std::max(scale, std::fabs(A[k]));
+    scale = std::max(scale, 1e-300);
+    for (int k = 0; k < m; ++k) z[k] = scale * std::pow(seed, k);
+    for (int it = 0; it < 500; ++it) {
+        for (int k = 0; k < m; ++k) {
+            std::complex<double> num = 1.0;
+            for (int j = 1; j <= m; ++j) num = num * z[k] + c[j];
+            std::complex<double> den = 1.0;
+            for (int j = 0; j < m; ++j)
+                if (j != k) den *= (z[k] - z[j]);
+            if (std::abs(den) > 0) z[k] -= num / den;
+        }
+    }
+    for (int k = 0; k < m; ++k) lam[k] = z[k];
+}
+
+// inverse of a small row-major matrix by Gauss-Jordan with partial pivoting
+bool invert(int m, const double* A, double* out) {
+    double w[LB_MAX_M][2 * LB_MAX_M];
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < 2 * m; ++j) w[i][j] = j < m ? A[i * m + j] : (j - m == i ? 1.0 : 0.0);
+    for (int k = 0; k < m; ++k) {
+        int pv = k;
+        for (int i = k + 1; i < m; ++i)
+            if (std::fabs(w[i][k]) > std::fabs(w[pv][k])) pv = i;
+        if (w[pv][k] == 0.0) return false;
+        for (int j = 0; j < 2 * m; ++j) std::swap(w[k][j], w[pv][j]);
+        const double d = w[k][k];
+        for (int j = 0; j < 2 * m; ++j) w[k][j] /= d;
+        for (int i = 0; i < m; ++i)
+            if (i != k) {
+                const double s = w[i][k];
+                for (int j = 0; j < 2 * m; ++j) w[i][j] -= s * w[k][j];
+            }
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) out[i * m + j] = w[i][m + j];
+    return true;
+}
+
+lb_status validate(const lb_params* p) {
+    if (!p) return fail(LB_EINVAL, "params is NULL");
+    if (p->nx < 2 || p->ny < 2) return fail(LB_EINVAL, "grid %d x %d: each side must be >= 2", p->nx, p->ny);
+    if ((long long)p->nx * p->ny > (1ll << 31) - 1) return fail(LB_EINVAL, "grid too large");
+    if (p->m < 1 || p->m > LB_MAX_M) return fail(LB_EINVAL, "m = %d outside 1..%d", p->m, LB_MAX_M);
+    if (p->model != LB_MODEL_LINEAR && p->model != LB_MODEL_CHEMOTAXIS) return fail(LB_EINVAL, "unknown model");
+    if (p->model == LB_MODEL_CHEMOTAXIS && p->m != 2) return fail(LB_EINVAL, "chemotaxis model needs m = 2");
+    if (p->storage < LB_STORE_F64 || p->storage > LB_STORE_F16) return fail(LB_EINVAL, "unknown storage");
+    if (p->collision != LB_COLL_BGK && p->collision != LB_COLL_MRT) return fail(LB_EINVAL, "unknown collision");
+    if (p->r_kind != LB_R_STEP && p->r_kind != LB_R_SMOOTH) return fail(LB_EINVAL, "unknown r_kind");
+    if (p->reserved != 0) return fail(LB_EINVAL, "reserved field must be 0");
+    if (!(p->tau_f > 0.5) || !std::isfinite(p->tau_f)) return fail(LB_EINVAL, "tau_f = %g must be > 1/2", p->tau_f);
+    if (!std::isfinite(p->rho0)) return fail(LB_EINVAL, "rho0 not finite");
+    for (int s = 0; s < 4; ++s) {
+        if (p->fluid_bc[s] < 0 || p->fluid_bc[s] > 2) return fail(LB_EINVAL, "fluid_bc[%d] invalid", s);
+        for (int a = 0; a < p->m; ++a) {
+            if (p->scalar_bc[s][a] < 0 || p->scalar_bc[s][a] > 2) return fail(LB_EINVAL, "scalar_bc[%d][%d] invalid", s, a);
+            if (!std::isfinite(p->wall[s][a])) return fail(LB_EINVAL, "wall[%d][%d] not finite", s, a);
+        }
+    }
+    for (int axis = 0; axis < 2; ++axis) {
+        const int s0 = 2 * axis, s1 = s0 + 1;
+        const bool per = p->fluid_bc[s0] == LB_BC_PERIODIC;
+        if ((p->fluid_bc[s1] == LB_BC_PERIODIC) != per)
+            return fail(LB_EINVAL, "periodic fluid sides must come in pairs (axis %d)", axis);
+        for (int a = 0; a < p->m; ++a)
+            if ((p->scalar_bc[s0][a] == LB_SBC_PERIODIC) != per || (p->scalar_bc[s1][a] == LB_SBC_PERIODIC) != per)
+                return fail(LB_EINVAL, "scalar %d periodicity on axis %d must match the fluid", a, axis);
+    }
+    if (p->collision == LB_COLL_MRT)
+        for (int k = 0; k < 9; ++k)
+            if (!(p->mrt_s[k] > 0.0 && p->mrt_s[k] < 2.0) && k != 7 && k != 8)
+                return fail(LB_EINVAL, "mrt_s[%d] = %g outside (0, 2)", k, p->mrt_s[k]);
+    const int m = p->m;
+    for (int k = 0; k < m * m; ++k)
+        if (!std::isfinite(p->D[k]) || !std::isfinite(p->K[k])) return fail(LB_EINVAL, "D or K not finite");
+    if (p->model == LB_MODEL_LINEAR) {
+        std::complex<double> lam[LB_MAX_M];
+        eigenvalues(m, p->D, lam);
+        for (int k = 0; k < m; ++k)
+            if (!(lam[k].real() > 0.0))
+                return fail(LB_EINVAL, "D has an eigenvalue with real part %g <= 0: eig(omega) leaves (0, 2)",
+                            lam[k].real());
+    } else {
+        if (!(p->D[0] > 0.0 && p->D[3] > 0.0)) return fail(LB_EINVAL, "chemotaxis: D00, D11 must be > 0");
+        if (p->D[2] != 0.0) return fail(LB_EINVAL, "chemotaxis: D10 must be 0 (upper-triangular D)");
+        if (!(p->chi >= 0.0) || !(p->beta >= 0.0)) return fail(LB_EINVAL, "chemotaxis: chi, beta must be >= 0");
+        if (p->r_kind == LB_R_SMOOTH && !(p->eps > 0.0)) return fail(LB_EINVAL, "smooth r(c) needs eps > 0");
+    }
+    if (p->storage == LB_STORE_F16 && !(p->fp16_scale > 0.0 && std::isfinite(p->fp16_scale)))
+        return fail(LB_EINVAL, "fp16_scale must be > 0");
+    return LB_OK;
+}
+
+template <class T>
+void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
+    std::memset(&k, 0, sizeof k);
+    const bool shifted = p.storage != LB_STORE_F64;
+    k.nx = p.nx;
+    k.ny = p.ny;
+    k.plane = (long long)L.plane;
+    k.px = p.fluid_bc[0] == LB_BC_PERIODIC;
+    k.py = p.fluid_bc[2] == LB_BC_PERIODIC;
+    for (int s = 0; s < 4; ++s) {
+        k.fbc[s] = p.fluid_bc[s];
+        for (int a = 0; a < LB_MAX_M; ++a) {
+            k.sbc[s][a] = a < p.m ? p.scalar_bc[s][a] : 0;
+            const double ref = shifted && a < p.m ? p.phi_ref[a] : 0.0;
+            k.wallr[s][a] = T(a < p.m ? p.wall[s][a] - ref : 0.0);
+        }
+    }
+    k.r_kind = p.r_kind;
+    k.src_mask = source_mask(p);
+    k.omega_f = T(1.0 / p.tau_f);
+    k.rho0_eff = T(shifted ? 0.0 : p.rho0);
+    k.h0_shift = T(shifted ? p.rho0 : 0.0);
+    const int m = p.m;
+    if (p.model == LB_MODEL_LINEAR) {
+        double A[LB_MAX_M * LB_MAX_M], om[LB_MAX_M * LB_MAX_M];
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) A[a * m + b] = 3.0 * p.D[a * m + b] + (a == b ? 0.5 : 0.0);
+        invert(m, A, om);
+        for (int q = 0; q < m * m; ++q) k.omega[q] = T(om[q]);
+    } else {
+        for (int q = 0; q < 4; ++q) k.Dc[q] = T(p.D[q]);
+    }
+    for (int q = 0; q < m * m; ++q) k.K[q] = T(p.K[q]);
+    k.F0[0] = T(p.F0[0]);
+    k.F0[1] = T(p.F0[1]);
+    for (int a = 0; a < m; ++a) {
+        k.Fphi[a][0] = T(p.Fphi[a][0]);
+        k.Fphi[a][1] = T(p.Fphi[a][1]);
+        k.phi_ref[a] = T(shifted ? p.phi_ref[a] : 0.0);
+    }
+    k.chi = T(p.chi);
+    k.beta = T(p.beta);
+    k.cstar = T(p.cstar);
+    k.eps = T(p.eps);
+    for (int q = 0; q < 9; ++q) k.mrt_s[q] = T(p.mrt_s[q]);
+    k.scale = T(p.storage == LB_STORE_F16 ? p.fp16_scale : 1.0);
+    k.inv_scale = T(p.storage == LB_STORE_F16 ? 1.0 / p.fp16_scale : 1.0);
+}
+
+}  // namespace
+
+struct lb_handle {
+    lb_params p;
+    Layout L;
+    KParams<double> kd;
+    KParams<float> kf;
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    int64_t t;           // steps taken; AA parity = t & 1
+    int has_snapshot;
+    Launch lc;
+};
+
+namespace {
+Launch default_launch(const lb_params& p) {
+    (void)p;
+    return Launch{64, 4};
+}
+
+void* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+struct StateHeader {
+    uint64_t magic;
+    int64_t t;
+    int64_t has_snapshot;
+    uint64_t param_hash;
+    uint64_t pop_bytes, sold_bytes, snap_bytes;
+};
+
+uint64_t fnv(const void* data, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(data);
+    uint64_t h = 1469598103934665603ull;
+    for (size_t k = 0; k < n; ++k) {
+        h ^= b[k];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+size_t sold_bytes(const lb_handle* h) { return h->L.nsrc * h->L.N * arith_bytes(h->p.storage); }
+size_t snap_bytes(const lb_handle* h) { return (size_t)(h->p.m + 2) * h->L.N * 8; }
+size_t pop_bytes(const lb_handle* h) { return h->L.npop * h->L.plane * h->L.elem; }
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+size_t lb_params_bytes(void) { return sizeof(lb_params); }
+
+lb_status lb_workspace_bytes(const lb_params* params, size_t* bytes) {
+    lb_status st = validate(params);
+    if (st != LB_OK) return st;
+    if (!bytes) return fail(LB_EINVAL, "bytes is NULL");
+    *bytes = make_layout(*params).total;
+    return LB_OK;
+}
+
+lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                  const double* phi0, const double* u0, const double* p0, lb_handle** out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    lb_status st = validate(params);
+    if (st != LB_OK) return st;
+    const Layout L = make_layout(*params);
+    if (!dev_workspace) return fail(LB_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return fail(LB_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(LB_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+    if (!phi0 || !u0) return fail(LB_EINVAL, "phi0 and u0 are required");
+    const size_t N = L.N, m = (size_t)params->m;
+    if (!finite_all(phi0, m * N) || !finite_all(u0, 2 * N) || (p0 && !finite_all(p0, N)))
+        return fail(LB_ENONFINITE, "initial fields contain non-finite values");
+
+    lb_handle* h = new (std::nothrow) lb_handle();
+    if (!h) return fail(LB_ENOMEM, "host allocation failed");
+    h->p = *params;
+    h->L = L;
+    fill_kparams(h->p, L, h->kd);
+    fill_kparams(h->p, L, h->kf);
+    h->ws = dev_workspace;
+    h->ws_bytes = workspace_bytes;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->t = 0;
+    h->has_snapshot = 0;
+    h->lc = default_launch(h->p);
+
+    double* stage = (double*)at(h->ws, L.stage_off);
+    hipError_t e = hipMemcpyAsync(stage, phi0, m * N * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(stage + m * N, u0, 2 * N * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && p0) e = hipMemcpyAsync(stage + (m + 2) * N, p0, N * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = launch_init(h->p, L, h->ws, h->kd, h->kf, p0 ? 1 : 0, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(LB_EDEVICE, "lb_init: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_handle* h, int64_t n) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LB_EINVAL, "n = %lld < 0", (long long)n);
+    for (int64_t s = 0; s < n; ++s) {
+        const bool odd = (h->t & 1) != 0;
+        hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, odd, h->lc, h->stream);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+        h->t += 1;
+    }
+    return LB_OK;
+}
+
+lb_status lb_moments_device(lb_handle* h, double* d_phi, double* d_u, double* d_p) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    hipError_t e = launch_moments(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, d_phi, d_u, d_p, h->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_moments_device: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+lb_status lb_moments(lb_handle* h, double* phi, double* u, double* p) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    const size_t N = h->L.N, m = (size_t)h->p.m;
+    double* stage = (double*)at(h->ws, h->L.stage_off);
+    double* dphi = stage;
+    double* du = stage + m * N;
+    double* dp = stage + (m + 2) * N;
+    lb_status st = lb_moments_device(h, phi ? dphi : nullptr, u ? du : nullptr, p ? dp : nullptr);
+    if (st != LB_OK) return st;
+    if (phi) HIPCHK(hipMemcpyAsync(phi, dphi, m * N * 8, hipMemcpyDeviceToHost, h->stream));
+    if (u) HIPCHK(hipMemcpyAsync(u, du, 2 * N * 8, hipMemcpyDeviceToHost, h->stream));
+    if (p) HIPCHK(hipMemcpyAsync(p, dp, N * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+lb_status lb_residual(lb_handle* h, double* res) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!res) return fail(LB_EINVAL, "res is NULL");
+    const int Q = h->p.m + 2;
+    const int mode = h->has_snapshot ? 0 : 1;
+    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, mode, h->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_residual: %s", hipGetErrorString(e));
+    double out[64];
+    HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (3 * Q + 1), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int q = 0; q < Q; ++q) res[q] = mode == 0 ? out[2 * Q + 1 + q] : HUGE_VAL;
+    h->has_snapshot = 1;
+    if (out[2 * Q] != 0.0) return fail(LB_ENONFINITE, "non-finite values at %.0f nodes", out[2 * Q]);
+    return LB_OK;
+}
+
+lb_status lb_mass(lb_handle* h, double* mass) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!mass) return fail(LB_EINVAL, "mass is NULL");
+    const int Q = h->p.m + 2;
+    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, 2, h->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_mass: %s", hipGetErrorString(e));
+    double out[64];
+    HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (2 * Q + 1), hipMemcpyDeviceToHost,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int a = 0; a <= h->p.m; ++a) mass[a] = out[a];
+    if (out[2 * Q] != 0.0) return fail(LB_ENONFINITE, "non-finite values at %.0f nodes", out[2 * Q]);
+    return LB_OK;
+}
+
+lb_status lb_populations(lb_handle* h, double* f, double* hpop) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    const size_t N = h->L.N, m = (size_t)h->p.m;
+    const int chunk = h->p.m + 3;  // planes the staging area holds
+    const int total = 9 + 5 * h->p.m;
+    double* stage = (double*)at(h->ws, h->L.stage_off);
+    for (int b = 0; b < total; b += chunk) {
+        const int cnt = std::min(chunk, total - b);
+        const bool want_h = hpop && b < 9, want_f = f && b + cnt > 9;
+        if (!want_h && !want_f) continue;
+        hipError_t e = launch_export(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, b, cnt, stage, h->stream);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "lb_populations: %s", hipGetErrorString(e));
+        for (int k = b; k < b + cnt; ++k) {
+            double* dst = k < 9 ? (hpop ? hpop + (size_t)k * N : nullptr) : (f ? f + (size_t)(k - 9) * N : nullptr);
+            if (dst) HIPCHK(hipMemcpyAsync(dst, stage + (size_t)(k - b) * N, N * 8, hipMemcpyDeviceToHost, h->stream));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    (void)m;
+    return LB_OK;
+}
+
+lb_status lb_time(lb_handle* h, int64_t* t) {
+    if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+    *t = h->t;
+    return LB_OK;
+}
+
+lb_status lb_state_bytes(lb_handle* h, size_t* bytes) {
+    if (!h || !bytes) return fail(LB_EINVAL, "NULL argument");
+    *bytes = sizeof(StateHeader) + pop_bytes(h) + sold_bytes(h) + snap_bytes(h);
+    return LB_OK;
+}
+
+lb_status lb_save(lb_handle* h, void* host_buf, size_t bytes) {
+    size_t need = 0;
+    lb_status st = lb_state_bytes(h, &need);
+    if (st != LB_OK) return st;
+    if (!host_buf || bytes < need) return fail(LB_EINVAL, "buffer of %zu bytes, %zu needed", bytes, need);
+    StateHeader hd{kMagic, h->t, h->has_snapshot, fnv(&h->p, sizeof h->p), pop_bytes(h), sold_bytes(h), snap_bytes(h)};
+    char* b = static_cast<char*>(host_buf);
+    std::memcpy(b, &hd, sizeof hd);
+    b += sizeof hd;
+    HIPCHK(hipMemcpyAsync(b, at(h->ws, h->L.pop_off), hd.pop_bytes, hipMemcpyDeviceToHost, h->stream));
+    b += hd.pop_bytes;
+    if (hd.sold_bytes) HIPCHK(hipMemcpyAsync(b, at(h->ws, h->L.sold_off), hd.sold_bytes, hipMemcpyDeviceToHost, h->stream));
+    b += hd.sold_bytes;
+    HIPCHK(hipMemcpyAsync(b, at(h->ws, h->L.snap_off), hd.snap_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes) {
+    size_t need = 0;
+    lb_status st = lb_state_bytes(h, &need);
+    if (st != LB_OK) return st;
+    if (!host_buf || bytes < need) return fail(LB_EINVAL, "buffer of %zu bytes, %zu needed", bytes, need);
+    StateHeader hd;
+    const char* b = static_cast<const char*>(host_buf);
+    std::memcpy(&hd, b, sizeof hd);
+    if (hd.magic != kMagic) return fail(LB_EINVAL, "not a state blob");
+    if (hd.param_hash != fnv(&h->p, sizeof h->p) || hd.pop_bytes != pop_bytes(h) || hd.sold_bytes != sold_bytes(h) ||
+        hd.snap_bytes != snap_bytes(h))
+        return fail(LB_EINVAL, "state blob was saved with different parameters");
+    b += sizeof hd;
+    HIPCHK(hipMemcpyAsync(at(h->ws, h->L.pop_off), b, hd.pop_bytes, hipMemcpyHostToDevice, h->stream));
+    b += hd.pop_bytes;
+    if (hd.sold_bytes) HIPCHK(hipMemcpyAsync(at(h->ws, h->L.sold_off), b, hd.sold_bytes, hipMemcpyHostToDevice, h->stream));
+    b += hd.sold_bytes;
+    HIPCHK(hipMemcpyAsync(at(h->ws, h->L.snap_off), b, hd.snap_bytes, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->t = hd.t;
+    h->has_snapshot = (int)hd.has_snapshot;
+    return LB_OK;
+}
+
+lb_status lb_set_tile(lb_handle* h, int32_t tile_x, int32_t tile_y) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (tile_x == 0 && tile_y == 0) {
+        h->lc = default_launch(h->p);
+        return LB_OK;
+    }
+    if (tile_x < 64 || tile_x % 64 || tile_y < 1 || tile_x * tile_y > 256)
+        return fail(LB_EINVAL, "tile %d x %d: tile_x must be a multiple of 64, tile_x * tile_y <= 256", tile_x, tile_y);
+    h->lc = Launch{tile_x, tile_y};
+    return LB_OK;
+}
+
+lb_status lb_free(lb_handle* h) {
+    delete h;
+    return LB_OK;
+}
+
+}  // extern "C"

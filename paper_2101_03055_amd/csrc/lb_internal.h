@@ -1,0 +1,70 @@
+// lb_internal.h -- shared declarations between the C ABI (lb_api.hip) and the
+// gfx950 kernels (lb_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lb.h"
+
+namespace lbk {
+
+// Kernel-side parameter block, in the arithmetic type T of the storage mode
+// (double for LB_STORE_F64, float otherwise).  Passed by value.
+template <class T>
+struct KParams {
+    int nx, ny;
+    long long plane;      // elements per population plane
+    int px, py;           // periodic in x / y
+    int fbc[4];           // fluid boundary code per side
+    int sbc[4][LB_MAX_M]; // scalar boundary code per side and species
+    int r_kind;
+    int src_mask;         // species carrying a source (need S_old)
+    T wallr[4][LB_MAX_M]; // Dirichlet value minus phi_ref
+    T omega_f;            // 1 / tau_f
+    T rho0_eff;           // constant in sigma_0 as seen by the stored h_0
+    T h0_shift;           // stored h_0 = h_0 - h0_shift
+    T omega[LB_MAX_M * LB_MAX_M]; // constant relaxation matrix (linear model)
+    T Dc[4];              // chemotaxis: constant part of D (2 x 2)
+    T K[LB_MAX_M * LB_MAX_M];
+    T F0[2];
+    T Fphi[LB_MAX_M][2];
+    T chi, beta, cstar, eps;
+    T mrt_s[9];
+    T phi_ref[LB_MAX_M];
+    T scale, inv_scale;   // storage scale (F16 only; 1 otherwise)
+};
+
+struct Layout {
+    size_t N;             // nodes
+    size_t elem;          // bytes per stored population value
+    size_t plane;         // elements per population plane (padded)
+    size_t npop;          // population planes, 9 + 5m
+    size_t nsrc;          // S_old planes
+    size_t pop_off, sold_off, snap_off, stage_off, part_off, res_off, total;
+};
+
+constexpr int kRedBlocks = 1024;   // blocks of the first reduction pass (upper bound)
+constexpr int kRedWidth = 16;      // doubles per partial record
+
+struct Launch {
+    int tile_x, tile_y;
+};
+
+// launchers (lb_kernels.hip); all return hipError_t of the launch
+hipError_t launch_init(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                       const KParams<float>& kf, int has_p0, hipStream_t s);
+hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                       const KParams<float>& kf, bool odd, Launch lc, hipStream_t s);
+hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                          const KParams<float>& kf, bool odd, double* phi, double* u, double* pr,
+                          hipStream_t s);
+hipError_t launch_export(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                         const KParams<float>& kf, bool odd, int plane_begin, int plane_count,
+                         double* out, hipStream_t s);
+// mode 0: residual (updates the snapshot), mode 1: snapshot only, mode 2: mass
+hipError_t launch_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                         const KParams<float>& kf, bool odd, int mode, hipStream_t s);
+
+}  // namespace lbk

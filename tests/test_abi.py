@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/lb.h declares, its record matches the binding, and
+lb_init / lb_workspace_bytes reject bad inputs before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2101_03055_amd import lb, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared(header):
+    with open(os.path.join(ROOT, "include", header)) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:lb|sg|lbb)_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lb.lib()
+    names = declared("lb.h")
+    assert "lb_init" in names and "lb_step" in names and "lb_residual" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_params_record_matches():
+    assert lb.lib().lb_params_bytes() == C.sizeof(lb.lb_params)
+
+
+def test_workspace_bytes_scales_with_storage():
+    wl, *_ = W.taylor_green_blobs()
+    b64 = lb.lb_workspace_bytes(lb.params_from_workload(wl, "f64"))
+    b32 = lb.lb_workspace_bytes(lb.params_from_workload(wl, "f32"))
+    b16 = lb.lb_workspace_bytes(lb.params_from_workload(wl, "f16", fp16_scale=100.0))
+    assert b64 > b32 > b16 > 19 * 64 * 64 * 2
+
+
+@pytest.mark.parametrize("mutate, status", [
+    (lambda p: setattr(p, "tau_f", 0.5), lb.LB_EINVAL),
+    (lambda p: setattr(p, "m", 5), lb.LB_EINVAL),
+    (lambda p: setattr(p, "nx", 1), lb.LB_EINVAL),
+    (lambda p: p.D.__setitem__(0, -0.01), lb.LB_EINVAL),        # eigenvalue with negative real part
+    (lambda p: p.fluid_bc.__setitem__(0, 1), lb.LB_EINVAL),     # half a periodic pair
+    (lambda p: setattr(p, "storage", 7), lb.LB_EINVAL),
+    (lambda p: setattr(p, "reserved", 1), lb.LB_EINVAL),
+])
+def test_validation_rejects(mutate, status):
+    wl, *_ = W.taylor_green_blobs()
+    p = lb.params_from_workload(wl)
+    mutate(p)
+    with pytest.raises(lb.LBError) as ei:
+        lb.lb_workspace_bytes(p)
+    assert ei.value.status == status
+    assert lb.lib().lb_last_error()
+
+
+def test_complex_eigenvalues_with_positive_real_part_accepted():
+    wl = W._base(8, 8, 2, 0.8, [[0.05, 0.04], [-0.04, 0.05]])  # eig 0.05 +- 0.04i
+    assert lb.lb_workspace_bytes(lb.params_from_workload(wl)) > 0
+
+
+def test_init_rejects_before_touching_the_device():
+    wl, phi0, u0, p0 = W.taylor_green_blobs()
+    p = lb.params_from_workload(wl)
+    n = lb.lb_workspace_bytes(p)
+    h = C.c_void_p()
+    L = lb.lib()
+    # NULL workspace
+    st = L.lb_init(C.byref(p), None, n, None, phi0.ctypes.data, u0.ctypes.data, None, C.byref(h))
+    assert st == lb.LB_EINVAL and not h.value
+    # misaligned workspace
+    st = L.lb_init(C.byref(p), C.c_void_p(0x1008), n, None, phi0.ctypes.data, u0.ctypes.data, None, C.byref(h))
+    assert st == lb.LB_EINVAL
+    # too small
+    st = L.lb_init(C.byref(p), C.c_void_p(0x10000), n - 1, None, phi0.ctypes.data, u0.ctypes.data, None, C.byref(h))
+    assert st == lb.LB_ENOMEM
+    # non-finite initial field (checked on the host, before any copy)
+    bad = np.ascontiguousarray(phi0.copy())
+    bad[1, 3, 4] = np.nan
+    st = L.lb_init(C.byref(p), C.c_void_p(0x10000), n, None, bad.ctypes.data, u0.ctypes.data, None, C.byref(h))
+    assert st == lb.LB_ENONFINITE and not h.value
+
+
+def test_free_null_is_ok():
+    assert lb.lib().lb_free(None) == lb.LB_OK
