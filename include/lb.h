@@ -98,7 +98,8 @@ typedef struct lb_params {
     double chi, beta, cstar, eps;/* chemotaxis closure coefficients (lattice units) */
     double wall[4][LB_MAX_M];    /* Dirichlet wall values [side][species] */
     double phi_ref[LB_MAX_M];    /* reference level subtracted in reduced-precision storage */
-    double fp16_scale;           /* multiplier of the deviations in LB_STORE_F16 (> 0) */
+    double fp16_scale;           /* multiplier of the scalar deviations in LB_STORE_F16 (> 0) */
+    double fp16_scale_h;         /* multiplier of the fluid deviations in LB_STORE_F16 (> 0) */
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -140,6 +141,15 @@ lb_status lb_moments_device(lb_handle* h, double* d_phi, double* d_u, double* d_
  * Synchronises the stream. */
 lb_status lb_residual(lb_handle* h, double* res);
 
+/* Steady solve: repeats { lb_step(check_every); lb_residual } until every
+ * residual component is below tol (criterion of Sec. 3.1.1, absolute values),
+ * or max_steps steps have been taken, or a field turns non-finite.
+ * *steps_out = steps taken by this call; res_out[m + 2] = last residual (may be
+ * NULL).  Returns LB_OK when converged, LB_ESTATE when max_steps was reached
+ * first, LB_ENONFINITE on divergence. */
+lb_status lb_solve_steady(lb_handle* h, double tol, int64_t check_every, int64_t max_steps,
+                          int64_t* steps_out, double* res_out);
+
 /* Totals: mass[a] = sum_x phi_a (a < m), mass[m] = sum_x sum_i h_i (= N rho0 for the
  * incompressible equilibrium).  FP64, deterministic.  Synchronises the stream. */
 lb_status lb_mass(lb_handle* h, double* mass);
@@ -158,6 +168,13 @@ lb_status lb_time(lb_handle* h, int64_t* t);
 lb_status lb_state_bytes(lb_handle* h, size_t* bytes);
 lb_status lb_save(lb_handle* h, void* host_buf, size_t bytes);
 lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes);
+
+/* Copies the state of src into dst (both initialised, same parameters except
+ * storage, phi_ref and the FP16 scales), converting the storage on the device:
+ * populations, previous-step source and time counter.  Used to finish an FP32
+ * or FP16 run in FP64 (mixed-precision steady solve).  dst's residual snapshot
+ * is reset.  Synchronises both streams. */
+lb_status lb_copy_state(lb_handle* dst, lb_handle* src);
 
 /* Launch shape of the step kernel: tile_x * tile_y threads per workgroup,
  * tile_x a multiple of 64 (one wavefront per row segment), product <= 1024.

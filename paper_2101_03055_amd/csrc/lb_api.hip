@@ -208,8 +208,9 @@ lb_status validate(const lb_params* p) {
         if (!(p->chi >= 0.0) || !(p->beta >= 0.0)) return fail(LB_EINVAL, "chemotaxis: chi, beta must be >= 0");
         if (p->r_kind == LB_R_SMOOTH && !(p->eps > 0.0)) return fail(LB_EINVAL, "smooth r(c) needs eps > 0");
     }
-    if (p->storage == LB_STORE_F16 && !(p->fp16_scale > 0.0 && std::isfinite(p->fp16_scale)))
-        return fail(LB_EINVAL, "fp16_scale must be > 0");
+    if (p->storage == LB_STORE_F16 && !(p->fp16_scale > 0.0 && std::isfinite(p->fp16_scale) &&
+                                        p->fp16_scale_h > 0.0 && std::isfinite(p->fp16_scale_h)))
+        return fail(LB_EINVAL, "fp16_scale and fp16_scale_h must be finite and > 0");
     return LB_OK;
 }
 
@@ -260,6 +261,8 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     for (int q = 0; q < 9; ++q) k.mrt_s[q] = T(p.mrt_s[q]);
     k.scale = T(p.storage == LB_STORE_F16 ? p.fp16_scale : 1.0);
     k.inv_scale = T(p.storage == LB_STORE_F16 ? 1.0 / p.fp16_scale : 1.0);
+    k.scale_h = T(p.storage == LB_STORE_F16 ? p.fp16_scale_h : 1.0);
+    k.inv_scale_h = T(p.storage == LB_STORE_F16 ? 1.0 / p.fp16_scale_h : 1.0);
 }
 
 }  // namespace
@@ -272,7 +275,8 @@ struct lb_handle {
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
-    int64_t t;           // steps taken; AA parity = t & 1
+    int64_t t;           // steps taken
+    int parity;          // 0: canonical layout (own slots); 1: layout left by an even step
     int has_snapshot;
     Launch lc;
 };
@@ -288,6 +292,7 @@ void* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 struct StateHeader {
     uint64_t magic;
     int64_t t;
+    int64_t parity;
     int64_t has_snapshot;
     uint64_t param_hash;
     uint64_t pop_bytes, sold_bytes, snap_bytes;
@@ -348,6 +353,7 @@ lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace
     h->ws_bytes = workspace_bytes;
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->t = 0;
+    h->parity = 0;
     h->has_snapshot = 0;
     h->lc = default_launch(h->p);
 
@@ -369,17 +375,18 @@ lb_status lb_step(lb_handle* h, int64_t n) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (n < 0) return fail(LB_EINVAL, "n = %lld < 0", (long long)n);
     for (int64_t s = 0; s < n; ++s) {
-        const bool odd = (h->t & 1) != 0;
-        hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, odd, h->lc, h->stream);
+        const bool odd = h->parity != 0;
+        hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, odd, h->lc, h->t, h->stream);
         if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
         h->t += 1;
+        h->parity ^= 1;
     }
     return LB_OK;
 }
 
 lb_status lb_moments_device(lb_handle* h, double* d_phi, double* d_u, double* d_p) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
-    hipError_t e = launch_moments(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, d_phi, d_u, d_p, h->stream);
+    hipError_t e = launch_moments(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, d_phi, d_u, d_p, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_moments_device: %s", hipGetErrorString(e));
     return LB_OK;
 }
@@ -405,7 +412,7 @@ lb_status lb_residual(lb_handle* h, double* res) {
     if (!res) return fail(LB_EINVAL, "res is NULL");
     const int Q = h->p.m + 2;
     const int mode = h->has_snapshot ? 0 : 1;
-    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, mode, h->stream);
+    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, mode, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_residual: %s", hipGetErrorString(e));
     double out[64];
     HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (3 * Q + 1), hipMemcpyDeviceToHost,
@@ -417,11 +424,43 @@ lb_status lb_residual(lb_handle* h, double* res) {
     return LB_OK;
 }
 
+lb_status lb_solve_steady(lb_handle* h, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
+                          double* res_out) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!(tol > 0.0) || check_every < 1 || max_steps < 0) return fail(LB_EINVAL, "tol > 0, check_every >= 1 required");
+    double res[LB_MAX_M + 2];
+    const int Q = h->p.m + 2;
+    int64_t done = 0;
+    lb_status st = LB_OK;
+    if (!h->has_snapshot) {
+        st = lb_residual(h, res);
+        if (st != LB_OK) goto out;
+    }
+    st = LB_ESTATE;
+    while (done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        lb_status s2 = lb_step(h, k);
+        if (s2 != LB_OK) { st = s2; break; }
+        done += k;
+        s2 = lb_residual(h, res);
+        if (s2 != LB_OK) { st = s2; break; }
+        double r = 0.0;
+        for (int q = 0; q < Q; ++q) r = std::max(r, res[q]);
+        if (k == check_every && r < tol) { st = LB_OK; break; }
+    }
+    if (st == LB_ESTATE) fail(LB_ESTATE, "not converged after %lld steps", (long long)done);
+out:
+    if (steps_out) *steps_out = done;
+    if (res_out)
+        for (int q = 0; q < Q; ++q) res_out[q] = res[q];
+    return st;
+}
+
 lb_status lb_mass(lb_handle* h, double* mass) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (!mass) return fail(LB_EINVAL, "mass is NULL");
     const int Q = h->p.m + 2;
-    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, 2, h->stream);
+    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, 2, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_mass: %s", hipGetErrorString(e));
     double out[64];
     HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (2 * Q + 1), hipMemcpyDeviceToHost,
@@ -442,7 +481,7 @@ lb_status lb_populations(lb_handle* h, double* f, double* hpop) {
         const int cnt = std::min(chunk, total - b);
         const bool want_h = hpop && b < 9, want_f = f && b + cnt > 9;
         if (!want_h && !want_f) continue;
-        hipError_t e = launch_export(h->p, h->L, h->ws, h->kd, h->kf, (h->t & 1) != 0, b, cnt, stage, h->stream);
+        hipError_t e = launch_export(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, b, cnt, stage, h->stream);
         if (e != hipSuccess) return fail(LB_EDEVICE, "lb_populations: %s", hipGetErrorString(e));
         for (int k = b; k < b + cnt; ++k) {
             double* dst = k < 9 ? (hpop ? hpop + (size_t)k * N : nullptr) : (f ? f + (size_t)(k - 9) * N : nullptr);
@@ -471,7 +510,7 @@ lb_status lb_save(lb_handle* h, void* host_buf, size_t bytes) {
     lb_status st = lb_state_bytes(h, &need);
     if (st != LB_OK) return st;
     if (!host_buf || bytes < need) return fail(LB_EINVAL, "buffer of %zu bytes, %zu needed", bytes, need);
-    StateHeader hd{kMagic, h->t, h->has_snapshot, fnv(&h->p, sizeof h->p), pop_bytes(h), sold_bytes(h), snap_bytes(h)};
+    StateHeader hd{kMagic, h->t, h->parity, h->has_snapshot, fnv(&h->p, sizeof h->p), pop_bytes(h), sold_bytes(h), snap_bytes(h)};
     char* b = static_cast<char*>(host_buf);
     std::memcpy(b, &hd, sizeof hd);
     b += sizeof hd;
@@ -504,7 +543,36 @@ lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes) {
     HIPCHK(hipMemcpyAsync(at(h->ws, h->L.snap_off), b, hd.snap_bytes, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->t = hd.t;
+    h->parity = (int)hd.parity;
     h->has_snapshot = (int)hd.has_snapshot;
+    return LB_OK;
+}
+
+lb_status lb_copy_state(lb_handle* dst, lb_handle* src) {
+    if (!dst || !src) return fail(LB_EINVAL, "handle is NULL");
+    lb_params a = dst->p, b = src->p;
+    a.storage = b.storage = 0;
+    for (int k = 0; k < LB_MAX_M; ++k) a.phi_ref[k] = b.phi_ref[k] = 0.0;
+    a.fp16_scale = b.fp16_scale = a.fp16_scale_h = b.fp16_scale_h = 0.0;
+    if (std::memcmp(&a, &b, sizeof a) != 0)
+        return fail(LB_EINVAL, "lb_copy_state: handles differ in more than storage, phi_ref and scales");
+    HIPCHK(hipStreamSynchronize(src->stream));
+    const int total = 9 + 5 * dst->p.m;
+    const int chunk = dst->p.m + 3;
+    double* stage = (double*)at(dst->ws, dst->L.stage_off);
+    for (int b0 = 0; b0 < total; b0 += chunk) {
+        const int cnt = std::min(chunk, total - b0);
+        hipError_t e = launch_export(src->p, src->L, src->ws, src->kd, src->kf, src->parity != 0, b0, cnt, stage,
+                                     dst->stream);
+        if (e == hipSuccess) e = launch_import(dst->p, dst->L, dst->ws, dst->kd, dst->kf, b0, cnt, stage, dst->stream);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "lb_copy_state: %s", hipGetErrorString(e));
+    }
+    hipError_t e = launch_copy_sold(src->p, src->L, src->ws, dst->p, dst->L, dst->ws, dst->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_copy_state: %s", hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(dst->stream));
+    dst->t = src->t;
+    dst->parity = 0;
+    dst->has_snapshot = 0;
     return LB_OK;
 }
 

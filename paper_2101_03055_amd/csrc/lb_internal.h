@@ -33,7 +33,8 @@ struct KParams {
     T chi, beta, cstar, eps;
     T mrt_s[9];
     T phi_ref[LB_MAX_M];
-    T scale, inv_scale;   // storage scale (F16 only; 1 otherwise)
+    T scale, inv_scale;   // storage scale of the scalar planes (F16 only; 1 otherwise)
+    T scale_h, inv_scale_h; // storage scale of the fluid planes (F16 only; 1 otherwise)
 };
 
 struct Layout {
@@ -56,13 +57,21 @@ struct Launch {
 hipError_t launch_init(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                        const KParams<float>& kf, int has_p0, hipStream_t s);
 hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                       const KParams<float>& kf, bool odd, Launch lc, hipStream_t s);
+                       const KParams<float>& kf, bool odd, Launch lc, int64_t step, hipStream_t s);
 hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                           const KParams<float>& kf, bool odd, double* phi, double* u, double* pr,
                           hipStream_t s);
 hipError_t launch_export(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                          const KParams<float>& kf, bool odd, int plane_begin, int plane_count,
                          double* out, hipStream_t s);
+// writes planes [plane_begin, plane_begin + count) of canonical raw FP64
+// populations (as produced by launch_export) into the own-slot layout
+hipError_t launch_import(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                         const KParams<float>& kf, int plane_begin, int plane_count, const double* in,
+                         hipStream_t s);
+// converts the previous-step source planes between storage modes
+hipError_t launch_copy_sold(const lb_params& ps, const Layout& Ls, void* wss, const lb_params& pd,
+                            const Layout& Ld, void* wsd, hipStream_t s);
 // mode 0: residual (updates the snapshot), mode 1: snapshot only, mode 2: mass
 hipError_t launch_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                          const KParams<float>& kf, bool odd, int mode, hipStream_t s);

@@ -77,19 +77,45 @@ struct St<_Float16> {
     static constexpr bool scaled = true;
 };
 
+// FP16 deviations carry one scale for the fluid planes (0..8) and one for
+// the scalar planes; FP32/FP64 are unscaled
 template <class S, class T>
-__device__ __forceinline__ T ld(const S* p, const KParams<T>& kp) {
+__device__ __forceinline__ T ld(const S* p, const KParams<T>& kp, bool fluid) {
     if constexpr (St<S>::scaled)
-        return T(*p) * kp.inv_scale;
+        return T(*p) * (fluid ? kp.inv_scale_h : kp.inv_scale);
     else
         return T(*p);
 }
+// 32-bit integer mixer (Wellons' "lowbias32"), used as a counter-based
+// generator for stochastic rounding
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// binary16 with stochastic rounding: adding uniform random bits below the 10
+// kept mantissa bits to the magnitude and truncating rounds up with
+// probability equal to the discarded fraction, so increments smaller than
+// half an ulp survive in expectation.  The random bits depend only on the
+// element index and the step (salt), so runs are reproducible.  Values below
+// the binary16 normal range fall back to round-to-nearest.
+__device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t key) {
+    if (!(fabsf(v) >= 6.103515625e-05f) || !(fabsf(v) < 65504.0f)) return _Float16(v);
+    uint32_t b = __float_as_uint(v);
+    b = (b + (mix32(key) & 0x1fffu)) & ~0x1fffu;
+    return _Float16(__uint_as_float(b));
+}
+
 template <class S, class T>
-__device__ __forceinline__ void st(S* p, T v, const KParams<T>& kp) {
+__device__ __forceinline__ void st(S* base, long long idx, T v, const KParams<T>& kp, bool fluid, uint32_t salt) {
     if constexpr (St<S>::scaled)
-        *p = S(v * kp.scale);
+        base[idx] = to_half_sr(v * (fluid ? kp.scale_h : kp.scale), (uint32_t)idx * 0x9e3779b9u ^ salt);
     else
-        *p = S(v);
+        base[idx] = S(v);
 }
 
 // ---- geometry helpers -------------------------------------------------------
@@ -120,23 +146,23 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
     const long long n = (long long)y * nx + x;
     if constexpr (!PULL) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = ld(pop + i * P + n, kp);
+        for (int i = 0; i < 9; ++i) h[i] = ld(pop + i * P + n, kp, true);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + (9 + 5 * a + i) * P + n, kp);
+            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
         return;
     } else {
         const bool interior = (x > 0) & (x < nx - 1) & (y > 0) & (y < ny - 1);
         if (interior) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                h[i] = ld(pop + OPP9[i] * P + n - CY9[i] * nx - CX9[i], kp);
+                h[i] = ld(pop + OPP9[i] * P + n - CY9[i] * nx - CX9[i], kp, true);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + n - CY5[i] * nx - CX5[i], kp);
+                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + n - CY5[i] * nx - CX5[i], kp, false);
             return;
         }
 #pragma unroll
@@ -170,7 +196,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                     }
                 }
             }
-            h[i] = ld(pop + pl * P + src, kp);
+            h[i] = ld(pop + pl * P + src, kp, true);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -179,10 +205,10 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                 int sx = x - CX5[i], sy = y - CY5[i];
                 const bool inx = wrap_in(sx, nx, kp.px), iny = wrap_in(sy, ny, kp.py);
                 if (inx & iny) {
-                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + (long long)sy * nx + sx, kp);
+                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + (long long)sy * nx + sx, kp, false);
                 } else {
                     const int side = inx ? side_y(sy) : side_x(sx);
-                    T v = ld(pop + (9 + 5 * a + i) * P + n, kp);
+                    T v = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
                     if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
                     f[a][i] = v;
                 }
@@ -195,28 +221,28 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
 // opp(i).  PUSH = true: odd step, to slot i of x + c_i, or by the wall rules.
 template <class S, int M, bool PUSH, class T>
 __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ pop, int x, int y,
-                                        const T h[9], const T f[M][5]) {
+                                        const T h[9], const T f[M][5], uint32_t salt) {
     const long long P = kp.plane;
     const int nx = kp.nx, ny = kp.ny;
     const long long n = (long long)y * nx + x;
     if constexpr (!PUSH) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st(pop + OPP9[i] * P + n, h[i], kp);
+        for (int i = 0; i < 9; ++i) st(pop, OPP9[i] * P + n, h[i], kp, true, salt);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st(pop + (9 + 5 * a + OPP5[i]) * P + n, f[a][i], kp);
+            for (int i = 0; i < 5; ++i) st(pop, (9 + 5 * a + OPP5[i]) * P + n, f[a][i], kp, false, salt);
         return;
     } else {
         const bool interior = (x > 0) & (x < nx - 1) & (y > 0) & (y < ny - 1);
         if (interior) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st(pop + i * P + n + CY9[i] * nx + CX9[i], h[i], kp);
+            for (int i = 0; i < 9; ++i) st(pop, i * P + n + CY9[i] * nx + CX9[i], h[i], kp, true, salt);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    st(pop + (9 + 5 * a + i) * P + n + CY5[i] * nx + CX5[i], f[a][i], kp);
+                    st(pop, (9 + 5 * a + i) * P + n + CY5[i] * nx + CX5[i], f[a][i], kp, false, salt);
             return;
         }
 #pragma unroll
@@ -250,7 +276,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     }
                 }
             }
-            st(pop + pl * P + dst, h[i], kp);
+            st(pop, pl * P + dst, h[i], kp, true, salt);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -259,12 +285,12 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                 int tx = x + CX5[i], ty = y + CY5[i];
                 const bool inx = wrap_in(tx, nx, kp.px), iny = wrap_in(ty, ny, kp.py);
                 if (inx & iny) {
-                    st(pop + (9 + 5 * a + i) * P + (long long)ty * nx + tx, f[a][i], kp);
+                    st(pop, (9 + 5 * a + i) * P + (long long)ty * nx + tx, f[a][i], kp, false, salt);
                 } else {
                     const int side = inx ? side_y(ty) : side_x(tx);
                     T v = f[a][i];
                     if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
-                    st(pop + (9 + 5 * a + OPP5[i]) * P + n, v, kp);
+                    st(pop, (9 + 5 * a + OPP5[i]) * P + n, v, kp, false, salt);
                 }
             }
     }
@@ -371,37 +397,58 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
     }
 
     // scalar matrix collision (Eq. evolution12), f^eq of Eq. feq-phi with
-    // lambda = I, vartheta = 0 in deviation form: W_i (phid + 3 phi c.u)
+    // lambda = I, vartheta = 0 in deviation form: W_i (phid + 3 phi c.u).
+    // The rest direction takes the remainder, f^eq_0 = phid - sum_{i>0} f^eq_i
+    // (and likewise for W_i S): with rounded weights sum_i W_i != 1, which
+    // would create or destroy mass by the same fraction at every step.
+    T feq[M][5], wsrc[M][5];
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+        const T iso = mc.phid[b] * (T(1) / T(6));
+        const T adv = T(0.5) * mc.phi[b];  // 3 W_i phi for i > 0
+        feq[b][1] = iso + adv * mc.u[0];
+        feq[b][3] = iso - adv * mc.u[0];
+        feq[b][2] = iso + adv * mc.u[1];
+        feq[b][4] = iso - adv * mc.u[1];
+        feq[b][0] = mc.phid[b] - T(4) * iso;
+        const T s6 = src[b] * (T(1) / T(6));
+        wsrc[b][1] = wsrc[b][2] = wsrc[b][3] = wsrc[b][4] = s6;
+        wsrc[b][0] = src[b] - T(4) * s6;
+    }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         const T wi = w5<T>(i);
-        const T cu = T(CX5[i]) * mc.u[0] + T(CY5[i]) * mc.u[1];
         T neq[M];
 #pragma unroll
-        for (int b = 0; b < M; ++b) neq[b] = f[b][i] - wi * (mc.phid[b] + T(3) * mc.phi[b] * cu);
+        for (int b = 0; b < M; ++b) neq[b] = f[b][i] - feq[b][i];
 #pragma unroll
         for (int a = 0; a < M; ++a) {
             T coll = T(0);
 #pragma unroll
             for (int b = 0; b < M; ++b) coll += om[a][b] * neq[b];
             const T cg = T(CX5[i]) * g[a][0] + T(CY5[i]) * g[a][1];
-            f[a][i] = f[a][i] - coll + wi * src[a] + T(3) * wi * cg;
+            f[a][i] = f[a][i] - coll + wsrc[a][i] + T(3) * wi * cg;
         }
     }
 
     // fluid: h^eq of Eq. heq, F_i of Eq. force with varphi = 0
     const T usq = mc.u[0] * mc.u[0] + mc.u[1] * mc.u[1];
+    // h^eq_0 = rho0 - sum_{i>0} h^eq_i (Eq. momentNS: sum_i h^eq_i = rho0), which
+    // equals sigma_0 - W_0 u.u/(2 cs2) of Eq. heq without a rounding bias
     T heq[9], Fi[9];
+    T hsum = T(0);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 1; i < 9; ++i) {
         const T wi = w9<T>(i);
         const T cu = T(CX9[i]) * mc.u[0] + T(CY9[i]) * mc.u[1];
+        heq[i] = wi * (T(3) * mc.p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+        hsum += heq[i];
+    }
+    heq[0] = kp.rho0_eff - hsum;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
         const T cF = T(CX9[i]) * mc.F[0] + T(CY9[i]) * mc.F[1];
-        if (i == 0)
-            heq[i] = -(T(5) / T(3)) * mc.p + kp.rho0_eff - (T(2) / T(3)) * usq;
-        else
-            heq[i] = wi * (T(3) * mc.p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
-        Fi[i] = T(3) * wi * cF;
+        Fi[i] = T(3) * w9<T>(i) * cF;
     }
     const T w = kp.omega_f;
     if constexpr (COLL == LB_COLL_BGK) {
@@ -448,7 +495,7 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
 template <class S, int M, int MODEL, int COLL, bool ODD>
 __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* __restrict__ pop,
                                               typename St<S>::T* __restrict__ sold, int tile_x, int tile_y,
-                                              int tiles_x) {
+                                              int tiles_x, uint32_t salt) {
     using T = typename St<S>::T;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = b % tiles_x, by = b / tiles_x;
@@ -470,7 +517,7 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
 #pragma unroll
     for (int a = 0; a < M; ++a)
         if (kp.src_mask >> a & 1) sold[(long long)(k++) * kp.nx * kp.ny + n] = Snew[a];
-    scatter<S, M, ODD>(kp, pop, x, y, h, f);
+    scatter<S, M, ODD>(kp, pop, x, y, h, f, salt);
 }
 
 // initial state: f = f^eq(phi0, u0), h = h^eq(p0, u0), S_old = S(phi0)
@@ -489,25 +536,28 @@ __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* 
     u[1] = T(stage[(M + 1) * N + n]);
     const T p = has_p0 ? T(stage[(M + 2) * N + n]) : T(0);
     const long long P = kp.plane;
+    const uint32_t salt = 0x51ed270bu;
 #pragma unroll
-    for (int a = 0; a < M; ++a)
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const T cu = T(CX5[i]) * u[0] + T(CY5[i]) * u[1];
-            const T wi = w5<T>(i);
-            st(pop + (9 + 5 * a + i) * P + n, wi * (phi[a] - kp.phi_ref[a]) + T(3) * wi * phi[a] * cu, kp);
-        }
-    const T usq = u[0] * u[0] + u[1] * u[1];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const T cu = T(CX9[i]) * u[0] + T(CY9[i]) * u[1];
-        T v;
-        if (i == 0)
-            v = -(T(5) / T(3)) * p + kp.rho0_eff - (T(2) / T(3)) * usq;
-        else
-            v = w9<T>(i) * (T(3) * p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
-        st(pop + i * P + n, v, kp);
+    for (int a = 0; a < M; ++a) {
+        const T phid = phi[a] - kp.phi_ref[a];
+        const T iso = phid * (T(1) / T(6));
+        const T adv = T(0.5) * phi[a];
+        st(pop, (9 + 5 * a + 1) * P + n, iso + adv * u[0], kp, false, salt);
+        st(pop, (9 + 5 * a + 3) * P + n, iso - adv * u[0], kp, false, salt);
+        st(pop, (9 + 5 * a + 2) * P + n, iso + adv * u[1], kp, false, salt);
+        st(pop, (9 + 5 * a + 4) * P + n, iso - adv * u[1], kp, false, salt);
+        st(pop, (9 + 5 * a + 0) * P + n, phid - T(4) * iso, kp, false, salt);
     }
+    const T usq = u[0] * u[0] + u[1] * u[1];
+    T hsum = T(0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const T cu = T(CX9[i]) * u[0] + T(CY9[i]) * u[1];
+        const T v = w9<T>(i) * (T(3) * p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+        hsum += v;
+        st(pop, i * P + n, v, kp, true, salt);
+    }
+    st(pop, 0 * P + n, kp.rho0_eff - hsum, kp, true, salt);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -570,6 +620,34 @@ __global__ __launch_bounds__(256) void k_export(KParams<typename St<S>::T> kp, c
         }
         out[(long long)(k - plane_begin) * N + n] = v;
     }
+}
+
+// inverse of k_export: raw canonical FP64 planes into the own-slot layout
+template <class S, int M>
+__global__ __launch_bounds__(256) void k_import(KParams<typename St<S>::T> kp, S* __restrict__ pop,
+                                                int plane_begin, int count, const double* __restrict__ in) {
+    using T = typename St<S>::T;
+    const long long N = (long long)kp.nx * kp.ny;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint32_t salt = 0x2545f491u;
+#pragma unroll
+    for (int k = 0; k < 9 + 5 * M; ++k) {
+        if (k < plane_begin || k >= plane_begin + count) continue;
+        const double v = in[(long long)(k - plane_begin) * N + n];
+        if (k < 9) {
+            st(pop, k * kp.plane + n, T(v - (k == 0 ? double(kp.h0_shift) : 0.0)), kp, true, salt);
+        } else {
+            const int a = (k - 9) / 5, i = (k - 9) % 5;
+            st(pop, k * kp.plane + n, T(v - double(w5<T>(i)) * double(kp.phi_ref[a])), kp, false, salt);
+        }
+    }
+}
+
+template <class TS, class TD>
+__global__ __launch_bounds__(256) void k_convert(const TS* __restrict__ src, TD* __restrict__ dst, long long n) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = TD(src[k]);
 }
 
 // deterministic block reduction of NV doubles (wave64 shuffles, then LDS)
@@ -710,7 +788,8 @@ hipError_t launch_init(const lb_params& p, const Layout& L, void* ws, const KPar
 }
 
 hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                       const KParams<float>& kf, bool odd, Launch lc, hipStream_t s) {
+                       const KParams<float>& kf, bool odd, Launch lc, int64_t step, hipStream_t s) {
+    const uint32_t salt = mix32((uint32_t)step ^ (uint32_t)(step >> 32) * 0x632be5abu);
     const int tiles_x = (p.nx + lc.tile_x - 1) / lc.tile_x;
     const int tiles_y = (p.ny + lc.tile_y - 1) / lc.tile_y;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)(lc.tile_x * lc.tile_y));
@@ -722,17 +801,17 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
         if (p.collision == LB_COLL_MRT) {
             if (odd)
                 hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_MRT, true>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x);
+                                   lc.tile_x, lc.tile_y, tiles_x, salt);
             else
                 hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_MRT, false>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x);
+                                   lc.tile_x, lc.tile_y, tiles_x, salt);
         } else {
             if (odd)
                 hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_BGK, true>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x);
+                                   lc.tile_x, lc.tile_y, tiles_x, salt);
             else
                 hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_BGK, false>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x);
+                                   lc.tile_x, lc.tile_y, tiles_x, salt);
         }
         return hipGetLastError();
     });
@@ -766,6 +845,35 @@ hipError_t launch_export(const lb_params& p, const Layout& L, void* ws, const KP
                                pop, plane_begin, plane_count, out);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_import(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                         const KParams<float>& kf, int plane_begin, int plane_count, const double* in,
+                         hipStream_t s) {
+    return dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
+        hipLaunchKernelGGL((k_import<S, M>), dim3(blocks_for(L.N)), dim3(256), 0, s, kpar<S>(kd, kf),
+                           (S*)at(ws, L.pop_off), plane_begin, plane_count, in);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_copy_sold(const lb_params& ps, const Layout& Ls, void* wss, const lb_params& pd,
+                            const Layout& Ld, void* wsd, hipStream_t s) {
+    const long long n = (long long)(Ls.nsrc * Ls.N);
+    if (n == 0) return hipSuccess;
+    const bool s64 = ps.storage == LB_STORE_F64, d64 = pd.storage == LB_STORE_F64;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    void* src = at(wss, Ls.sold_off);
+    void* dst = at(wsd, Ld.sold_off);
+    if (s64 && d64)
+        hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, s, (const double*)src, (double*)dst, n);
+    else if (s64)
+        hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, s, (const double*)src, (float*)dst, n);
+    else if (d64)
+        hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, s, (const float*)src, (double*)dst, n);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, s, (const float*)src, (float*)dst, n);
+    return hipGetLastError();
 }
 
 int reduce_blocks(size_t N) {

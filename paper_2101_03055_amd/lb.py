@@ -51,6 +51,7 @@ class lb_params(C.Structure):
         ("wall", (C.c_double * MAXM) * 4),
         ("phi_ref", C.c_double * MAXM),
         ("fp16_scale", C.c_double),
+        ("fp16_scale_h", C.c_double),
     ]
 
 
@@ -81,6 +82,8 @@ def lib():
             "lb_save": [vp, vp, sz],
             "lb_load": [vp, vp, sz],
             "lb_set_tile": [vp, C.c_int32, C.c_int32],
+            "lb_copy_state": [vp, vp],
+            "lb_solve_steady": [vp, C.c_double, i64, i64, C.POINTER(i64), vp],
             "lb_free": [vp],
         }
         for name, args in sig.items():
@@ -100,7 +103,8 @@ def _check(status):
         raise LBError(status, lib().lb_last_error().decode())
 
 
-def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scale: float = 1.0) -> lb_params:
+def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scale: float = 1.0,
+                         fp16_scale_h: float | None = None) -> lb_params:
     """Fill the C record from a workload dict (see ``workloads``)."""
     p = lb_params()
     m = wl["m"]
@@ -139,6 +143,7 @@ def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scal
         for a in range(m):
             p.phi_ref[a] = float(phi_ref[a])
     p.fp16_scale = fp16_scale
+    p.fp16_scale_h = fp16_scale if fp16_scale_h is None else fp16_scale_h
     return p
 
 
@@ -227,6 +232,21 @@ def lb_load(h, blob: bytes):
     _check(lib().lb_load(h, buf, len(blob)))
 
 
+def lb_solve_steady(h, m: int, tol: float, check_every: int, max_steps: int):
+    """Returns (steps, res[m + 2], status) with status LB_OK (converged),
+    LB_ESTATE (step cap reached) or LB_ENONFINITE (diverged)."""
+    steps = C.c_int64()
+    res = np.full(m + 2, np.inf)
+    st = lib().lb_solve_steady(h, float(tol), int(check_every), int(max_steps), C.byref(steps), res.ctypes.data)
+    if st not in (LB_OK, LB_ESTATE, LB_ENONFINITE):
+        _check(st)
+    return steps.value, res, st
+
+
+def lb_copy_state(dst, src):
+    _check(lib().lb_copy_state(dst, src))
+
+
 def lb_set_tile(h, tile_x: int, tile_y: int):
     _check(lib().lb_set_tile(h, int(tile_x), int(tile_y)))
 
@@ -239,13 +259,14 @@ class Solver:
     """A handle plus the torch workspace that backs it (freed together)."""
 
     def __init__(self, wl: dict, phi0, u0, p0=None, storage: str = "f64", phi_ref=None,
-                 fp16_scale: float = 1.0, device: str = "cuda:0", stream=None):
+                 fp16_scale: float = 1.0, fp16_scale_h: float | None = None, device: str = "cuda:0",
+                 stream=None):
         import torch
 
         lib()
         self.wl = wl
         self.m, self.ny, self.nx = wl["m"], wl["ny"], wl["nx"]
-        self.params = params_from_workload(wl, storage, phi_ref, fp16_scale)
+        self.params = params_from_workload(wl, storage, phi_ref, fp16_scale, fp16_scale_h)
         nbytes = lb_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
@@ -263,6 +284,9 @@ class Solver:
 
     def mass(self):
         return lb_mass(self.handle, self.m)
+
+    def solve_steady(self, tol=1e-8, check_every=1000, max_steps=5_000_000):
+        return lb_solve_steady(self.handle, self.m, tol, check_every, max_steps)
 
     def populations(self):
         return lb_populations(self.handle, self.m, self.ny, self.nx)

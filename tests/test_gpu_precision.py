@@ -1,0 +1,122 @@
+"""Reduced-precision storage (FP32 deviations, scaled FP16 deviations with
+stochastic rounding) against the FP64 oracle, and the mixed-precision steady
+solve (FP32 phase, FP64 finish through lb_copy_state).
+
+Tolerances: FP32 has unit roundoff 6e-8; each step rounds every stored
+deviation once and the collision adds a few FP32 roundings, so after n steps
+the scalar fields carry ~ c sqrt(n) 6e-8 relative to their largest deviation
+(c ~ 10 for 5 directions and a few operations): 3e-5 at n = 2000.  The
+velocity is a difference of populations, so its relative error is larger by
+|h| / |u|.  FP16 has unit roundoff 4.9e-4 (10 stored mantissa bits); with
+stochastic rounding errors stay unbiased and grow like sqrt(n).
+"""
+import numpy as np
+import pytest
+
+from paper_2101_03055_amd import lb, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def field_errors(g, o, phi_ref):
+    phi, u, _ = g.moments()
+    po, uo, _ = o.moments()
+    ephi = max(np.abs(phi[a] - po[a]).max() / np.abs(po[a] - phi_ref[a]).max() for a in range(phi.shape[0]))
+    eu = max(np.abs(u[d] - uo[d]).max() / np.abs(uo[d]).max() for d in range(2))
+    return ephi, eu
+
+
+CASES = {
+    "taylor_green_blobs_64": (lambda: W.taylor_green_blobs(), 1000, [1.0, 1.0]),
+    "ddc_cavity_256": (lambda: W.ddc_cavity(256), 2000, [0.5, 0.5]),
+    "chemotaxis_plume_512x256": (lambda: W.chemotaxis_plume(), 2000, [1.0, 1.0]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_f32_against_oracle(oracle_mod, case):
+    make, steps, ref = CASES[case]
+    wl, phi0, u0, p0 = make()
+    o = oracle_mod.Oracle(wl, phi0, u0, p0)
+    o.step(steps)
+    g = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=ref)
+    g.step(steps)
+    ephi, eu = field_errors(g, o, ref)
+    print(f"f32 {case} {steps} steps: phi {ephi:.2e} u {eu:.2e}", flush=True)
+    assert ephi < 3e-5
+    assert eu < 5e-4
+
+
+@pytest.mark.parametrize("case", ["taylor_green_blobs_64", "ddc_cavity_256"])
+def test_f16_against_oracle(oracle_mod, case):
+    make, steps, ref = CASES[case]
+    wl, phi0, u0, p0 = make()
+    o = oracle_mod.Oracle(wl, phi0, u0, p0)
+    o.step(steps)
+    g = lb.Solver(wl, phi0, u0, p0, storage="f16", phi_ref=ref, fp16_scale=1e4, fp16_scale_h=1e5)
+    g.step(steps)
+    ephi, eu = field_errors(g, o, ref)
+    print(f"f16 {case} {steps} steps: phi {ephi:.2e} u {eu:.2e}", flush=True)
+    assert ephi < 1e-2
+    assert eu < 5e-2
+
+
+def test_f16_reproducible():
+    wl, phi0, u0, p0 = W.ddc_cavity(64)
+    a = lb.Solver(wl, phi0, u0, p0, storage="f16", phi_ref=[0.5, 0.5], fp16_scale=1e4, fp16_scale_h=1e5)
+    b = lb.Solver(wl, phi0, u0, p0, storage="f16", phi_ref=[0.5, 0.5], fp16_scale=1e4, fp16_scale_h=1e5)
+    a.step(300)
+    b.step(300)
+    fa, ha = a.populations()
+    fb, hb = b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ha, hb)
+
+
+def test_copy_state_f64_roundtrip_bitwise():
+    wl, phi0, u0, p0 = W.random_case(53, 41, seed=12, source=True, fluid_bc=["noslip"] * 4,
+                                     scalar_bc=[["dirichlet"] * 2] * 2 + [["noflux"] * 2] * 2)
+    a = lb.Solver(wl, phi0, u0, p0)
+    b = lb.Solver(wl, phi0 * 0 + 1, u0 * 0)
+    a.step(33)  # odd: a's layout is the even-step one, b receives canonical
+    lb.lb_copy_state(b.handle, a.handle)
+    assert b.t == 33
+    a.step(20)
+    b.step(20)
+    fa, ha = a.populations()
+    fb, hb = b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ha, hb)
+
+
+def test_copy_state_f32_to_f64():
+    wl, phi0, u0, p0 = W.ddc_cavity(64)
+    a = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[0.5, 0.5])
+    a.step(501)
+    b = lb.Solver(wl, phi0, u0, p0, storage="f64")
+    lb.lb_copy_state(b.handle, a.handle)
+    fa, ha = a.populations()
+    fb, hb = b.populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ha, hb)  # FP32 values are exact in FP64
+
+
+def test_mixed_precision_steady_matches_fp64():
+    """Steady DDC cavity (96 x 96, Ra 1e4): FP32 to its noise floor, then FP64
+    to residual 1e-8, ends within 1e-6 relative L2 of the all-FP64 solve."""
+    wl, phi0, u0, p0 = W.ddc(96, Ra=1e4, Pr=0.71, Le=2.0, Nc=1.0, Sr=0.1, Df=0.1)
+    ref = lb.Solver(wl, phi0, u0, p0, storage="f64")
+    n64, r64, st64 = ref.solve_steady(1e-8, 1000, 3_000_000)
+    assert st64 == lb.LB_OK
+    phi_r, u_r, _ = ref.moments()
+    a = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[0.5, 0.5])
+    n32, r32, st32 = a.solve_steady(1e-6, 1000, 3_000_000)
+    phi32, u32, _ = a.moments()
+    e32 = max(np.linalg.norm(phi32 - phi_r) / np.linalg.norm(phi_r), np.linalg.norm(u32 - u_r) / np.linalg.norm(u_r))
+    b = lb.Solver(wl, phi0, u0, p0, storage="f64")
+    lb.lb_copy_state(b.handle, a.handle)
+    nfin, rfin, stfin = b.solve_steady(1e-8, 1000, 3_000_000)
+    phi, u, _ = b.moments()
+    e = max(np.linalg.norm(phi - phi_r) / np.linalg.norm(phi_r), np.linalg.norm(u - u_r) / np.linalg.norm(u_r))
+    print(f"steady ddc96: fp64 {n64} steps; fp32 {n32} steps (status {st32}, res {r32.max():.1e}, "
+          f"relL2 {e32:.1e}) + fp64 finish {nfin} steps -> relL2 {e:.1e}", flush=True)
+    assert stfin == lb.LB_OK
+    assert e32 < 1e-4
+    assert e < 1e-6
