@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--mode", choices=["bench", "pmc", "copy"], default="bench",
+                    help="pmc: only the timed workload's step kernel (for counter runs); "
+                         "copy: a plain 1 GiB device copy to calibrate the byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -116,7 +119,22 @@ def main():
     from paper_2101_03055_amd import lb, workloads as W
 
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 5}), flush=True)
+        return
     wl, phi0, u0, p0 = W.chemotaxis_plume()
+    if args.mode == "pmc":
+        solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
+        solver.step(200)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_steps": 200, "bytes_per_launch": bytes_per_lu(2, "f32", 1) * wl["nx"] * wl["ny"]}),
+              flush=True)
+        return
     N = wl["nx"] * wl["ny"]
     solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
     n_src = 1

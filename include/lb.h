@@ -184,6 +184,55 @@ lb_status lb_set_tile(lb_handle* h, int32_t tile_x, int32_t tile_y);
 /* Releases the handle (never the workspace).  NULL is accepted. */
 lb_status lb_free(lb_handle* h);
 
+/* ---- batched parameter sweep ------------------------------------------------
+ * count independent cavities of uneven size (each its own lb_params: grid,
+ * tau_f, D, forces, walls, boundary kinds) advanced together: every time step
+ * is ONE launch over a list of tiles of all running cavities, each workgroup
+ * reading its cavity's parameter record from device memory.  All cavities
+ * must share m, model, storage, collision and r_kind.  Residuals are reduced
+ * per cavity (FP64, deterministic); converged, diverged or capped cavities are
+ * retired from the tile list and keep their final state.
+ * Per-cavity status: 0 running, 1 converged, 2 diverged (non-finite), 3 step cap. */
+typedef struct lbb_handle lbb_handle;
+
+/* Workspace bytes for the batch (validates every record). */
+lb_status lbb_workspace_bytes(const lb_params* params, int32_t count, size_t* bytes);
+
+/* Initialises every cavity at equilibrium of its host fields phi0[c] ([m][ny][nx]),
+ * u0[c] ([2][ny][nx]) and p0[c] ([ny][nx]; p0 or p0[c] may be NULL).  Synchronises. */
+lb_status lbb_init(const lb_params* params, int32_t count, void* dev_workspace, size_t workspace_bytes,
+                   void* hip_stream, const double* const* phi0, const double* const* u0, const double* const* p0,
+                   lbb_handle** out);
+
+/* Advances every running cavity by n steps (n launches), asynchronously. */
+lb_status lbb_step(lbb_handle* b, int64_t n);
+
+/* Runs until every cavity is retired or max_steps steps were taken: windows of
+ * check_every steps (rounded up to even) followed by the per-cavity residual of
+ * lb_residual; a cavity retires when all its residual components are below tol,
+ * when a field turns non-finite, or at the cap.  Outputs (any may be NULL):
+ * steps_out[count], status_out[count], res_out[count][m + 2].  Synchronises. */
+lb_status lbb_run(lbb_handle* b, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
+                  int32_t* status_out, double* res_out);
+
+/* Fields of cavity i (host arrays as in lb_moments; any may be NULL).  Synchronises. */
+lb_status lbb_moments(lbb_handle* b, int32_t i, double* phi, double* u, double* p);
+
+/* Steps taken by cavity i and its status. */
+lb_status lbb_time(lbb_handle* b, int32_t i, int64_t* steps, int32_t* status);
+
+/* Tile shape of the batched step: one of 32x4, 32x8, 64x2, 64x4, 128x1, 128x2, 256x1. */
+lb_status lbb_set_tile(lbb_handle* b, int32_t tile_x, int32_t tile_y);
+
+/* Autotuner: times trial_steps steps (rounded up to even, plus 2 warm-up steps)
+ * of every supported tile shape on the live batch and keeps the fastest.  The
+ * timed steps are real steps of every running cavity (counted in their step
+ * totals; results do not depend on the tile shape).  Outputs may be NULL. */
+lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y, double* us_per_step);
+
+/* Releases the batch handle (never the workspace).  NULL is accepted. */
+lb_status lbb_free(lbb_handle* b);
+
 /* Thread-local text of the last error, "" if none. */
 const char* lb_last_error(void);
 

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lb_internal.h"
 
@@ -590,6 +591,366 @@ lb_status lb_set_tile(lb_handle* h, int32_t tile_x, int32_t tile_y) {
 
 lb_status lb_free(lb_handle* h) {
     delete h;
+    return LB_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// batched sweep
+// ============================================================================
+namespace {
+constexpr int kTileCand[][2] = {{32, 4}, {32, 8}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
+constexpr int kStatusRunning = 0, kStatusConverged = 1, kStatusDiverged = 2, kStatusCap = 3;
+}  // namespace
+
+struct lbb_handle {
+    int count;
+    lb_params p0;                    // shared template fields (m, model, storage, collision)
+    std::vector<lb_params> p;
+    std::vector<Layout> L;           // absolute offsets from ws
+    std::vector<KParams<double>> kd;
+    std::vector<KParams<float>> kf;
+    std::vector<CavRec> cav;
+    void* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    size_t kp_off, cav_off, tiles_off, ranges_off, part_off, out_off, stage_off, max_tiles;
+    std::vector<int> status, parity, has_snap;
+    std::vector<int64_t> steps;
+    int cur_parity;
+    int64_t t;
+    Launch lc;
+    std::vector<int2> tiles;
+    std::vector<int4> ranges;
+    std::vector<double> out;
+};
+
+namespace {
+bool same_template(const lb_params& a, const lb_params& b) {
+    return a.m == b.m && a.model == b.model && a.storage == b.storage && a.collision == b.collision &&
+           a.r_kind == b.r_kind;
+}
+
+size_t batch_max_tiles(const lb_params* params, int count) {
+    size_t best = 0;
+    for (const auto& tc : kTileCand) {
+        size_t t = 0;
+        for (int c = 0; c < count; ++c)
+            t += (size_t)((params[c].nx + tc[0] - 1) / tc[0]) * (size_t)((params[c].ny + tc[1] - 1) / tc[1]);
+        best = std::max(best, t);
+    }
+    return best;
+}
+
+// workspace plan: shared arrays first, then each cavity's own region
+size_t batch_plan(const lb_params* params, int count, lbb_handle* b) {
+    size_t N_max = 0;
+    for (int c = 0; c < count; ++c) N_max = std::max(N_max, (size_t)params[c].nx * params[c].ny);
+    const size_t maxt = batch_max_tiles(params, count);
+    const size_t kpb = params[0].storage == LB_STORE_F64 ? sizeof(KParams<double>) : sizeof(KParams<float>);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = round_up(off + bytes, 256);
+        return o;
+    };
+    const size_t kp_off = take(kpb * count), cav_off = take(sizeof(CavRec) * count);
+    const size_t tiles_off = take(sizeof(int2) * maxt), ranges_off = take(sizeof(int4) * count);
+    const size_t part_off = take(sizeof(double) * kRedWidth * maxt), out_off = take(sizeof(double) * 64 * count);
+    const size_t stage_off = take(sizeof(double) * (params[0].m + 3) * N_max);
+    if (b) {
+        b->kp_off = kp_off; b->cav_off = cav_off; b->tiles_off = tiles_off; b->ranges_off = ranges_off;
+        b->part_off = part_off; b->out_off = out_off; b->stage_off = stage_off; b->max_tiles = maxt;
+    }
+    for (int c = 0; c < count; ++c) {
+        Layout Lc = make_layout(params[c]);
+        const size_t base = off;
+        const size_t own = Lc.stage_off;  // populations, S_old and snapshot precede the staging area
+        if (b) {
+            Lc.pop_off += base;
+            Lc.sold_off += base;
+            Lc.snap_off += base;
+            Lc.stage_off = stage_off;
+            Lc.part_off = part_off;
+            Lc.res_off = out_off;
+            b->L.push_back(Lc);
+        }
+        off = round_up(base + own, 4096);
+    }
+    return off;
+}
+
+void batch_build_tiles(lbb_handle* b) {
+    b->tiles.clear();
+    b->ranges.clear();
+    for (int c = 0; c < b->count; ++c) {
+        if (b->status[c] != kStatusRunning) continue;
+        const int tx = (b->p[c].nx + b->lc.tile_x - 1) / b->lc.tile_x;
+        const int ty = (b->p[c].ny + b->lc.tile_y - 1) / b->lc.tile_y;
+        b->cav[c].tiles_x = tx;
+        b->cav[c].tiles_y = ty;
+        b->ranges.push_back(int4{c, (int)b->tiles.size(), tx * ty, 0});
+        for (int k = 0; k < tx * ty; ++k) b->tiles.push_back(int2{c, k});
+    }
+}
+
+lb_status batch_upload(lbb_handle* b) {
+    char* w = static_cast<char*>(b->ws);
+    HIPCHK(hipMemcpyAsync(w + b->cav_off, b->cav.data(), sizeof(CavRec) * b->count, hipMemcpyHostToDevice, b->stream));
+    if (!b->tiles.empty())
+        HIPCHK(hipMemcpyAsync(w + b->tiles_off, b->tiles.data(), sizeof(int2) * b->tiles.size(), hipMemcpyHostToDevice,
+                              b->stream));
+    if (!b->ranges.empty())
+        HIPCHK(hipMemcpyAsync(w + b->ranges_off, b->ranges.data(), sizeof(int4) * b->ranges.size(),
+                              hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));  // host vectors may change after return
+    return LB_OK;
+}
+
+const void* batch_kparams(lbb_handle* b) { return static_cast<char*>(b->ws) + b->kp_off; }
+
+lb_status batch_reduce(lbb_handle* b, int mode) {
+    char* w = static_cast<char*>(b->ws);
+    hipError_t e = launch_breduce(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
+                                  (const int2*)(w + b->tiles_off), (int)b->tiles.size(),
+                                  (const int4*)(w + b->ranges_off), (int)b->ranges.size(), b->cur_parity != 0, b->lc,
+                                  mode, (double*)(w + b->part_off), (double*)(w + b->out_off), b->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "batched reduction: %s", hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(b->out.data(), w + b->out_off, sizeof(double) * 64 * b->count, hipMemcpyDeviceToHost,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return LB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lb_status lbb_workspace_bytes(const lb_params* params, int32_t count, size_t* bytes) {
+    if (!params || count < 1 || !bytes) return fail(LB_EINVAL, "params, count >= 1 and bytes required");
+    for (int c = 0; c < count; ++c) {
+        lb_status st = validate(&params[c]);
+        if (st != LB_OK) return fail(st, "cavity %d: %s", c, g_err.c_str());
+        if (!same_template(params[0], params[c]))
+            return fail(LB_EINVAL, "cavity %d: m, model, storage, collision and r_kind must match cavity 0", c);
+    }
+    *bytes = batch_plan(params, count, nullptr);
+    return LB_OK;
+}
+
+lb_status lbb_init(const lb_params* params, int32_t count, void* dev_workspace, size_t workspace_bytes,
+                   void* hip_stream, const double* const* phi0, const double* const* u0, const double* const* p0,
+                   lbb_handle** out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    lb_status st = lbb_workspace_bytes(params, count, &need);
+    if (st != LB_OK) return st;
+    if (!dev_workspace || reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return fail(LB_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (workspace_bytes < need) return fail(LB_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+    if (!phi0 || !u0) return fail(LB_EINVAL, "phi0 and u0 are required");
+    for (int c = 0; c < count; ++c) {
+        const size_t N = (size_t)params[c].nx * params[c].ny;
+        if (!phi0[c] || !u0[c]) return fail(LB_EINVAL, "cavity %d: phi0 and u0 are required", c);
+        if (!finite_all(phi0[c], params[c].m * N) || !finite_all(u0[c], 2 * N) || (p0 && p0[c] && !finite_all(p0[c], N)))
+            return fail(LB_ENONFINITE, "cavity %d: initial fields contain non-finite values", c);
+    }
+    lbb_handle* b = new (std::nothrow) lbb_handle();
+    if (!b) return fail(LB_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->p0 = params[0];
+    b->p.assign(params, params + count);
+    b->ws = dev_workspace;
+    b->ws_bytes = workspace_bytes;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    batch_plan(params, count, b);
+    b->kd.resize(count);
+    b->kf.resize(count);
+    b->cav.resize(count);
+    b->status.assign(count, kStatusRunning);
+    b->parity.assign(count, 0);
+    b->has_snap.assign(count, 0);
+    b->steps.assign(count, 0);
+    b->out.assign((size_t)64 * count, 0.0);
+    b->cur_parity = 0;
+    b->t = 0;
+    b->lc = Launch{64, 4};
+    char* w = static_cast<char*>(b->ws);
+    for (int c = 0; c < count; ++c) {
+        fill_kparams(b->p[c], b->L[c], b->kd[c]);
+        fill_kparams(b->p[c], b->L[c], b->kf[c]);
+        b->cav[c] = CavRec{(long long)b->L[c].pop_off, (long long)b->L[c].sold_off, (long long)b->L[c].snap_off, 1, 1};
+    }
+    hipError_t e = b->p0.storage == LB_STORE_F64
+                       ? hipMemcpyAsync(w + b->kp_off, b->kd.data(), sizeof(KParams<double>) * count,
+                                        hipMemcpyHostToDevice, b->stream)
+                       : hipMemcpyAsync(w + b->kp_off, b->kf.data(), sizeof(KParams<float>) * count,
+                                        hipMemcpyHostToDevice, b->stream);
+    for (int c = 0; c < count && e == hipSuccess; ++c) {
+        const size_t N = b->L[c].N, m = (size_t)b->p[c].m;
+        double* stage = (double*)(w + b->stage_off);
+        e = hipMemcpyAsync(stage, phi0[c], m * N * 8, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(stage + m * N, u0[c], 2 * N * 8, hipMemcpyHostToDevice, b->stream);
+        const bool hp = p0 && p0[c];
+        if (e == hipSuccess && hp) e = hipMemcpyAsync(stage + (m + 2) * N, p0[c], N * 8, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = launch_init(b->p[c], b->L[c], b->ws, b->kd[c], b->kf[c], hp ? 1 : 0, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // the staging area is reused
+    }
+    if (e != hipSuccess) {
+        delete b;
+        return fail(LB_EDEVICE, "lbb_init: %s", hipGetErrorString(e));
+    }
+    batch_build_tiles(b);
+    st = batch_upload(b);
+    if (st != LB_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return LB_OK;
+}
+
+lb_status lbb_step(lbb_handle* b, int64_t n) {
+    if (!b) return fail(LB_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LB_EINVAL, "n < 0");
+    char* w = static_cast<char*>(b->ws);
+    for (int64_t s = 0; s < n; ++s) {
+        hipError_t e = launch_bstep(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
+                                    (const int2*)(w + b->tiles_off), (int)b->tiles.size(), b->cur_parity != 0, b->lc,
+                                    b->t, b->stream);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_step: %s", hipGetErrorString(e));
+        b->cur_parity ^= 1;
+        b->t += 1;
+    }
+    for (int c = 0; c < b->count; ++c)
+        if (b->status[c] == kStatusRunning) {
+            b->steps[c] += n;
+            b->parity[c] = b->cur_parity;
+        }
+    return LB_OK;
+}
+
+lb_status lbb_run(lbb_handle* b, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
+                  int32_t* status_out, double* res_out) {
+    if (!b) return fail(LB_EINVAL, "handle is NULL");
+    if (!(tol > 0.0) || check_every < 1 || max_steps < 0) return fail(LB_EINVAL, "tol > 0, check_every >= 1 required");
+    check_every += check_every & 1;  // even windows keep every running cavity at the same AA parity
+    const int Q = b->p0.m + 2;
+    lb_status st = batch_reduce(b, 1);  // snapshots of every running cavity
+    if (st != LB_OK) return st;
+    for (int c = 0; c < b->count; ++c)
+        if (b->status[c] == kStatusRunning) b->has_snap[c] = 1;
+    int64_t done = 0;
+    while (!b->tiles.empty() && done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        st = lbb_step(b, k);
+        if (st != LB_OK) return st;
+        done += k;
+        st = batch_reduce(b, 0);
+        if (st != LB_OK) return st;
+        bool changed = false;
+        for (int c = 0; c < b->count; ++c) {
+            if (b->status[c] != kStatusRunning) continue;
+            const double* o = &b->out[(size_t)64 * c];
+            double r = 0.0;
+            for (int q = 0; q < Q; ++q) r = std::max(r, o[2 * Q + 1 + q]);
+            if (o[2 * Q] != 0.0) {
+                b->status[c] = kStatusDiverged;
+                changed = true;
+            } else if (k == check_every && r < tol) {
+                b->status[c] = kStatusConverged;
+                changed = true;
+            } else if (done >= max_steps) {
+                b->status[c] = kStatusCap;
+                changed = true;
+            }
+        }
+        if (changed) {
+            batch_build_tiles(b);
+            st = batch_upload(b);
+            if (st != LB_OK) return st;
+        }
+    }
+    for (int c = 0; c < b->count; ++c) {
+        if (steps_out) steps_out[c] = b->steps[c];
+        if (status_out) status_out[c] = b->status[c];
+        if (res_out)
+            for (int q = 0; q < Q; ++q) res_out[(size_t)c * Q + q] = b->out[(size_t)64 * c + 2 * Q + 1 + q];
+    }
+    return LB_OK;
+}
+
+lb_status lbb_moments(lbb_handle* b, int32_t i, double* phi, double* u, double* p) {
+    if (!b || i < 0 || i >= b->count) return fail(LB_EINVAL, "bad handle or cavity index");
+    const Layout& L = b->L[i];
+    const size_t N = L.N, m = (size_t)b->p[i].m;
+    double* stage = (double*)(static_cast<char*>(b->ws) + b->stage_off);
+    hipError_t e = launch_moments(b->p[i], L, b->ws, b->kd[i], b->kf[i], b->parity[i] != 0, stage, stage + m * N,
+                                  stage + (m + 2) * N, b->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_moments: %s", hipGetErrorString(e));
+    if (phi) HIPCHK(hipMemcpyAsync(phi, stage, m * N * 8, hipMemcpyDeviceToHost, b->stream));
+    if (u) HIPCHK(hipMemcpyAsync(u, stage + m * N, 2 * N * 8, hipMemcpyDeviceToHost, b->stream));
+    if (p) HIPCHK(hipMemcpyAsync(p, stage + (m + 2) * N, N * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return LB_OK;
+}
+
+lb_status lbb_set_tile(lbb_handle* b, int32_t tile_x, int32_t tile_y) {
+    if (!b) return fail(LB_EINVAL, "handle is NULL");
+    bool ok = false;
+    for (const auto& tc : kTileCand) ok |= (tc[0] == tile_x && tc[1] == tile_y);
+    if (!ok) return fail(LB_EINVAL, "tile %d x %d is not one of the supported batch tiles", tile_x, tile_y);
+    b->lc = Launch{tile_x, tile_y};
+    batch_build_tiles(b);
+    return batch_upload(b);
+}
+
+lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y, double* us_per_step) {
+    if (!b) return fail(LB_EINVAL, "handle is NULL");
+    if (trial_steps < 2) trial_steps = 2;
+    trial_steps += trial_steps & 1;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    Launch best_lc = b->lc;
+    for (const auto& tc : kTileCand) {
+        lb_status st = lbb_set_tile(b, tc[0], tc[1]);
+        if (st != LB_OK) return st;
+        st = lbb_step(b, 2);  // warm-up: first launch of this shape
+        if (st != LB_OK) return st;
+        HIPCHK(hipEventRecord(e0, b->stream));
+        st = lbb_step(b, trial_steps);
+        if (st != LB_OK) return st;
+        HIPCHK(hipEventRecord(e1, b->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_lc = b->lc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    lb_status st = lbb_set_tile(b, best_lc.tile_x, best_lc.tile_y);
+    if (st != LB_OK) return st;
+    if (tile_x) *tile_x = best_lc.tile_x;
+    if (tile_y) *tile_y = best_lc.tile_y;
+    if (us_per_step) *us_per_step = 1e3 * best / trial_steps;
+    return LB_OK;
+}
+
+lb_status lbb_time(lbb_handle* b, int32_t i, int64_t* steps, int32_t* status) {
+    if (!b || i < 0 || i >= b->count) return fail(LB_EINVAL, "bad handle or cavity index");
+    if (steps) *steps = b->steps[i];
+    if (status) *status = b->status[i];
+    return LB_OK;
+}
+
+lb_status lbb_free(lbb_handle* b) {
+    delete b;
     return LB_OK;
 }
 

@@ -1,0 +1,181 @@
+// lb_batch.hip -- batched parameter sweep: many independent cavities of
+// uneven size advanced by one launch per time step.
+//
+// The grid is a list of tiles (cavity, tile index) over every cavity still
+// running; each workgroup updates one tile of one cavity with the same fused
+// AA-pattern update as the single-domain kernel, reading that cavity's own
+// parameter record (relaxation matrix, forces, walls, grid size) from device
+// memory.  Tiles of a cavity are contiguous in the list and the XCD-aware
+// remap keeps them on one XCD.  Residuals are reduced per tile and then per
+// cavity in a fixed order (deterministic FP64), so converged or diverged
+// cavities can be retired from the list between launches.
+#include <hip/hip_runtime.h>
+
+#include "lb_device.h"
+
+namespace lbk {
+
+template <class S, int M, int MODEL, int COLL, bool ODD>
+__global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>* __restrict__ kps,
+                                               const CavRec* __restrict__ cav, const int2* __restrict__ tiles,
+                                               int ntiles, char* __restrict__ ws, int tile_x, int tile_y,
+                                               uint32_t salt) {
+    using T = typename St<S>::T;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    if (b >= ntiles) return;
+    const int2 t = tiles[b];
+    const KParams<T>& kp = kps[t.x];
+    const CavRec cr = cav[t.x];
+    const int bx = t.y % cr.tiles_x, by = t.y / cr.tiles_x;
+    const int x = bx * tile_x + (int)(threadIdx.x % tile_x);
+    const int y = by * tile_y + (int)(threadIdx.x / tile_x);
+    if (x >= kp.nx || y >= kp.ny) return;
+    const long long N = (long long)kp.nx * kp.ny;
+    const long long n = (long long)y * kp.nx + x;
+    S* pop = reinterpret_cast<S*>(ws + cr.pop_off);
+    T* sold = reinterpret_cast<T*>(ws + cr.sold_off);
+
+    T h[9], f[M][5], Sold[M], Snew[M];
+    gather<S, M, ODD>(kp, pop, x, y, h, f);
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        Sold[a] = T(0);
+        if (kp.src_mask >> a & 1) Sold[a] = sold[(long long)(k++) * N + n];
+    }
+    collide<T, M, MODEL, COLL>(kp, h, f, Sold, Snew);
+    k = 0;
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+        if (kp.src_mask >> a & 1) sold[(long long)(k++) * N + n] = Snew[a];
+    scatter<S, M, ODD>(kp, pop, x, y, h, f, salt);
+}
+
+template <class S, int M, bool ODD>
+__global__ __launch_bounds__(256) void k_breduce(const KParams<typename St<S>::T>* __restrict__ kps,
+                                                 const CavRec* __restrict__ cav, const int2* __restrict__ tiles,
+                                                 int ntiles, char* __restrict__ ws, int tile_x, int tile_y,
+                                                 double* __restrict__ part, int mode) {
+    using T = typename St<S>::T;
+    constexpr int Q = M + 2;
+    double acc[2 * Q + 1];
+#pragma unroll
+    for (int k = 0; k < 2 * Q + 1; ++k) acc[k] = 0.0;
+    const int2 t = tiles[blockIdx.x];
+    const KParams<T>& kp = kps[t.x];
+    const CavRec cr = cav[t.x];
+    const int bx = t.y % cr.tiles_x, by = t.y / cr.tiles_x;
+    const int x = bx * tile_x + (int)(threadIdx.x % tile_x);
+    const int y = by * tile_y + (int)(threadIdx.x / tile_x);
+    if (x < kp.nx && y < kp.ny) {
+        const long long N = (long long)kp.nx * kp.ny;
+        const long long n = (long long)y * kp.nx + x;
+        const S* pop = reinterpret_cast<const S*>(ws + cr.pop_off);
+        double* snap = reinterpret_cast<double*>(ws + cr.snap_off);
+        T h[9], f[M][5];
+        gather<S, M, ODD>(kp, pop, x, y, h, f);
+        Macro<T, M> mc;
+        macro<T, M>(kp, h, f, mc);
+        double q[Q];
+        q[0] = double(mc.u[0]);
+        q[1] = double(mc.u[1]);
+#pragma unroll
+        for (int a = 0; a < M; ++a) q[2 + a] = double(kp.phi_ref[a]) + double(mc.phid[a]);
+        bool bad = false;
+        if (mode == 2) {
+#pragma unroll
+            for (int a = 0; a < M; ++a) acc[a] = q[2 + a];
+            double hs = double(kp.h0_shift);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) hs += double(h[i]);
+            acc[M] = hs;
+            bad = !isfinite(hs);
+#pragma unroll
+            for (int a = 0; a < M; ++a) bad |= !isfinite(q[2 + a]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                acc[k] = fabs(q[k] - snap[(long long)k * N + n]);
+                acc[Q + k] = fabs(q[k]);
+                snap[(long long)k * N + n] = q[k];
+                bad |= !isfinite(q[k]);
+            }
+        }
+        acc[2 * Q] = bad ? 1.0 : 0.0;
+    }
+    block_sum<2 * Q + 1>(acc, part + (long long)blockIdx.x * kRedWidth);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_bfinal(const int4* __restrict__ ranges, const double* __restrict__ part,
+                                                double* __restrict__ out, int mode) {
+    constexpr int NV = 2 * Q + 1;
+    __shared__ double tot[NV];
+    const int4 r = ranges[blockIdx.x];
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < r.z; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += part[(long long)(r.y + b) * kRedWidth + k];
+    block_sum<NV>(acc, tot);
+    __syncthreads();
+    double* o = out + (long long)r.x * 64;
+    if (threadIdx.x < NV) o[threadIdx.x] = tot[threadIdx.x];
+    if (mode == 0 && threadIdx.x < Q) {
+        const double d = tot[threadIdx.x], s = tot[Q + threadIdx.x];
+        o[NV + threadIdx.x] = s > 0.0 ? d / s : (d == 0.0 ? 0.0 : __builtin_huge_val());
+    }
+}
+
+hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
+                        int ntiles, bool odd, Launch lc, int64_t step, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    const uint32_t salt = mix32((uint32_t)step ^ (uint32_t)(step >> 32) * 0x632be5abu);
+    const dim3 grid((unsigned)ntiles), block((unsigned)(lc.tile_x * lc.tile_y));
+    return dispatch(p0, [&]<class S, int M, int MODEL>() -> hipError_t {
+        using T = typename St<S>::T;
+        const KParams<T>* kp = static_cast<const KParams<T>*>(kparams);
+        char* w = static_cast<char*>(ws);
+        if (p0.collision == LB_COLL_MRT) {
+            if (odd)
+                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_MRT, true>), grid, block, 0, s, kp, cav, tiles, ntiles,
+                                   w, lc.tile_x, lc.tile_y, salt);
+            else
+                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_MRT, false>), grid, block, 0, s, kp, cav, tiles,
+                                   ntiles, w, lc.tile_x, lc.tile_y, salt);
+        } else {
+            if (odd)
+                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_BGK, true>), grid, block, 0, s, kp, cav, tiles, ntiles,
+                                   w, lc.tile_x, lc.tile_y, salt);
+            else
+                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_BGK, false>), grid, block, 0, s, kp, cav, tiles,
+                                   ntiles, w, lc.tile_x, lc.tile_y, salt);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_breduce(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
+                          int ntiles, const int4* ranges, int nranges, bool odd, Launch lc, int mode, double* part,
+                          double* out, hipStream_t s) {
+    if (ntiles <= 0 || nranges <= 0) return hipSuccess;
+    const dim3 grid((unsigned)ntiles), block((unsigned)(lc.tile_x * lc.tile_y));
+    return dispatch(p0, [&]<class S, int M, int MODEL>() -> hipError_t {
+        using T = typename St<S>::T;
+        const KParams<T>* kp = static_cast<const KParams<T>*>(kparams);
+        char* w = static_cast<char*>(ws);
+        if (odd)
+            hipLaunchKernelGGL((k_breduce<S, M, true>), grid, block, 0, s, kp, cav, tiles, ntiles, w, lc.tile_x,
+                               lc.tile_y, part, mode);
+        else
+            hipLaunchKernelGGL((k_breduce<S, M, false>), grid, block, 0, s, kp, cav, tiles, ntiles, w, lc.tile_x,
+                               lc.tile_y, part, mode);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_bfinal<M + 2>), dim3((unsigned)nranges), dim3(256), 0, s, ranges, part, out, mode);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace lbk

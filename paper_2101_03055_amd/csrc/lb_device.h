@@ -1,0 +1,535 @@
+// lb_device.h -- device-side building blocks of the fused lattice Boltzmann
+// update (lattices, storage traits, AA-pattern gather/scatter with the wall
+// rules, moments and the collision), shared by the single-domain kernels
+// (lb_kernels.hip) and the batched sweep kernels (lb_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "lb_internal.h"
+
+namespace lbk {
+
+// ---- lattices (Sec. 2: D2Q5 for the scalars, D2Q9 for the fluid) ---------
+__device__ constexpr int CX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int CY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+__device__ constexpr int MIRY9[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};  // c_y -> -c_y
+__device__ constexpr int MIRX9[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};  // c_x -> -c_x
+__device__ constexpr int CX5[5] = {0, 1, 0, -1, 0};
+__device__ constexpr int CY5[5] = {0, 0, 1, 0, -1};
+__device__ constexpr int OPP5[5] = {0, 3, 4, 1, 2};
+
+template <class T>
+__device__ __forceinline__ T w9(int i) {
+    return i == 0 ? T(4) / T(9) : (i < 5 ? T(1) / T(9) : T(1) / T(36));
+}
+template <class T>
+__device__ __forceinline__ T w5(int i) {
+    return i == 0 ? T(1) / T(3) : T(1) / T(6);
+}
+
+// Lallemand-Luo D2Q9 moment basis (rows rho, e, eps, jx, qx, jy, qy, pxx, pxy);
+// rows are orthogonal, so M^-1 = M^T diag(1/|row|^2).
+__device__ constexpr int MM[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},     {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1}, {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},  {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},  {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+__device__ constexpr int MNORM[9] = {9, 36, 36, 6, 12, 6, 12, 4, 4};
+
+// ---- storage traits --------------------------------------------------------
+template <class S>
+struct St;
+template <>
+struct St<double> {
+    using T = double;
+    static constexpr bool scaled = false;
+};
+template <>
+struct St<float> {
+    using T = float;
+    static constexpr bool scaled = false;
+};
+template <>
+struct St<_Float16> {
+    using T = float;
+    static constexpr bool scaled = true;
+};
+
+// FP16 deviations carry one scale for the fluid planes (0..8) and one for
+// the scalar planes; FP32/FP64 are unscaled
+template <class S, class T>
+__device__ __forceinline__ T ld(const S* p, const KParams<T>& kp, bool fluid) {
+    if constexpr (St<S>::scaled)
+        return T(*p) * (fluid ? kp.inv_scale_h : kp.inv_scale);
+    else
+        return T(*p);
+}
+// 32-bit integer mixer (Wellons' "lowbias32"), used as a counter-based
+// generator for stochastic rounding
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// binary16 with stochastic rounding: adding uniform random bits below the 10
+// kept mantissa bits to the magnitude and truncating rounds up with
+// probability equal to the discarded fraction, so increments smaller than
+// half an ulp survive in expectation.  The random bits depend only on the
+// element index and the step (salt), so runs are reproducible.  Values below
+// the binary16 normal range fall back to round-to-nearest.
+__device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t key) {
+    if (!(fabsf(v) >= 6.103515625e-05f) || !(fabsf(v) < 65504.0f)) return _Float16(v);
+    uint32_t b = __float_as_uint(v);
+    b = (b + (mix32(key) & 0x1fffu)) & ~0x1fffu;
+    return _Float16(__uint_as_float(b));
+}
+
+template <class S, class T>
+__device__ __forceinline__ void st(S* base, long long idx, T v, const KParams<T>& kp, bool fluid, uint32_t salt) {
+    if constexpr (St<S>::scaled)
+        base[idx] = to_half_sr(v * (fluid ? kp.scale_h : kp.scale), (uint32_t)idx * 0x9e3779b9u ^ salt);
+    else
+        base[idx] = S(v);
+}
+
+// ---- geometry helpers -------------------------------------------------------
+// wraps c into [0, n) on a periodic axis; returns false when c is outside a
+// non-periodic axis
+__device__ __forceinline__ bool wrap_in(int& c, int n, int periodic) {
+    if (c < 0) {
+        if (!periodic) return false;
+        c += n;
+    } else if (c >= n) {
+        if (!periodic) return false;
+        c -= n;
+    }
+    return true;
+}
+__device__ __forceinline__ int side_x(int c) { return c < 0 ? 0 : 1; }
+__device__ __forceinline__ int side_y(int c) { return c < 0 ? 2 : 3; }
+
+// ---- gather ---------------------------------------------------------------
+// Canonical pre-collision populations of node (x, y).  PULL = false: the own
+// slots (state after an odd step or initialisation).  PULL = true: the state
+// left by an even step, read from the upstream neighbours with the wall rules.
+template <class S, int M, bool PULL, class T>
+__device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict__ pop, int x, int y,
+                                       T h[9], T f[M][5]) {
+    const long long P = kp.plane;
+    const int nx = kp.nx, ny = kp.ny;
+    const long long n = (long long)y * nx + x;
+    if constexpr (!PULL) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = ld(pop + i * P + n, kp, true);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
+        return;
+    } else {
+        const bool interior = (x > 0) & (x < nx - 1) & (y > 0) & (y < ny - 1);
+        if (__all(interior)) {  // wave-uniform choice: no lane pays for both paths
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                h[i] = ld(pop + OPP9[i] * P + n - CY9[i] * nx - CX9[i], kp, true);
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+#pragma unroll
+                for (int i = 0; i < 5; ++i)
+                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + n - CY5[i] * nx - CX5[i], kp, false);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx = x - CX9[i], sy = y - CY9[i];
+            const bool inx = wrap_in(sx, nx, kp.px), iny = wrap_in(sy, ny, kp.py);
+            long long src;
+            int pl;
+            if (inx & iny) {
+                src = (long long)sy * nx + sx;
+                pl = OPP9[i];
+            } else {
+                src = n;  // bounce-back: the node's own reflected value
+                pl = i;
+                if (inx != iny) {
+                    const int side = inx ? side_y(sy) : side_x(sx);
+                    if (kp.fbc[side] == LB_BC_FREESLIP) {
+                        if (!iny) {  // specular across a y-wall: from (x - c_x, y), direction mirrored
+                            int rx = x - CX9[i];
+                            if (wrap_in(rx, nx, kp.px)) {
+                                src = (long long)y * nx + rx;
+                                pl = OPP9[MIRY9[i]];
+                            }
+                        } else {  // across an x-wall: from (x, y - c_y)
+                            int ry = y - CY9[i];
+                            if (wrap_in(ry, ny, kp.py)) {
+                                src = (long long)ry * nx + x;
+                                pl = OPP9[MIRX9[i]];
+                            }
+                        }
+                    }
+                }
+            }
+            h[i] = ld(pop + pl * P + src, kp, true);
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                int sx = x - CX5[i], sy = y - CY5[i];
+                const bool inx = wrap_in(sx, nx, kp.px), iny = wrap_in(sy, ny, kp.py);
+                if (inx & iny) {
+                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + (long long)sy * nx + sx, kp, false);
+                } else {
+                    const int side = inx ? side_y(sy) : side_x(sx);
+                    T v = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
+                    if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
+                    f[a][i] = v;
+                }
+            }
+    }
+}
+
+// ---- scatter ---------------------------------------------------------------
+// PUSH = false: even step, post-collision value of direction i to own slot
+// opp(i).  PUSH = true: odd step, to slot i of x + c_i, or by the wall rules.
+template <class S, int M, bool PUSH, class T>
+__device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ pop, int x, int y,
+                                        const T h[9], const T f[M][5], uint32_t salt) {
+    const long long P = kp.plane;
+    const int nx = kp.nx, ny = kp.ny;
+    const long long n = (long long)y * nx + x;
+    if constexpr (!PUSH) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st(pop, OPP9[i] * P + n, h[i], kp, true, salt);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) st(pop, (9 + 5 * a + OPP5[i]) * P + n, f[a][i], kp, false, salt);
+        return;
+    } else {
+        const bool interior = (x > 0) & (x < nx - 1) & (y > 0) & (y < ny - 1);
+        if (__all(interior)) {  // wave-uniform choice: no lane pays for both paths
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st(pop, i * P + n + CY9[i] * nx + CX9[i], h[i], kp, true, salt);
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+#pragma unroll
+                for (int i = 0; i < 5; ++i)
+                    st(pop, (9 + 5 * a + i) * P + n + CY5[i] * nx + CX5[i], f[a][i], kp, false, salt);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int tx = x + CX9[i], ty = y + CY9[i];
+            const bool inx = wrap_in(tx, nx, kp.px), iny = wrap_in(ty, ny, kp.py);
+            long long dst;
+            int pl;
+            if (inx & iny) {
+                dst = (long long)ty * nx + tx;
+                pl = i;
+            } else {
+                dst = n;  // bounce-back into the node's own opposite slot
+                pl = OPP9[i];
+                if (inx != iny) {
+                    const int side = inx ? side_y(ty) : side_x(tx);
+                    if (kp.fbc[side] == LB_BC_FREESLIP) {
+                        if (!iny) {
+                            int rx = x + CX9[i];
+                            if (wrap_in(rx, nx, kp.px)) {
+                                dst = (long long)y * nx + rx;
+                                pl = MIRY9[i];
+                            }
+                        } else {
+                            int ry = y + CY9[i];
+                            if (wrap_in(ry, ny, kp.py)) {
+                                dst = (long long)ry * nx + x;
+                                pl = MIRX9[i];
+                            }
+                        }
+                    }
+                }
+            }
+            st(pop, pl * P + dst, h[i], kp, true, salt);
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                int tx = x + CX5[i], ty = y + CY5[i];
+                const bool inx = wrap_in(tx, nx, kp.px), iny = wrap_in(ty, ny, kp.py);
+                if (inx & iny) {
+                    st(pop, (9 + 5 * a + i) * P + (long long)ty * nx + tx, f[a][i], kp, false, salt);
+                } else {
+                    const int side = inx ? side_y(ty) : side_x(tx);
+                    T v = f[a][i];
+                    if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
+                    st(pop, (9 + 5 * a + OPP5[i]) * P + n, v, kp, false, salt);
+                }
+            }
+    }
+}
+
+// ---- closures ---------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T cutoff_r(const KParams<T>& kp, T c) {
+    if (kp.r_kind == LB_R_STEP) return c >= kp.cstar ? T(1) : T(0);
+    const T d = c - kp.cstar;
+    return T(0.5) * (T(1) + d / sqrt(d * d + kp.eps * kp.eps));
+}
+
+// Macroscopic quantities of one node (Eq. sum) in deviation form.
+template <class T, int M>
+struct Macro {
+    T phid[M];  // phi - phi_ref
+    T phi[M];
+    T F[2];
+    T u[2];
+    T p;
+};
+
+template <class T, int M>
+__device__ __forceinline__ void macro(const KParams<T>& kp, const T h[9], const T f[M][5], Macro<T, M>& mc) {
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        mc.phid[a] = ((f[a][0] + f[a][1]) + (f[a][2] + f[a][3])) + f[a][4];
+        mc.phi[a] = kp.phi_ref[a] + mc.phid[a];
+    }
+    mc.F[0] = kp.F0[0];
+    mc.F[1] = kp.F0[1];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        mc.F[0] += kp.Fphi[a][0] * mc.phi[a];
+        mc.F[1] += kp.Fphi[a][1] * mc.phi[a];
+    }
+    const T jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    const T jy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+    mc.u[0] = jx + T(0.5) * mc.F[0];
+    mc.u[1] = jy + T(0.5) * mc.F[1];
+    const T s = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
+    const T usq = mc.u[0] * mc.u[0] + mc.u[1] * mc.u[1];
+    // p = cs2/(1 - W0) [sum_{i>0} h_i - W0 u.u/(2 cs2)] = (3/5)(s - (2/3) u.u)
+    mc.p = T(0.6) * (s - (T(2) / T(3)) * usq);
+}
+
+// ---- the node update ------------------------------------------------------
+template <class T, int M, int MODEL, int COLL>
+__device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5], const T Sold[M], T Snew[M]) {
+    Macro<T, M> mc;
+    macro<T, M>(kp, h, f, mc);
+
+    // relaxation matrix, Eq. omega-D with lambda = I: omega = (3 D + I/2)^-1
+    T om[M][M];
+    T S[M];
+    if constexpr (MODEL == LB_MODEL_CHEMOTAXIS) {
+        const T r = cutoff_r(kp, mc.phi[1]);
+        const T a = T(3) * kp.Dc[0] + T(0.5);
+        const T b = T(3) * (kp.Dc[1] - kp.chi * r * mc.phi[0]);
+        const T c = T(3) * kp.Dc[2];
+        const T d = T(3) * kp.Dc[3] + T(0.5);
+        const T idet = T(1) / (a * d - b * c);
+        om[0][0] = d * idet;
+        om[0][1] = -b * idet;
+        om[1][0] = -c * idet;
+        om[1][1] = a * idet;
+        S[0] = T(0);
+        S[1] = -kp.beta * r * mc.phi[0];
+    } else {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+#pragma unroll
+            for (int b = 0; b < M; ++b) om[a][b] = kp.omega[a * M + b];
+            S[a] = T(0);
+            if (kp.src_mask >> a & 1) {
+#pragma unroll
+                for (int b = 0; b < M; ++b) S[a] += kp.K[a * M + b] * mc.phi[b];
+            }
+        }
+    }
+
+    // auxiliary source, Eq. Gi: G_{i,a} = 3 W_i c_i . g_a with
+    // g_a = sum_b (delta_ab - omega_ab/2)(u S_b + phi_b F)
+    T g[M][2];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        g[a][0] = T(0);
+        g[a][1] = T(0);
+#pragma unroll
+        for (int b = 0; b < M; ++b) {
+            const T cf = (a == b ? T(1) : T(0)) - T(0.5) * om[a][b];
+            g[a][0] += cf * (mc.u[0] * S[b] + mc.phi[b] * mc.F[0]);
+            g[a][1] += cf * (mc.u[1] * S[b] + mc.phi[b] * mc.F[1]);
+        }
+    }
+    // source with its time-derivative correction (Eq. source, gamma = 0):
+    // dt S_i + (dt/2)(S_i(t) - S_i(t - dt)) = W_i (3/2 S - 1/2 S_old)
+    T src[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        src[a] = T(1.5) * S[a] - T(0.5) * Sold[a];
+        Snew[a] = S[a];
+    }
+
+    // scalar matrix collision (Eq. evolution12), f^eq of Eq. feq-phi with
+    // lambda = I, vartheta = 0 in deviation form: W_i (phid + 3 phi c.u).
+    // The rest direction takes the remainder, f^eq_0 = phid - sum_{i>0} f^eq_i
+    // (and likewise for W_i S): with rounded weights sum_i W_i != 1, which
+    // would create or destroy mass by the same fraction at every step.
+    T feq[M][5], wsrc[M][5];
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+        const T iso = mc.phid[b] * (T(1) / T(6));
+        const T adv = T(0.5) * mc.phi[b];  // 3 W_i phi for i > 0
+        feq[b][1] = iso + adv * mc.u[0];
+        feq[b][3] = iso - adv * mc.u[0];
+        feq[b][2] = iso + adv * mc.u[1];
+        feq[b][4] = iso - adv * mc.u[1];
+        feq[b][0] = mc.phid[b] - T(4) * iso;
+        const T s6 = src[b] * (T(1) / T(6));
+        wsrc[b][1] = wsrc[b][2] = wsrc[b][3] = wsrc[b][4] = s6;
+        wsrc[b][0] = src[b] - T(4) * s6;
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const T wi = w5<T>(i);
+        T neq[M];
+#pragma unroll
+        for (int b = 0; b < M; ++b) neq[b] = f[b][i] - feq[b][i];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            T coll = T(0);
+#pragma unroll
+            for (int b = 0; b < M; ++b) coll += om[a][b] * neq[b];
+            const T cg = T(CX5[i]) * g[a][0] + T(CY5[i]) * g[a][1];
+            f[a][i] = f[a][i] - coll + wsrc[a][i] + T(3) * wi * cg;
+        }
+    }
+
+    // fluid: h^eq of Eq. heq, F_i of Eq. force with varphi = 0
+    const T usq = mc.u[0] * mc.u[0] + mc.u[1] * mc.u[1];
+    // h^eq_0 = rho0 - sum_{i>0} h^eq_i (Eq. momentNS: sum_i h^eq_i = rho0), which
+    // equals sigma_0 - W_0 u.u/(2 cs2) of Eq. heq without a rounding bias
+    T heq[9], Fi[9];
+    T hsum = T(0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const T wi = w9<T>(i);
+        const T cu = T(CX9[i]) * mc.u[0] + T(CY9[i]) * mc.u[1];
+        heq[i] = wi * (T(3) * mc.p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+        hsum += heq[i];
+    }
+    heq[0] = kp.rho0_eff - hsum;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const T cF = T(CX9[i]) * mc.F[0] + T(CY9[i]) * mc.F[1];
+        Fi[i] = T(3) * w9<T>(i) * cF;
+    }
+    const T w = kp.omega_f;
+    if constexpr (COLL == LB_COLL_BGK) {
+        const T fc = T(1) - T(0.5) * w;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = h[i] - w * (h[i] - heq[i]) + fc * Fi[i];
+    } else {
+        T dm[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            T mne = T(0), mf = T(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if (MM[k][i] != 0) {
+                    mne += T(MM[k][i]) * (h[i] - heq[i]);
+                    mf += T(MM[k][i]) * Fi[i];
+                }
+            }
+            const T s = (k >= 7) ? w : kp.mrt_s[k];
+            dm[k] = (-s * mne + (T(1) - T(0.5) * s) * mf) / T(MNORM[k]);
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                if (MM[k][i] != 0) acc += T(MM[k][i]) * dm[k];
+            h[i] = h[i] + acc;
+        }
+    }
+}
+
+// ---- XCD-aware block placement ----------------------------------------------
+// Workgroups are dealt round-robin to the 8 XCDs.  Remap so that each XCD
+// processes one contiguous run of tiles: neighbouring tiles (which share
+// cache lines of the shifted odd-step accesses) then sit in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int k = b & 7, j = b >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
+// deterministic block reduction of NV doubles (wave64 shuffles, then LDS)
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double* __restrict__ dst) {
+    __shared__ double red[4][NV];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) red[wid][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x, nw = (int)(blockDim.x + 63) >> 6;  // 1..4 wavefronts
+        double t = red[0][k];
+        for (int w = 1; w < nw; ++w) t += red[w][k];
+        dst[k] = t;
+    }
+}
+
+// ---- launch helpers ----------------------------------------------------------
+static inline void* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+template <class S>
+static const KParams<typename St<S>::T>& kpar(const KParams<double>& kd, const KParams<float>& kf) {
+    if constexpr (std::is_same<typename St<S>::T, double>::value)
+        return kd;
+    else
+        return kf;
+}
+
+// calls fn.template operator()<S, M, MODEL>() for the runtime storage/m/model
+template <class Fn>
+static hipError_t dispatch(const lb_params& p, Fn&& fn) {
+    auto by_m = [&](auto sTag) -> hipError_t {
+        using S = decltype(sTag);
+        if (p.model == LB_MODEL_CHEMOTAXIS) return fn.template operator()<S, 2, LB_MODEL_CHEMOTAXIS>();
+        switch (p.m) {
+            case 1: return fn.template operator()<S, 1, LB_MODEL_LINEAR>();
+            case 2: return fn.template operator()<S, 2, LB_MODEL_LINEAR>();
+            case 3: return fn.template operator()<S, 3, LB_MODEL_LINEAR>();
+            case 4: return fn.template operator()<S, 4, LB_MODEL_LINEAR>();
+        }
+        return hipErrorInvalidValue;
+    };
+    switch (p.storage) {
+        case LB_STORE_F64: return by_m(double{});
+        case LB_STORE_F32: return by_m(float{});
+        case LB_STORE_F16: return by_m(_Float16{});
+    }
+    return hipErrorInvalidValue;
+}
+
+static inline unsigned blocks_for(size_t N) { return (unsigned)((N + 255) / 256); }
+
+}  // namespace lbk

@@ -76,4 +76,22 @@ hipError_t launch_copy_sold(const lb_params& ps, const Layout& Ls, void* wss, co
 hipError_t launch_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                          const KParams<float>& kf, bool odd, int mode, hipStream_t s);
 
+// ---- batched sweep ---------------------------------------------------------
+// Per-cavity record visible to the batched kernels (offsets in bytes from the
+// workspace base).
+struct CavRec {
+    long long pop_off, sold_off, snap_off;
+    int tiles_x, tiles_y;
+};
+
+// one step of every listed tile: tiles[k] = (cavity, tile index in the cavity)
+hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
+                        int ntiles, bool odd, Launch lc, int64_t step, hipStream_t s);
+// per-tile partial sums (mode 0 residual + snapshot, 1 snapshot only, 2 mass),
+// then per-cavity totals: ranges[k] = (cavity, first tile, tile count, 0);
+// out[cavity][3 (m + 2) + 1]: diff sums, norms, non-finite count, residuals
+hipError_t launch_breduce(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
+                          int ntiles, const int4* ranges, int nranges, bool odd, Launch lc, int mode, double* part,
+                          double* out, hipStream_t s);
+
 }  // namespace lbk

@@ -90,6 +90,22 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = st
+        pvp = C.POINTER(C.c_void_p)
+        bsig = {
+            "lbb_workspace_bytes": [pp, C.c_int32, C.POINTER(sz)],
+            "lbb_init": [pp, C.c_int32, vp, sz, vp, pvp, pvp, pvp, C.POINTER(vp)],
+            "lbb_step": [vp, i64],
+            "lbb_run": [vp, C.c_double, i64, i64, vp, vp, vp],
+            "lbb_moments": [vp, C.c_int32, vp, vp, vp],
+            "lbb_time": [vp, C.c_int32, C.POINTER(i64), C.POINTER(C.c_int32)],
+            "lbb_set_tile": [vp, C.c_int32, C.c_int32],
+            "lbb_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
+            "lbb_free": [vp],
+        }
+        for name, args in bsig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = st
         L.lb_last_error.restype = C.c_char_p
         L.lb_params_bytes.restype = sz
         if L.lb_params_bytes() != C.sizeof(lb_params):
@@ -298,6 +314,139 @@ class Solver:
     def close(self):
         if getattr(self, "handle", None) is not None:
             lb_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batched sweep -------------------------------------------------------------
+LBB_RUNNING, LBB_CONVERGED, LBB_DIVERGED, LBB_CAP = 0, 1, 2, 3
+
+
+def _params_array(plist):
+    arr = (lb_params * len(plist))()
+    for k, q in enumerate(plist):
+        arr[k] = q
+    return arr
+
+
+def lbb_workspace_bytes(plist) -> int:
+    arr = _params_array(plist)
+    n = C.c_size_t()
+    _check(lib().lbb_workspace_bytes(arr, len(plist), C.byref(n)))
+    return n.value
+
+
+def lbb_init(plist, workspace_ptr: int, workspace_bytes: int, stream: int, phi0s, u0s, p0s=None):
+    arr = _params_array(plist)
+    cnt = len(plist)
+    keep = []
+
+    def ptrs(arrays, shapes):
+        out = (C.c_void_p * cnt)()
+        for k in range(cnt):
+            if arrays is None or arrays[k] is None:
+                out[k] = None
+                continue
+            a = _host(arrays[k], shapes[k])
+            keep.append(a)
+            out[k] = a.ctypes.data
+        return out
+
+    sh_phi = [(q.m, q.ny, q.nx) for q in plist]
+    sh_u = [(2, q.ny, q.nx) for q in plist]
+    sh_p = [(q.ny, q.nx) for q in plist]
+    h = C.c_void_p()
+    _check(lib().lbb_init(arr, cnt, C.c_void_p(workspace_ptr), workspace_bytes, C.c_void_p(stream),
+                          ptrs(phi0s, sh_phi), ptrs(u0s, sh_u), None if p0s is None else ptrs(p0s, sh_p),
+                          C.byref(h)))
+    return h
+
+
+def lbb_step(b, n: int):
+    _check(lib().lbb_step(b, int(n)))
+
+
+def lbb_run(b, count: int, m: int, tol: float, check_every: int, max_steps: int):
+    steps = np.zeros(count, dtype=np.int64)
+    status = np.zeros(count, dtype=np.int32)
+    res = np.zeros((count, m + 2))
+    _check(lib().lbb_run(b, float(tol), int(check_every), int(max_steps), steps.ctypes.data, status.ctypes.data,
+                         res.ctypes.data))
+    return steps, status, res
+
+
+def lbb_moments(b, i: int, m: int, ny: int, nx: int):
+    phi = np.empty((m, ny, nx))
+    u = np.empty((2, ny, nx))
+    pr = np.empty((ny, nx))
+    _check(lib().lbb_moments(b, int(i), phi.ctypes.data, u.ctypes.data, pr.ctypes.data))
+    return phi, u, pr
+
+
+def lbb_time(b, i: int):
+    s = C.c_int64()
+    st = C.c_int32()
+    _check(lib().lbb_time(b, int(i), C.byref(s), C.byref(st)))
+    return s.value, st.value
+
+
+def lbb_set_tile(b, tile_x: int, tile_y: int):
+    _check(lib().lbb_set_tile(b, int(tile_x), int(tile_y)))
+
+
+def lbb_autotune(b, trial_steps: int = 20):
+    tx, ty, us = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().lbb_autotune(b, int(trial_steps), C.byref(tx), C.byref(ty), C.byref(us)))
+    return tx.value, ty.value, us.value
+
+
+def lbb_free(b):
+    lib().lbb_free(b)
+
+
+class Batch:
+    """A batch handle plus its torch workspace."""
+
+    def __init__(self, cases, storage: str = "f64", phi_ref=None, fp16_scale: float = 1.0,
+                 fp16_scale_h=None, device: str = "cuda:0", stream=None):
+        """cases: list of (workload dict, phi0, u0, p0)."""
+        import torch
+
+        lib()
+        self.wls = [c[0] for c in cases]
+        self.count = len(cases)
+        self.m = self.wls[0]["m"]
+        self.params = [params_from_workload(wl, storage, phi_ref, fp16_scale, fp16_scale_h) for wl in self.wls]
+        nbytes = lbb_workspace_bytes(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        self.handle = lbb_init(self.params, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream,
+                               [c[1] for c in cases], [c[2] for c in cases], [c[3] for c in cases])
+
+    def step(self, n: int):
+        lbb_step(self.handle, n)
+
+    def run(self, tol=1e-8, check_every=1000, max_steps=5_000_000):
+        return lbb_run(self.handle, self.count, self.m, tol, check_every, max_steps)
+
+    def moments(self, i: int):
+        wl = self.wls[i]
+        return lbb_moments(self.handle, i, self.m, wl["ny"], wl["nx"])
+
+    def time(self, i: int):
+        return lbb_time(self.handle, i)
+
+    def autotune(self, trial_steps: int = 20):
+        return lbb_autotune(self.handle, trial_steps)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lbb_free(self.handle)
             self.handle = None
 
     def __del__(self):
