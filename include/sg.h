@@ -1,0 +1,98 @@
+/*
+ * sg.h -- C ABI of the CNN surrogate that warm-starts steady-state runs of the
+ * lattice Boltzmann solver (lb.h).  Project addition: the paper defines no
+ * learned component; the network maps the parameters of a double-diffusive
+ * cavity (Sec. 3.2: Ra, Le, Nc, Sr = S_TC, Df = D_CT) plus the grid
+ * coordinates to the steady fields (u, v, T, C), and the LB iteration remains
+ * the judge of its error.
+ *
+ * Network (fixed): six 3x3 convolutions, zero padding, channels-last
+ *   15 -> 64 -> 128 -> 64 -> 64 -> 64 -> 4, SiLU after each hidden layer.
+ * Input features per pixel: the 5 normalised parameters, the cell-centre
+ * coordinates xc = (i + 1/2)/W, yc = (j + 1/2)/H and sin/cos of pi xc, 2 pi xc,
+ * pi yc, 2 pi yc.  Weights and activations are stored in bfloat16, products
+ * accumulate in FP32 on the gfx950 matrix cores; master weights, the loss
+ * (mean squared error over the 4 outputs) and Adam run in FP32.
+ *
+ * Packed parameter vector (FP32), layer by layer: w[co][tap][ci] with
+ * tap = (dy + 1) * 3 + (dx + 1) (input pixel (y + dy, x + dx)), over the padded
+ * channel counts of sg_layer_info, then b[co].  Padded entries must be 0 and
+ * stay 0.
+ *
+ * Device arrays: params [n][5] FP32 (normalised), fields [n][4][H][W] FP32
+ * (u, v, T, C).  Ownership, errors and streams as in lb.h.
+ */
+#ifndef LBCDF_SG_H
+#define LBCDF_SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_LAYERS 6
+#define SG_IN_PARAMS 5
+#define SG_OUTPUTS 4
+
+typedef struct sg_config {
+    int32_t batch;        /* samples per training step / largest prediction batch */
+    int32_t height, width;/* grid; width a multiple of 64 */
+    int32_t reserved;     /* must be 0 */
+    float lr, beta1, beta2, eps; /* Adam */
+} sg_config;
+
+typedef struct sg_handle sg_handle;
+
+/* Real and padded channel counts of layer l (0..SG_LAYERS-1). */
+lb_status sg_layer_info(int32_t layer, int32_t* cin, int32_t* cout, int32_t* cin_pad, int32_t* cout_pad);
+
+/* Length of the packed parameter vector (padded) and number of real parameters. */
+lb_status sg_param_count(int64_t* packed, int64_t* real);
+
+lb_status sg_workspace_bytes(const sg_config* cfg, size_t* bytes);
+lb_status sg_create(const sg_config* cfg, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                    sg_handle** out);
+
+/* Host copies of the FP32 master weights (packed layout); set also resets Adam. */
+lb_status sg_set_weights(sg_handle* h, const float* host_packed);
+lb_status sg_get_weights(sg_handle* h, float* host_packed);
+
+/* Loss and gradients of one batch without updating: samples host_idx[0..batch)
+ * of the device arrays.  loss_out (host) and grads_out (host, packed) may be NULL. */
+lb_status sg_gradients(sg_handle* h, const float* d_params, const float* d_fields, const int32_t* host_idx,
+                       float* loss_out, float* grads_out);
+
+/* One Adam step on one batch (as sg_gradients, then the update). */
+lb_status sg_train_step(sg_handle* h, const float* d_params, const float* d_fields, const int32_t* host_idx,
+                        float* loss_out);
+
+/* Epochs over n samples in seeded shuffled order (full batches only);
+ * losses_out[epoch] = mean batch loss.  Synchronises. */
+lb_status sg_train_epochs(sg_handle* h, const float* d_params, const float* d_fields, int32_t n, int32_t epochs,
+                          uint64_t seed, float* losses_out);
+
+/* Prediction for n samples (any n; processed in chunks of the batch size):
+ * d_out [n][4][H][W] FP32 on the device.  Asynchronous. */
+lb_status sg_predict(sg_handle* h, const float* d_params, int32_t n, float* d_out);
+
+/* Pre-activations z of layer l from the last forward pass, host [batch][H][W][cout_pad]. */
+lb_status sg_layer_output(sg_handle* h, int32_t layer, float* host_out);
+
+/* Input of layer l (bfloat16 values widened to FP32) from the last forward
+ * pass, host [batch][H][W][cin_pad]. */
+lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out);
+
+lb_status sg_free(sg_handle* h);
+
+/* Thread-local text of the last surrogate error. */
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBCDF_SG_H */

@@ -1,0 +1,680 @@
+// sg_kernels.hip -- CNN surrogate on the gfx950 matrix cores: 3x3 convolutions
+// as implicit GEMMs with bfloat16 operands and FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16), fused bias/SiLU epilogues, weight gradients by
+// split-K implicit GEMM with a deterministic reduction, MSE loss and Adam.
+//
+// Tensors are channels-last: pixel p = (b H + y) W + x, channel contiguous.
+// A convolution  z[p][co] = b[co] + sum_{tap, ci} w[co][tap][ci] x[p + off(tap)][ci]
+// is the GEMM  Z[M = pixels][N = co] = A[M][K = (tap, ci)] B[K][N]  with
+// A gathered from the shifted input (zero outside the image) and B the
+// weights; the data gradient is the same GEMM with the transposed, flipped
+// weights, and the weight gradient is  dW[co][(tap, ci)] = sum_p dZ[p][co]
+// x[p + off(tap)][ci]  (K = pixels, split over workgroups).
+//
+// Workgroup tile 64 x 64 (4 wavefronts of 32 x 32, each 2 x 2 MFMA blocks of
+// 16 x 16), K step 32 staged through LDS.  MFMA operand layout (16x16x32):
+// lane l holds A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l % 16], j < 8,
+// and D[4 (l / 16) + j][l % 16], j < 4.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/sg.h"
+
+namespace sgk {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int kLayers = SG_LAYERS;
+constexpr int kCin[kLayers] = {15, 64, 128, 64, 64, 64};
+constexpr int kCout[kLayers] = {64, 128, 64, 64, 64, 4};
+constexpr int kCinPad[kLayers] = {32, 64, 128, 64, 64, 64};
+constexpr int kCoutPad[kLayers] = {64, 128, 64, 64, 64, 64};
+constexpr int kMaxC = 128;
+constexpr int kFeat = 15;
+constexpr int kSplit = 64;      // split-K factor of the weight gradient
+constexpr int kRed = 256;       // blocks of the first pass of small reductions
+constexpr int LDSK = 40;        // LDS row pitch in bf16 (32 + 8 pad, 16-byte aligned)
+
+// ---- features ------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ params, const int* __restrict__ idx,
+                                                  int nb, int H, int W, bf16* __restrict__ x) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long P = (long long)nb * H * W;
+    if (p >= P) return;
+    const int b = (int)(p / ((long long)H * W));
+    const int rem = (int)(p % ((long long)H * W));
+    const int yi = rem / W, xi = rem % W;
+    const float* pr = params + (long long)idx[b] * SG_IN_PARAMS;
+    const float xc = (xi + 0.5f) / W, yc = (yi + 0.5f) / H;
+    const float pi = 3.14159265358979f;
+    float f[kFeat] = {pr[0], pr[1], pr[2], pr[3], pr[4], xc, yc,
+                      sinf(pi * xc), cosf(pi * xc), sinf(2 * pi * xc), cosf(2 * pi * xc),
+                      sinf(pi * yc), cosf(pi * yc), sinf(2 * pi * yc), cosf(2 * pi * yc)};
+    bf16* o = x + p * kCinPad[0];
+#pragma unroll
+    for (int c = 0; c < kCinPad[0]; ++c) o[c] = bf16(c < kFeat ? f[c] : 0.0f);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ---- implicit-GEMM convolution -------------------------------------------
+// MODE 0 (forward): z = acc + bias; Zout = z; Yout = bf16(act ? SiLU(z) : z).
+// MODE 1 (data gradient): Yout = bf16(acc * SiLU'(Zprev)).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
+                                              const float* __restrict__ bias, const float* __restrict__ Zprev,
+                                              float* __restrict__ Zout, bf16* __restrict__ Yout, int H, int W,
+                                              int Cin, int Cout, int act) {
+    __shared__ __attribute__((aligned(16))) bf16 As[64 * LDSK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_per_row = W >> 6;
+    const int img_row = blockIdx.x / tiles_per_row;  // b * H + y
+    const int x0 = (blockIdx.x % tiles_per_row) << 6;
+    const int y = img_row % H;
+    const int n0 = blockIdx.y << 6;
+    const int sj = tid >> 2, sq = tid & 3;
+    const int wr = (wave >> 1) << 5, wc = (wave & 1) << 5;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int yy = y + dy, xx = x0 + sj + dx;
+        const bool in = (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W);
+        const long long src = ((long long)(img_row + dy) * W + xx) * Cin;
+        const long long wsrc = ((long long)(n0 + sj) * 9 + tap) * Cin;
+        for (int c0 = 0; c0 < Cin; c0 += 32) {
+            uint4 va = make_uint4(0u, 0u, 0u, 0u);
+            if (in) va = *reinterpret_cast<const uint4*>(X + src + c0 + 8 * sq);
+            *reinterpret_cast<uint4*>(&As[sj * LDSK + 8 * sq]) = va;
+            *reinterpret_cast<uint4*>(&Bs[sj * LDSK + 8 * sq]) =
+                *reinterpret_cast<const uint4*>(Wk + wsrc + c0 + 8 * sq);
+            __syncthreads();
+            const int r = lane & 15, kq = (lane >> 4) * 8;
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSK + kq]);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSK + kq]);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + r) * LDSK + kq]);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + 16 + r) * LDSK + kq]);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+            __syncthreads();
+        }
+    }
+    const long long pbase = (long long)img_row * W + x0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = wr + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + wc + 16 * j + (lane & 15);
+                const long long o = (pbase + m) * Cout + n;
+                const float v = acc[i][j][e];
+                if constexpr (MODE == 0) {
+                    const float z = v + bias[n];
+                    Zout[o] = z;
+                    Yout[o] = bf16(act ? silu(z) : z);
+                } else {
+                    Yout[o] = bf16(v * silu_grad(Zprev[o]));
+                }
+            }
+}
+
+// ---- weight gradient: split-K implicit GEMM -------------------------------
+// part[s][tap][co][ci] = sum over the pixel chunks of split s of dZ[p][co] x[p + off(tap)][ci]
+__global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, const bf16* __restrict__ X,
+                                               float* __restrict__ part, int H, int W, int P, int Ci, int Co) {
+    __shared__ __attribute__((aligned(16))) bf16 As[64 * LDSK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x << 6, n0 = blockIdx.y << 6;
+    const int tap = blockIdx.z % 9, s = blockIdx.z / 9;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int chunks = P >> 5;
+    const int c_begin = (int)((long long)s * chunks / kSplit), c_end = (int)((long long)(s + 1) * chunks / kSplit);
+    const int sk = tid >> 3, sq = tid & 7;  // pixel in chunk (0..31), 8-channel group (0..7)
+    const int wr = (wave >> 1) << 5, wc = (wave & 1) << 5;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool bcol = n0 + 8 * sq < Ci;
+    for (int c = c_begin; c < c_end; ++c) {
+        const long long p = ((long long)c << 5) + sk;
+        const int img_row = (int)(p / W), xi = (int)(p % W), yi = img_row % H;
+        // A[co][k] = dZ[p][m0 + co]
+        const uint4 va = *reinterpret_cast<const uint4*>(dZ + p * Co + m0 + 8 * sq);
+        const bf16* ea = reinterpret_cast<const bf16*>(&va);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) As[(8 * sq + e) * LDSK + sk] = ea[e];
+        // B[ci][k] = x[p + off(tap)][n0 + ci]
+        const int yy = yi + dy, xx = xi + dx;
+        uint4 vb = make_uint4(0u, 0u, 0u, 0u);
+        if (bcol && yy >= 0 && yy < H && xx >= 0 && xx < W)
+            vb = *reinterpret_cast<const uint4*>(X + ((long long)(img_row + dy) * W + xx) * Ci + n0 + 8 * sq);
+        const bf16* eb = reinterpret_cast<const bf16*>(&vb);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[(8 * sq + e) * LDSK + sk] = eb[e];
+        __syncthreads();
+        const int r = lane & 15, kq = (lane >> 4) * 8;
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSK + kq]);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSK + kq]);
+        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + r) * LDSK + kq]);
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + 16 + r) * LDSK + kq]);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        __syncthreads();
+    }
+    float* dst = part + ((long long)s * 9 + tap) * Co * Ci;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = m0 + wr + 16 * i + 4 * (lane >> 4) + e;
+                const int ci = n0 + wc + 16 * j + (lane & 15);
+                if (ci < Ci) dst[(long long)co * Ci + ci] = acc[i][j][e];
+            }
+}
+
+// dW[co][tap][ci] (packed) = sum_s part[s][tap][co][ci], fixed order
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int Ci, int Co,
+                                                      float* __restrict__ dW) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = 9ll * Co * Ci;
+    if (k >= n) return;
+    const int tap = (int)(k / ((long long)Co * Ci));
+    const long long rem = k % ((long long)Co * Ci);
+    const int co = (int)(rem / Ci), ci = (int)(rem % Ci);
+    float s = 0.f;
+    for (int q = 0; q < kSplit; ++q) s += part[(long long)q * n + k];
+    dW[((long long)co * 9 + tap) * Ci + ci] = s;
+}
+
+// bias gradient, two passes: part[block][co] over pixel ranges, then fixed-order sum
+__global__ __launch_bounds__(128) void k_bgrad_part(const bf16* __restrict__ dZ, long long P, int Co,
+                                                    float* __restrict__ part) {
+    const int co = threadIdx.x;
+    if (co >= Co) return;
+    const long long b0 = P * blockIdx.x / gridDim.x, b1 = P * (blockIdx.x + 1) / gridDim.x;
+    float s = 0.f;
+    for (long long p = b0; p < b1; ++p) s += float(dZ[p * Co + co]);
+    part[(long long)blockIdx.x * kMaxC + co] = s;
+}
+__global__ __launch_bounds__(128) void k_bgrad_final(const float* __restrict__ part, int nb, int Co,
+                                                     float* __restrict__ db) {
+    const int co = threadIdx.x;
+    if (co >= Co) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[(long long)b * kMaxC + co];
+    db[co] = s;
+}
+
+// MSE over the SG_OUTPUTS real channels: dZ = 2 (z - t) / count (bf16, zero on
+// padded channels); per-block partial sums of (z - t)^2 in FP64
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Z, const float* __restrict__ fields,
+                                             const int* __restrict__ idx, int nb, int H, int W, int Co,
+                                             bf16* __restrict__ dZ, double* __restrict__ part) {
+    __shared__ double red[256];
+    const long long P = (long long)nb * H * W;
+    const double inv = 2.0 / (double)(P * SG_OUTPUTS);
+    double acc = 0.0;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(p / ((long long)H * W));
+        const long long pix = p % ((long long)H * W);
+        for (int c = 0; c < Co; ++c) {
+            float g = 0.f;
+            if (c < SG_OUTPUTS) {
+                const float d = Z[p * Co + c] - fields[((long long)idx[b] * SG_OUTPUTS + c) * H * W + pix];
+                acc += (double)d * d;
+                g = (float)(inv * d);
+            }
+            dZ[p * Co + c] = bf16(g);
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_mse_final(const double* __restrict__ part, int nb, double count, float* __restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    *loss = (float)(s / count);
+}
+
+// Adam (bias-corrected), FP32 master weights
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, long long n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// bf16 weights for the forward GEMM ([co][tap][ci]) and the data-gradient GEMM
+// ([ci][8 - tap][co]: transposed and flipped)
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, int Ci, int Co, bf16* __restrict__ wk,
+                                              bf16* __restrict__ wt) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 9ll * Co * Ci) return;
+    const int co = (int)(k / (9ll * Ci));
+    const long long rem = k % (9ll * Ci);
+    const int tap = (int)(rem / Ci), ci = (int)(rem % Ci);
+    const bf16 v = bf16(w[k]);
+    wk[k] = v;
+    wt[((long long)ci * 9 + (8 - tap)) * Co + co] = v;
+}
+
+// [p][Co] (first SG_OUTPUTS channels) -> out[b][c][y][x]
+__global__ __launch_bounds__(256) void k_unpack_out(const float* __restrict__ Z, int nb, int H, int W, int Co,
+                                                    float* __restrict__ out) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long P = (long long)nb * H * W;
+    if (p >= P) return;
+    const int b = (int)(p / ((long long)H * W));
+    const long long pix = p % ((long long)H * W);
+#pragma unroll
+    for (int c = 0; c < SG_OUTPUTS; ++c) out[((long long)b * SG_OUTPUTS + c) * H * W + pix] = Z[p * Co + c];
+}
+
+}  // namespace sgk
+
+// ============================================================================
+// host side
+// ============================================================================
+using namespace sgk;
+
+namespace {
+thread_local std::string g_sgerr;
+lb_status sgfail(lb_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_sgerr = buf;
+    return st;
+}
+#define SGCHK(expr)                                                                                  \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return sgfail(LB_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+size_t rup(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Plan {
+    size_t P;
+    long long nw[kLayers], woff[kLayers], boff[kLayers], npacked;
+    size_t w_off, m_off, v_off, g_off, wk_off[kLayers], wt_off[kLayers], x0_off, z_off[kLayers], y_off[kLayers],
+        dz_off[2], part_off, bpart_off, lpart_off, loss_off, idx_off, total;
+};
+
+Plan make_plan(const sg_config& c) {
+    Plan pl{};
+    pl.P = (size_t)c.batch * c.height * c.width;
+    long long off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        pl.nw[l] = 9ll * kCoutPad[l] * kCinPad[l];
+        pl.woff[l] = off;
+        off += pl.nw[l];
+        pl.boff[l] = off;
+        off += kCoutPad[l];
+    }
+    pl.npacked = off;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = rup(o + bytes);
+        return r;
+    };
+    pl.w_off = take(4 * pl.npacked);
+    pl.m_off = take(4 * pl.npacked);
+    pl.v_off = take(4 * pl.npacked);
+    pl.g_off = take(4 * pl.npacked);
+    for (int l = 0; l < kLayers; ++l) {
+        pl.wk_off[l] = take(2 * pl.nw[l]);
+        pl.wt_off[l] = take(2 * pl.nw[l]);
+    }
+    pl.x0_off = take(2 * pl.P * kCinPad[0]);
+    for (int l = 0; l < kLayers; ++l) {
+        pl.z_off[l] = take(4 * pl.P * kCoutPad[l]);
+        pl.y_off[l] = take(2 * pl.P * kCoutPad[l]);
+    }
+    pl.dz_off[0] = take(2 * pl.P * kMaxC);
+    pl.dz_off[1] = take(2 * pl.P * kMaxC);
+    pl.part_off = take(4ull * kSplit * 9 * kMaxC * kMaxC);
+    pl.bpart_off = take(4ull * kRed * kMaxC);
+    pl.lpart_off = take(8ull * kRed);
+    pl.loss_off = take(8);
+    pl.idx_off = take(4ull * c.batch);
+    pl.total = o;
+    return pl;
+}
+}  // namespace
+
+struct sg_handle {
+    sg_config c;
+    Plan pl;
+    char* ws;
+    hipStream_t s;
+    long long t;  // Adam step counter
+    int nb_last;  // samples in the last forward pass
+};
+
+namespace {
+template <class T>
+T* ptr(sg_handle* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
+
+lb_status pack_weights(sg_handle* h) {
+    for (int l = 0; l < kLayers; ++l) {
+        const long long n = h->pl.nw[l];
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s,
+                           ptr<float>(h, h->pl.w_off) + h->pl.woff[l], kCinPad[l], kCoutPad[l],
+                           ptr<bf16>(h, h->pl.wk_off[l]), ptr<bf16>(h, h->pl.wt_off[l]));
+        SGCHK(hipGetLastError());
+    }
+    return LB_OK;
+}
+
+// forward pass of nb samples listed in the device index array
+lb_status forward(sg_handle* h, const float* d_params, int nb) {
+    const int H = h->c.height, W = h->c.width;
+    const long long P = (long long)nb * H * W;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, h->s, d_params,
+                       ptr<int>(h, h->pl.idx_off), nb, H, W, ptr<bf16>(h, h->pl.x0_off));
+    SGCHK(hipGetLastError());
+    const bf16* x = ptr<bf16>(h, h->pl.x0_off);
+    for (int l = 0; l < kLayers; ++l) {
+        const dim3 grid((unsigned)(P / 64), (unsigned)(kCoutPad[l] / 64));
+        hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, h->s, x, ptr<bf16>(h, h->pl.wk_off[l]),
+                           ptr<float>(h, h->pl.w_off) + h->pl.boff[l], (const float*)nullptr,
+                           ptr<float>(h, h->pl.z_off[l]), ptr<bf16>(h, h->pl.y_off[l]), H, W, kCinPad[l],
+                           kCoutPad[l], l + 1 < kLayers ? 1 : 0);
+        SGCHK(hipGetLastError());
+        x = ptr<bf16>(h, h->pl.y_off[l]);
+    }
+    h->nb_last = nb;
+    return LB_OK;
+}
+
+lb_status set_indices(sg_handle* h, const int32_t* host_idx, int nb) {
+    SGCHK(hipMemcpyAsync(ptr<int>(h, h->pl.idx_off), host_idx, 4ull * nb, hipMemcpyHostToDevice, h->s));
+    return LB_OK;
+}
+
+// loss + gradients of every layer into the packed gradient vector
+lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host) {
+    const int H = h->c.height, W = h->c.width;
+    const long long P = (long long)nb * H * W;
+    const int L = kLayers - 1;
+    bf16* dz = ptr<bf16>(h, h->pl.dz_off[0]);
+    hipLaunchKernelGGL(k_mse, dim3(kRed), dim3(256), 0, h->s, ptr<float>(h, h->pl.z_off[L]), d_fields,
+                       ptr<int>(h, h->pl.idx_off), nb, H, W, kCoutPad[L], dz, ptr<double>(h, h->pl.lpart_off));
+    SGCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, h->s, ptr<double>(h, h->pl.lpart_off), kRed,
+                       (double)(P * SG_OUTPUTS), ptr<float>(h, h->pl.loss_off));
+    SGCHK(hipGetLastError());
+    float* grads = ptr<float>(h, h->pl.g_off);
+    for (int l = L; l >= 0; --l) {
+        const int Ci = kCinPad[l], Co = kCoutPad[l];
+        const bf16* xin = l == 0 ? ptr<bf16>(h, h->pl.x0_off) : ptr<bf16>(h, h->pl.y_off[l - 1]);
+        hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 9u * kSplit), dim3(256), 0,
+                           h->s, dz, xin, ptr<float>(h, h->pl.part_off), H, W, (int)P, Ci, Co);
+        SGCHK(hipGetLastError());
+        const long long n = 9ll * Co * Ci;
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s,
+                           ptr<float>(h, h->pl.part_off), Ci, Co, grads + h->pl.woff[l]);
+        SGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(128), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
+        SGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(128), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co,
+                           grads + h->pl.boff[l]);
+        SGCHK(hipGetLastError());
+        if (l > 0) {
+            bf16* dzn = ptr<bf16>(h, h->pl.dz_off[(L - l + 1) & 1]);
+            const dim3 grid((unsigned)(P / 64), (unsigned)(Ci / 64));
+            hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, h->s, dz, ptr<bf16>(h, h->pl.wt_off[l]),
+                               (const float*)nullptr, ptr<float>(h, h->pl.z_off[l - 1]), (float*)nullptr, dzn, H, W,
+                               Co, Ci, 0);
+            SGCHK(hipGetLastError());
+            dz = dzn;
+        }
+    }
+    if (loss_host) {
+        SGCHK(hipMemcpyAsync(loss_host, ptr<float>(h, h->pl.loss_off), 4, hipMemcpyDeviceToHost, h->s));
+        SGCHK(hipStreamSynchronize(h->s));
+    }
+    return LB_OK;
+}
+
+lb_status adam(sg_handle* h) {
+    h->t += 1;
+    const float c1 = 1.f - powf(h->c.beta1, (float)h->t), c2 = 1.f - powf(h->c.beta2, (float)h->t);
+    const long long n = h->pl.npacked;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s, ptr<float>(h, h->pl.w_off),
+                       ptr<float>(h, h->pl.g_off), ptr<float>(h, h->pl.m_off), ptr<float>(h, h->pl.v_off), n, h->c.lr,
+                       h->c.beta1, h->c.beta2, h->c.eps, c1, c2);
+    SGCHK(hipGetLastError());
+    return pack_weights(h);
+}
+
+lb_status check_idx(sg_handle* h, const int32_t* idx) {
+    if (!idx) return sgfail(LB_EINVAL, "host_idx is NULL");
+    for (int b = 0; b < h->c.batch; ++b)
+        if (idx[b] < 0) return sgfail(LB_EINVAL, "negative sample index");
+    return LB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lb_status sg_layer_info(int32_t layer, int32_t* cin, int32_t* cout, int32_t* cin_pad, int32_t* cout_pad) {
+    if (layer < 0 || layer >= kLayers) return sgfail(LB_EINVAL, "layer out of range");
+    if (cin) *cin = kCin[layer];
+    if (cout) *cout = kCout[layer];
+    if (cin_pad) *cin_pad = kCinPad[layer];
+    if (cout_pad) *cout_pad = kCoutPad[layer];
+    return LB_OK;
+}
+
+lb_status sg_param_count(int64_t* packed, int64_t* real) {
+    long long p = 0, r = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        p += 9ll * kCoutPad[l] * kCinPad[l] + kCoutPad[l];
+        r += 9ll * kCout[l] * kCin[l] + kCout[l];
+    }
+    if (packed) *packed = p;
+    if (real) *real = r;
+    return LB_OK;
+}
+
+lb_status sg_workspace_bytes(const sg_config* cfg, size_t* bytes) {
+    if (!cfg || !bytes) return sgfail(LB_EINVAL, "NULL argument");
+    if (cfg->batch < 1 || cfg->height < 1 || cfg->width < 64 || cfg->width % 64 || cfg->reserved != 0)
+        return sgfail(LB_EINVAL, "batch >= 1, height >= 1, width a multiple of 64 required");
+    if (!(cfg->lr >= 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+        !(cfg->eps > 0.f))
+        return sgfail(LB_EINVAL, "invalid Adam hyper-parameters");
+    *bytes = make_plan(*cfg).total;
+    return LB_OK;
+}
+
+lb_status sg_create(const sg_config* cfg, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
+                    sg_handle** out) {
+    if (!out) return sgfail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    lb_status st = sg_workspace_bytes(cfg, &need);
+    if (st != LB_OK) return st;
+    if (!dev_workspace || reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+        return sgfail(LB_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (workspace_bytes < need) return sgfail(LB_ENOMEM, "workspace has %zu bytes, %zu needed", workspace_bytes, need);
+    sg_handle* h = new (std::nothrow) sg_handle();
+    if (!h) return sgfail(LB_ENOMEM, "host allocation failed");
+    h->c = *cfg;
+    h->pl = make_plan(*cfg);
+    h->ws = static_cast<char*>(dev_workspace);
+    h->s = static_cast<hipStream_t>(hip_stream);
+    h->t = 0;
+    h->nb_last = 0;
+    *out = h;
+    return LB_OK;
+}
+
+lb_status sg_set_weights(sg_handle* h, const float* host_packed) {
+    if (!h || !host_packed) return sgfail(LB_EINVAL, "NULL argument");
+    const size_t n = (size_t)h->pl.npacked;
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(host_packed[k])) return sgfail(LB_ENONFINITE, "non-finite weight");
+    SGCHK(hipMemcpyAsync(ptr<float>(h, h->pl.w_off), host_packed, 4 * n, hipMemcpyHostToDevice, h->s));
+    SGCHK(hipMemsetAsync(ptr<float>(h, h->pl.m_off), 0, 4 * n, h->s));
+    SGCHK(hipMemsetAsync(ptr<float>(h, h->pl.v_off), 0, 4 * n, h->s));
+    h->t = 0;
+    lb_status st = pack_weights(h);
+    if (st != LB_OK) return st;
+    SGCHK(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status sg_get_weights(sg_handle* h, float* host_packed) {
+    if (!h || !host_packed) return sgfail(LB_EINVAL, "NULL argument");
+    SGCHK(hipMemcpyAsync(host_packed, ptr<float>(h, h->pl.w_off), 4ull * h->pl.npacked, hipMemcpyDeviceToHost, h->s));
+    SGCHK(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status sg_gradients(sg_handle* h, const float* d_params, const float* d_fields, const int32_t* host_idx,
+                       float* loss_out, float* grads_out) {
+    if (!h || !d_params || !d_fields) return sgfail(LB_EINVAL, "NULL argument");
+    lb_status st = check_idx(h, host_idx);
+    if (st == LB_OK) st = set_indices(h, host_idx, h->c.batch);
+    if (st == LB_OK) st = forward(h, d_params, h->c.batch);
+    if (st == LB_OK) st = backward(h, d_fields, h->c.batch, loss_out);
+    if (st != LB_OK) return st;
+    if (grads_out) {
+        SGCHK(hipMemcpyAsync(grads_out, ptr<float>(h, h->pl.g_off), 4ull * h->pl.npacked, hipMemcpyDeviceToHost, h->s));
+        SGCHK(hipStreamSynchronize(h->s));
+    }
+    return LB_OK;
+}
+
+lb_status sg_train_step(sg_handle* h, const float* d_params, const float* d_fields, const int32_t* host_idx,
+                        float* loss_out) {
+    lb_status st = sg_gradients(h, d_params, d_fields, host_idx, loss_out, nullptr);
+    if (st != LB_OK) return st;
+    return adam(h);
+}
+
+lb_status sg_train_epochs(sg_handle* h, const float* d_params, const float* d_fields, int32_t n, int32_t epochs,
+                          uint64_t seed, float* losses_out) {
+    if (!h || n < h->c.batch || epochs < 0) return sgfail(LB_EINVAL, "need n >= batch and epochs >= 0");
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::mt19937_64 rng(seed);
+    const int nbatch = n / h->c.batch;
+    std::vector<float> losses((size_t)nbatch);
+    for (int e = 0; e < epochs; ++e) {
+        for (int k = n - 1; k > 0; --k) {  // Fisher-Yates with the seeded generator
+            const int j = (int)(rng() % (uint64_t)(k + 1));
+            std::swap(order[k], order[j]);
+        }
+        double sum = 0.0;
+        for (int b = 0; b < nbatch; ++b) {
+            float loss = 0.f;
+            lb_status st = sg_train_step(h, d_params, d_fields, order.data() + (size_t)b * h->c.batch, &loss);
+            if (st != LB_OK) return st;
+            sum += loss;
+        }
+        if (losses_out) losses_out[e] = (float)(sum / nbatch);
+    }
+    SGCHK(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status sg_predict(sg_handle* h, const float* d_params, int32_t n, float* d_out) {
+    if (!h || !d_params || !d_out || n < 0) return sgfail(LB_EINVAL, "bad argument");
+    const int H = h->c.height, W = h->c.width, L = kLayers - 1;
+    std::vector<int32_t> idx((size_t)h->c.batch);
+    for (int s0 = 0; s0 < n; s0 += h->c.batch) {
+        const int nb = std::min(h->c.batch, n - s0);
+        for (int b = 0; b < nb; ++b) idx[b] = s0 + b;
+        lb_status st = set_indices(h, idx.data(), nb);
+        if (st == LB_OK) st = forward(h, d_params, nb);
+        if (st != LB_OK) return st;
+        const long long P = (long long)nb * H * W;
+        hipLaunchKernelGGL(k_unpack_out, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, h->s,
+                           ptr<float>(h, h->pl.z_off[L]), nb, H, W, kCoutPad[L],
+                           d_out + (long long)s0 * SG_OUTPUTS * H * W);
+        SGCHK(hipGetLastError());
+        SGCHK(hipStreamSynchronize(h->s));  // the index staging buffer is reused by the next chunk
+    }
+    return LB_OK;
+}
+
+lb_status sg_layer_output(sg_handle* h, int32_t layer, float* host_out) {
+    if (!h || !host_out || layer < 0 || layer >= kLayers) return sgfail(LB_EINVAL, "bad argument");
+    const size_t n = (size_t)h->nb_last * h->c.height * h->c.width * kCoutPad[layer];
+    SGCHK(hipMemcpyAsync(host_out, ptr<float>(h, h->pl.z_off[layer]), 4 * n, hipMemcpyDeviceToHost, h->s));
+    SGCHK(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out) {
+    if (!h || !host_out || layer < 0 || layer >= kLayers) return sgfail(LB_EINVAL, "bad argument");
+    const size_t n = (size_t)h->nb_last * h->c.height * h->c.width * kCinPad[layer];
+    const size_t off = layer == 0 ? h->pl.x0_off : h->pl.y_off[layer - 1];
+    std::vector<uint16_t> tmp(n);
+    SGCHK(hipMemcpyAsync(tmp.data(), h->ws + off, 2 * n, hipMemcpyDeviceToHost, h->s));
+    SGCHK(hipStreamSynchronize(h->s));
+    for (size_t k = 0; k < n; ++k) {
+        const uint32_t bits = (uint32_t)tmp[k] << 16;
+        std::memcpy(&host_out[k], &bits, 4);
+    }
+    return LB_OK;
+}
+
+lb_status sg_free(sg_handle* h) {
+    delete h;
+    return LB_OK;
+}
+
+const char* sg_last_error(void) { return g_sgerr.c_str(); }
+
+}  // extern "C"

@@ -20,12 +20,20 @@ def declared(header):
     return sorted(set(re.findall(r"\b((?:lb|sg|lbb)_[a-z_0-9]+)\s*\(", text)))
 
 
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("header", ["lb.h", "sg.h"])
+def test_library_exports_every_declared_symbol(header):
     L = lb.lib()
-    names = declared("lb.h")
-    assert "lb_init" in names and "lb_step" in names and "lb_residual" in names
+    names = declared(header)
+    assert len(names) >= 10
     for name in names:
         assert hasattr(L, name), name
+
+
+def test_surrogate_host_queries():
+    from paper_2101_03055_amd import sg
+    packed, real = sg.param_count()
+    assert 200_000 < real < 300_000 and packed > real
+    assert sg.layer_info(0) == (15, 64, 32, 64) and sg.layer_info(5) == (64, 4, 64, 64)
 
 
 def test_params_record_matches():
