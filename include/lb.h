@@ -86,7 +86,10 @@ typedef struct lb_params {
     int32_t r_kind;              /* LB_R_* */
     int32_t fluid_bc[4];         /* LB_BC_* per side; periodic only in pairs (0,1) / (2,3) */
     int32_t scalar_bc[4][LB_MAX_M]; /* LB_SBC_* per side and species; periodic must match the fluid */
-    int32_t reserved;            /* must be 0 */
+    int32_t fused_steps;         /* 0 or 1: one AA-pattern launch per step (single population array);
+                                    2: two steps per launch, temporally blocked through LDS (two
+                                    population arrays: twice the population memory, half the HBM
+                                    traffic per step) */
     double tau_f;                /* fluid relaxation time (> 1/2); nu = (tau_f - 1/2)/3 */
     double rho0;                 /* constant of the fluid equilibrium (Eq. heq) */
     double mrt_s[9];             /* MRT rates, moment order rho,e,eps,jx,qx,jy,qy,pxx,pxy;
@@ -112,8 +115,9 @@ lb_status lb_workspace_bytes(const lb_params* params, size_t* bytes);
 
 /* Validates the parameters (tau_f > 1/2, Re(eig D) > 0 so that eig(omega) lies in
  * (0, 2), m range, boundary codes, finite inputs), then initialises
- * f = f^eq(phi0, u0), h = h^eq(p0, u0) and S_old = S(phi0) at t = 0 (reading of
- * the paper: it does not state the initial populations).  phi0: host [m][ny][nx];
+ * f = f^eq(phi0, u0), h = h^eq(p0, u0 - F(phi0)/2) and S_old = S(phi0) at t = 0, so
+ * that the velocity of Eq. sum-u is the prescribed u0 (reading of the paper: it
+ * does not state the initial populations).  phi0: host [m][ny][nx];
  * u0: host [2][ny][nx]; p0: host [ny][nx] or NULL (p0 = 0).  Synchronises the
  * stream before returning.  *out receives a new handle. */
 lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace_bytes,
@@ -192,7 +196,7 @@ lb_status lb_free(lb_handle* h);
  * must share m, model, storage, collision and r_kind.  Residuals are reduced
  * per cavity (FP64, deterministic); converged, diverged or capped cavities are
  * retired from the tile list and keep their final state.
- * Per-cavity status: 0 running, 1 converged, 2 diverged (non-finite), 3 step cap. */
+ * Per-cavity status: 0 running, 1 converged, 2 diverged (non-finite). */
 typedef struct lbb_handle lbb_handle;
 
 /* Workspace bytes for the batch (validates every record). */
@@ -207,13 +211,22 @@ lb_status lbb_init(const lb_params* params, int32_t count, void* dev_workspace, 
 /* Advances every running cavity by n steps (n launches), asynchronously. */
 lb_status lbb_step(lbb_handle* b, int64_t n);
 
-/* Runs until every cavity is retired or max_steps steps were taken: windows of
- * check_every steps (rounded up to even) followed by the per-cavity residual of
- * lb_residual; a cavity retires when all its residual components are below tol,
- * when a field turns non-finite, or at the cap.  Outputs (any may be NULL):
- * steps_out[count], status_out[count], res_out[count][m + 2].  Synchronises. */
+/* Runs until every cavity is retired or max_steps steps were taken by this call:
+ * windows of check_every steps (rounded up to even) followed by the per-cavity
+ * residual of lb_residual; a cavity retires when all its residual components
+ * are below tol or when a field turns non-finite.  Cavities still running at
+ * the end keep status 0 and continue in the next call (a call sequence is a
+ * long run with progress points).  Outputs (any may be NULL): steps_out[count]
+ * (total steps per cavity), status_out[count], res_out[count][m + 2] (last
+ * residual).  Synchronises. */
 lb_status lbb_run(lbb_handle* b, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
                   int32_t* status_out, double* res_out);
+
+/* Copies cavity j of src into cavity i of dst (same parameters except storage,
+ * phi_ref and the FP16 scales), converting the storage on the device; cavity i
+ * becomes running with src's step count.  dst must be at an even batch step.
+ * Used for the FP64 finish of an FP32 sweep.  Synchronises both streams. */
+lb_status lbb_copy_cavity(lbb_handle* dst, int32_t i, lbb_handle* src, int32_t j);
 
 /* Fields of cavity i (host arrays as in lb_moments; any may be NULL).  Synchronises. */
 lb_status lbb_moments(lbb_handle* b, int32_t i, double* phi, double* u, double* p);

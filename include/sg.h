@@ -86,6 +86,14 @@ lb_status sg_layer_output(sg_handle* h, int32_t layer, float* host_out);
  * pass, host [batch][H][W][cin_pad]. */
 lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out);
 
+/* Separable [1 2 1]/4 x [1 2 1]/4 filter of `planes` device planes of
+ * height x width (edge values replicated), d_in -> d_out (not in place),
+ * asynchronous on hip_stream.  Applied to predictions before a warm start: it
+ * removes the grid-scale (Nyquist) content that the lattice Boltzmann
+ * iteration damps very slowly. */
+lb_status sg_smooth(const float* d_in, float* d_out, int32_t planes, int32_t height, int32_t width,
+                    void* hip_stream);
+
 lb_status sg_free(sg_handle* h);
 
 /* Thread-local text of the last surrogate error. */

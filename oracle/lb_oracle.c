@@ -25,6 +25,8 @@
  *   - varphi = 0 in Eqs. force and sum-p (Sec. 3).
  *   - gamma = 0 and the first-order backward difference for d/dt S (text
  *     after Eq. source); S_old at t = 0 is S(phi0).
+ *   - Initial populations: scalar equilibrium of (phi0, u0); fluid equilibrium
+ *     of (p0, u0 - F(phi0)/2), so that Eq. sum-u gives u0 at t = 0.
  *   - Half-way walls; anti-bounce-back f_opp = -f*_i + 2 W_i phi_w for
  *     Dirichlet scalars, half-way bounce-back for no-flux scalars and no-slip
  *     fluid, specular reflection for a free-slip fluid wall; a link leaving
@@ -434,7 +436,13 @@ int orc_init(const orc_cfg *cfg, const double *phi0, const double *u0, const dou
             u[1] = u0[N + n];
             double p = p0 ? p0[n] : 0.0;
             orc_feq(m, phi, u, feq);
-            orc_heq(p, u, cfg->rho0, heq);
+            /* fluid: equilibrium at the momentum sum c_i h_i = u0 - (dt/2) F(phi0), so that
+             * Eq. sum-u returns the prescribed u0 at t = 0 */
+            double F[2], j[2];
+            body_force(cfg, phi, F);
+            j[0] = u[0] - dt / 2.0 * F[0];
+            j[1] = u[1] - dt / 2.0 * F[1];
+            orc_heq(p, j, cfg->rho0, heq);
             source_S(cfg, phi, S);
             for (int a = 0; a < m; ++a) {
                 for (int i = 0; i < 5; ++i) f[(a * 5 + i) * N + n] = feq[a * 5 + i];

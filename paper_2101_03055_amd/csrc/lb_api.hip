@@ -84,6 +84,16 @@ Layout make_layout(const lb_params& p) {
     off += round_up((size_t)kRedBlocks * kRedWidth * 8, 256);
     L.res_off = off;
     off += 256 * 8;
+    L.pop2_off = L.pop_off;
+    L.sold2_off = L.sold_off;
+    if (p.fused_steps == 2) {
+        off = round_up(off, 4096);
+        L.pop2_off = off;
+        off += L.npop * pb;
+        off = round_up(off, 256);
+        L.sold2_off = off;
+        off += round_up(L.nsrc * L.N * arith_bytes(p.storage), 256);
+    }
     L.total = off;
     return L;
 }
@@ -170,7 +180,7 @@ lb_status validate(const lb_params* p) {
     if (p->storage < LB_STORE_F64 || p->storage > LB_STORE_F16) return fail(LB_EINVAL, "unknown storage");
     if (p->collision != LB_COLL_BGK && p->collision != LB_COLL_MRT) return fail(LB_EINVAL, "unknown collision");
     if (p->r_kind != LB_R_STEP && p->r_kind != LB_R_SMOOTH) return fail(LB_EINVAL, "unknown r_kind");
-    if (p->reserved != 0) return fail(LB_EINVAL, "reserved field must be 0");
+    if (p->fused_steps < 0 || p->fused_steps > 2) return fail(LB_EINVAL, "fused_steps must be 0, 1 or 2");
     if (!(p->tau_f > 0.5) || !std::isfinite(p->tau_f)) return fail(LB_EINVAL, "tau_f = %g must be > 1/2", p->tau_f);
     if (!std::isfinite(p->rho0)) return fail(LB_EINVAL, "rho0 not finite");
     for (int s = 0; s < 4; ++s) {
@@ -375,6 +385,23 @@ lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace
 lb_status lb_step(lb_handle* h, int64_t n) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (n < 0) return fail(LB_EINVAL, "n = %lld < 0", (long long)n);
+    if (h->p.fused_steps == 2) {
+        // finish a pending AA odd step, then two steps per launch, a last single even step if n is odd
+        if (h->parity && n > 0) {
+            hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, true, h->lc, h->t, h->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+            h->t += 1;
+            h->parity = 0;
+            n -= 1;
+        }
+        for (; n >= 2; n -= 2) {
+            hipError_t e = launch_step2(h->p, h->L, h->ws, h->kd, h->kf, h->t, h->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step two-step launch: %s", hipGetErrorString(e));
+            std::swap(h->L.pop_off, h->L.pop2_off);
+            std::swap(h->L.sold_off, h->L.sold2_off);
+            h->t += 2;
+        }
+    }
     for (int64_t s = 0; s < n; ++s) {
         const bool odd = h->parity != 0;
         hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, odd, h->lc, h->t, h->stream);
@@ -555,8 +582,9 @@ lb_status lb_copy_state(lb_handle* dst, lb_handle* src) {
     a.storage = b.storage = 0;
     for (int k = 0; k < LB_MAX_M; ++k) a.phi_ref[k] = b.phi_ref[k] = 0.0;
     a.fp16_scale = b.fp16_scale = a.fp16_scale_h = b.fp16_scale_h = 0.0;
+    a.fused_steps = b.fused_steps = 0;
     if (std::memcmp(&a, &b, sizeof a) != 0)
-        return fail(LB_EINVAL, "lb_copy_state: handles differ in more than storage, phi_ref and scales");
+        return fail(LB_EINVAL, "lb_copy_state: handles differ in more than storage, phi_ref, scales and fused_steps");
     HIPCHK(hipStreamSynchronize(src->stream));
     const int total = 9 + 5 * dst->p.m;
     const int chunk = dst->p.m + 3;
@@ -601,7 +629,7 @@ lb_status lb_free(lb_handle* h) {
 // ============================================================================
 namespace {
 constexpr int kTileCand[][2] = {{32, 4}, {32, 8}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
-constexpr int kStatusRunning = 0, kStatusConverged = 1, kStatusDiverged = 2, kStatusCap = 3;
+constexpr int kStatusRunning = 0, kStatusConverged = 1, kStatusDiverged = 2;
 }  // namespace
 
 struct lbb_handle {
@@ -733,6 +761,7 @@ lb_status lbb_workspace_bytes(const lb_params* params, int32_t count, size_t* by
         if (st != LB_OK) return fail(st, "cavity %d: %s", c, g_err.c_str());
         if (!same_template(params[0], params[c]))
             return fail(LB_EINVAL, "cavity %d: m, model, storage, collision and r_kind must match cavity 0", c);
+        if (params[c].fused_steps == 2) return fail(LB_EINVAL, "cavity %d: the batched sweep takes one step per launch", c);
     }
     *bytes = batch_plan(params, count, nullptr);
     return LB_OK;
@@ -861,9 +890,6 @@ lb_status lbb_run(lbb_handle* b, double tol, int64_t check_every, int64_t max_st
             } else if (k == check_every && r < tol) {
                 b->status[c] = kStatusConverged;
                 changed = true;
-            } else if (done >= max_steps) {
-                b->status[c] = kStatusCap;
-                changed = true;
             }
         }
         if (changed) {
@@ -939,6 +965,41 @@ lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int3
     if (tile_x) *tile_x = best_lc.tile_x;
     if (tile_y) *tile_y = best_lc.tile_y;
     if (us_per_step) *us_per_step = 1e3 * best / trial_steps;
+    return LB_OK;
+}
+
+lb_status lbb_copy_cavity(lbb_handle* dst, int32_t i, lbb_handle* src, int32_t j) {
+    if (!dst || !src || i < 0 || i >= dst->count || j < 0 || j >= src->count)
+        return fail(LB_EINVAL, "bad handle or cavity index");
+    if (dst->cur_parity != 0) return fail(LB_ESTATE, "destination batch is between an even and an odd step");
+    lb_params a = dst->p[i], c = src->p[j];
+    a.storage = c.storage = 0;
+    for (int k = 0; k < LB_MAX_M; ++k) a.phi_ref[k] = c.phi_ref[k] = 0.0;
+    a.fp16_scale = c.fp16_scale = a.fp16_scale_h = c.fp16_scale_h = 0.0;
+    if (std::memcmp(&a, &c, sizeof a) != 0)
+        return fail(LB_EINVAL, "cavities differ in more than storage, phi_ref and scales");
+    HIPCHK(hipStreamSynchronize(src->stream));
+    const int total = 9 + 5 * dst->p[i].m, chunk = dst->p[i].m + 3;
+    double* stage = (double*)(static_cast<char*>(dst->ws) + dst->stage_off);
+    for (int b0 = 0; b0 < total; b0 += chunk) {
+        const int cnt = std::min(chunk, total - b0);
+        hipError_t e = launch_export(src->p[j], src->L[j], src->ws, src->kd[j], src->kf[j], src->parity[j] != 0, b0,
+                                     cnt, stage, dst->stream);
+        if (e == hipSuccess)
+            e = launch_import(dst->p[i], dst->L[i], dst->ws, dst->kd[i], dst->kf[i], b0, cnt, stage, dst->stream);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_copy_cavity: %s", hipGetErrorString(e));
+    }
+    hipError_t e = launch_copy_sold(src->p[j], src->L[j], src->ws, dst->p[i], dst->L[i], dst->ws, dst->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_copy_cavity: %s", hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(dst->stream));
+    dst->steps[i] = src->steps[j];
+    dst->parity[i] = 0;
+    dst->has_snap[i] = 0;
+    if (dst->status[i] != kStatusRunning) {
+        dst->status[i] = kStatusRunning;
+        batch_build_tiles(dst);
+        return batch_upload(dst);
+    }
     return LB_OK;
 }
 

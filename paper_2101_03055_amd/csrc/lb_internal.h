@@ -44,6 +44,7 @@ struct Layout {
     size_t npop;          // population planes, 9 + 5m
     size_t nsrc;          // S_old planes
     size_t pop_off, sold_off, snap_off, stage_off, part_off, res_off, total;
+    size_t pop2_off, sold2_off;  // second population / source arrays (two-step launches only)
 };
 
 constexpr int kRedBlocks = 1024;   // blocks of the first reduction pass (upper bound)
@@ -58,6 +59,10 @@ hipError_t launch_init(const lb_params& p, const Layout& L, void* ws, const KPar
                        const KParams<float>& kf, int has_p0, hipStream_t s);
 hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                        const KParams<float>& kf, bool odd, Launch lc, int64_t step, hipStream_t s);
+// two steps per launch: canonical state of L.pop_off / L.sold_off at t into
+// L.pop2_off / L.sold2_off at t + 2
+hipError_t launch_step2(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                        const KParams<float>& kf, int64_t step, hipStream_t s);
 hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                           const KParams<float>& kf, bool odd, double* phi, double* u, double* pr,
                           hipStream_t s);

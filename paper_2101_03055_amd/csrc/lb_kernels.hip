@@ -58,6 +58,175 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
     scatter<S, M, ODD>(kp, pop, x, y, h, f, salt);
 }
 
+// ---- two steps per launch (temporal blocking through LDS) -----------------
+// Reads the canonical state at t (own slots) of a tile plus a 2-node ring
+// from `src`, collides every node of that region (step 1) into LDS buffer 1,
+// streams inside LDS (with the wall rules) and collides the tile plus a
+// 1-node ring (step 2) into LDS buffer 2, then streams once more and writes
+// the canonical state at t + 2 of the tile to `dst` (own slots).  src/dst and
+// the previous-step source planes are ping-pong pairs: neighbouring
+// workgroups read the ring of this tile from `src` while it is updated.
+// Each state value therefore crosses HBM once per two steps.
+template <int TX, int TY>
+struct Tb2Geom {
+    static constexpr int RX = TX + 4, RY = TY + 4;  // region of step 1 (ring 2)
+    static constexpr int R1X = TX + 2, R1Y = TY + 2;  // region of step 2 (ring 1)
+};
+
+__device__ __forceinline__ bool node_exists(int& gx, int& gy, int nx, int ny, int px, int py) {
+    const bool inx = wrap_in(gx, nx, px), iny = wrap_in(gy, ny, py);
+    return inx && iny;
+}
+
+// Pull of the pre-collision populations of local node (lx, ly) from the
+// post-collision values in an LDS buffer of pitch BX (rows) with origin
+// (ox, oy) relative to the step-1 region; ex(lx, ly) tells whether a local
+// node exists in the domain.  Same wall rules as gather<.., true>.
+template <class T, int M, int NQ, class ExFn>
+__device__ __forceinline__ void lds_pull(const KParams<T>& kp, const T* __restrict__ buf, int BX, int BN, int lx,
+                                         int ly, ExFn&& ex, T h[9], T f[M][5]) {
+    auto at = [&](int q, int x, int y) -> T { return buf[q * BN + y * BX + x]; };
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = lx - CX9[i], sy = ly - CY9[i];
+        int ox, oy;
+        const int e = ex(sx, sy, ox, oy);  // bit 0: exists; ox, oy: side flags
+        T v;
+        if (e) {
+            v = at(i, sx, sy);
+        } else {
+            v = at(OPP9[i], lx, ly);  // bounce-back
+            if ((ox >= 0) != (oy >= 0)) {
+                const int side = ox >= 0 ? ox : oy;
+                if (kp.fbc[side] == LB_BC_FREESLIP) {
+                    int ax, ay;
+                    if (oy >= 0) {
+                        if (ex(lx - CX9[i], ly, ax, ay)) v = at(MIRY9[i], lx - CX9[i], ly);
+                    } else {
+                        if (ex(lx, ly - CY9[i], ax, ay)) v = at(MIRX9[i], lx, ly - CY9[i]);
+                    }
+                }
+            }
+        }
+        h[i] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const int sx = lx - CX5[i], sy = ly - CY5[i];
+            int ox, oy;
+            if (ex(sx, sy, ox, oy)) {
+                f[a][i] = at(9 + 5 * a + i, sx, sy);
+            } else {
+                const int side = ox >= 0 ? ox : oy;
+                T v = at(9 + 5 * a + OPP5[i], lx, ly);
+                if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
+                f[a][i] = v;
+            }
+        }
+}
+
+template <class S, int M, int MODEL, int COLL, int TX, int TY>
+__global__ __launch_bounds__(256) void k_step2(KParams<typename St<S>::T> kp, const S* __restrict__ src,
+                                               S* __restrict__ dst, const typename St<S>::T* __restrict__ sold_src,
+                                               typename St<S>::T* __restrict__ sold_dst, int tiles_x,
+                                               uint32_t salt) {
+    using T = typename St<S>::T;
+    using G = Tb2Geom<TX, TY>;
+    constexpr int NQ = 9 + 5 * M;
+    constexpr int N1 = G::RX * G::RY, N2 = G::R1X * G::R1Y;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T* buf1 = reinterpret_cast<T*>(smem);    // [NQ][RY][RX] post-collision, step 1
+    T* buf2 = buf1 + NQ * N1;                 // [NQ][R1Y][R1X] post-collision, step 2
+    T* sb = buf2 + NQ * N2;                   // [M][RY][RX] source after step 1 / [M][R1Y][R1X] after step 2
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = b % tiles_x, by = b / tiles_x;
+    const int x0 = bx * TX - 2, y0 = by * TY - 2;  // global origin of the step-1 region
+    const int nx = kp.nx, ny = kp.ny;
+    const long long N = (long long)nx * ny, P = kp.plane;
+    // existence of a step-1-region node, with the side it lies beyond on each axis (-1: inside/periodic)
+    auto ex1 = [&](int lx, int ly, int& ox, int& oy) -> int {
+        int gx = x0 + lx, gy = y0 + ly;
+        const bool inx = wrap_in(gx, nx, kp.px), iny = wrap_in(gy, ny, kp.py);
+        ox = inx ? -1 : side_x(gx);
+        oy = iny ? -1 : side_y(gy);
+        return inx & iny;
+    };
+
+    // phase A: load + collide (step 1) on the ring-2 region
+    for (int r = threadIdx.x; r < N1; r += blockDim.x) {
+        const int lx = r % G::RX, ly = r / G::RX;
+        int gx = x0 + lx, gy = y0 + ly;
+        if (!node_exists(gx, gy, nx, ny, kp.px, kp.py)) continue;
+        const long long n = (long long)gy * nx + gx;
+        T h[9], f[M][5], So[M], Sn[M];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = ld(src + i * P + n, kp, true);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) f[a][i] = ld(src + (9 + 5 * a + i) * P + n, kp, false);
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            So[a] = T(0);
+            if (kp.src_mask >> a & 1) So[a] = sold_src[(long long)(k++) * N + n];
+        }
+        collide<T, M, MODEL, COLL>(kp, h, f, So, Sn);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) buf1[i * N1 + r] = h[i];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) buf1[(9 + 5 * a + i) * N1 + r] = f[a][i];
+            sb[a * N1 + r] = Sn[a];
+        }
+    }
+    __syncthreads();
+    // phase B: stream (in LDS) + collide (step 2) on the ring-1 region
+    T* sb2 = sb + M * N1;
+    for (int r = threadIdx.x; r < N2; r += blockDim.x) {
+        const int lx = 1 + r % G::R1X, ly = 1 + r / G::R1X;
+        int ox, oy;
+        if (!ex1(lx, ly, ox, oy)) continue;
+        T h[9], f[M][5], So[M], Sn[M];
+        lds_pull<T, M, NQ>(kp, buf1, G::RX, N1, lx, ly, ex1, h, f);
+#pragma unroll
+        for (int a = 0; a < M; ++a) So[a] = sb[a * N1 + ly * G::RX + lx];
+        collide<T, M, MODEL, COLL>(kp, h, f, So, Sn);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) buf2[i * N2 + r] = h[i];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) buf2[(9 + 5 * a + i) * N2 + r] = f[a][i];
+            sb2[a * N2 + r] = Sn[a];
+        }
+    }
+    __syncthreads();
+    // phase C: stream (in LDS) into the tile and write the canonical state at t + 2
+    auto ex2 = [&](int lx, int ly, int& ox, int& oy) -> int { return ex1(lx + 1, ly + 1, ox, oy); };
+    for (int r = threadIdx.x; r < TX * TY; r += blockDim.x) {
+        const int tx = r % TX, ty = r / TX;
+        const int gx = x0 + 2 + tx, gy = y0 + 2 + ty;
+        if (gx >= nx || gy >= ny) continue;
+        const long long n = (long long)gy * nx + gx;
+        T h[9], f[M][5];
+        lds_pull<T, M, NQ>(kp, buf2, G::R1X, N2, tx + 1, ty + 1, ex2, h, f);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st(dst, i * P + n, h[i], kp, true, salt);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) st(dst, (9 + 5 * a + i) * P + n, f[a][i], kp, false, salt);
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (kp.src_mask >> a & 1) sold_dst[(long long)(k++) * N + n] = sb2[a * N2 + (ty + 1) * G::R1X + tx + 1];
+    }
+}
+
 // initial state: f = f^eq(phi0, u0), h = h^eq(p0, u0), S_old = S(phi0)
 template <class S, int M, int MODEL>
 __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* __restrict__ pop,
@@ -86,11 +255,19 @@ __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* 
         st(pop, (9 + 5 * a + 4) * P + n, iso - adv * u[1], kp, false, salt);
         st(pop, (9 + 5 * a + 0) * P + n, phid - T(4) * iso, kp, false, salt);
     }
-    const T usq = u[0] * u[0] + u[1] * u[1];
+    // fluid equilibrium at the momentum c_i h_i = u0 - F(phi0)/2 so that the
+    // velocity of Eq. sum-u equals the prescribed u0 at t = 0
+    T j[2] = {u[0] - T(0.5) * kp.F0[0], u[1] - T(0.5) * kp.F0[1]};
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        j[0] -= T(0.5) * kp.Fphi[a][0] * phi[a];
+        j[1] -= T(0.5) * kp.Fphi[a][1] * phi[a];
+    }
+    const T usq = j[0] * j[0] + j[1] * j[1];
     T hsum = T(0);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-        const T cu = T(CX9[i]) * u[0] + T(CY9[i]) * u[1];
+        const T cu = T(CX9[i]) * j[0] + T(CY9[i]) * j[1];
         const T v = w9<T>(i) * (T(3) * p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
         hsum += v;
         st(pop, i * P + n, v, kp, true, salt);
@@ -298,6 +475,38 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
                                    lc.tile_x, lc.tile_y, tiles_x, salt);
         }
         return hipGetLastError();
+    });
+}
+
+template <class S, int M, int MODEL, int COLL, int TX, int TY>
+static hipError_t launch_step2_t(const KParams<typename St<S>::T>& kp, const Layout& L, void* ws, uint32_t salt,
+                                 hipStream_t s) {
+    using T = typename St<S>::T;
+    using G = Tb2Geom<TX, TY>;
+    const size_t lds = sizeof(T) * (9 + 5 * M + M) * (G::RX * G::RY + G::R1X * G::R1Y);
+    auto kern = k_step2<S, M, MODEL, COLL, TX, TY>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int tiles_x = (kp.nx + TX - 1) / TX, tiles_y = (kp.ny + TY - 1) / TY;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles_x * tiles_y)), dim3(256), lds, s, kp,
+                       (const S*)at(ws, L.pop_off), (S*)at(ws, L.pop2_off), (const T*)at(ws, L.sold_off),
+                       (T*)at(ws, L.sold2_off), tiles_x, salt);
+    return hipGetLastError();
+}
+
+hipError_t launch_step2(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                        const KParams<float>& kf, int64_t step, hipStream_t s) {
+    const uint32_t salt = mix32((uint32_t)step ^ (uint32_t)(step >> 32) * 0x632be5abu ^ 0x2b2b2b2bu);
+    return dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
+        const auto& kp = kpar<S>(kd, kf);
+        if constexpr (std::is_same<S, double>::value) {
+            if (p.collision == LB_COLL_MRT) return launch_step2_t<S, M, MODEL, LB_COLL_MRT, 32, 4>(kp, L, ws, salt, s);
+            return launch_step2_t<S, M, MODEL, LB_COLL_BGK, 32, 4>(kp, L, ws, salt, s);
+        } else {
+            if (p.collision == LB_COLL_MRT) return launch_step2_t<S, M, MODEL, LB_COLL_MRT, 64, 4>(kp, L, ws, salt, s);
+            return launch_step2_t<S, M, MODEL, LB_COLL_BGK, 64, 4>(kp, L, ws, salt, s);
+        }
     });
 }
 

@@ -313,6 +313,30 @@ __global__ __launch_bounds__(256) void k_unpack_out(const float* __restrict__ Z,
     for (int c = 0; c < SG_OUTPUTS; ++c) out[((long long)b * SG_OUTPUTS + c) * H * W + pix] = Z[p * Co + c];
 }
 
+// separable [1 2 1]/4 filter per plane, edge values replicated; it removes
+// the grid-scale (Nyquist) content of a prediction exactly
+__global__ __launch_bounds__(256) void k_smooth(const float* __restrict__ in, float* __restrict__ out,
+                                                long long planes, int H, int W) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= planes * H * W) return;
+    const long long pl = k / ((long long)H * W);
+    const int rem = (int)(k % ((long long)H * W));
+    const int y = rem / W, x = rem % W;
+    const float* q = in + pl * H * W;
+    const float wt[3] = {0.25f, 0.5f, 0.25f};
+    float s = 0.f;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int yy = min(max(y + dy, 0), H - 1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = min(max(x + dx, 0), W - 1);
+            s += wt[dy + 1] * wt[dx + 1] * q[yy * W + xx];
+        }
+    }
+    out[k] = s;
+}
+
 }  // namespace sgk
 
 // ============================================================================
@@ -667,6 +691,18 @@ lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out) {
         const uint32_t bits = (uint32_t)tmp[k] << 16;
         std::memcpy(&host_out[k], &bits, 4);
     }
+    return LB_OK;
+}
+
+lb_status sg_smooth(const float* d_in, float* d_out, int32_t planes, int32_t height, int32_t width,
+                    void* hip_stream) {
+    if (!d_in || !d_out || d_in == d_out || planes < 0 || height < 1 || width < 1)
+        return sgfail(LB_EINVAL, "bad argument (the filter is not in place)");
+    const long long n = (long long)planes * height * width;
+    if (n == 0) return LB_OK;
+    hipLaunchKernelGGL(k_smooth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       d_in, d_out, (long long)planes, height, width);
+    SGCHK(hipGetLastError());
     return LB_OK;
 }
 

@@ -40,7 +40,7 @@ class lb_params(C.Structure):
         ("storage", C.c_int32), ("collision", C.c_int32), ("r_kind", C.c_int32),
         ("fluid_bc", C.c_int32 * 4),
         ("scalar_bc", (C.c_int32 * MAXM) * 4),
-        ("reserved", C.c_int32),
+        ("fused_steps", C.c_int32),
         ("tau_f", C.c_double), ("rho0", C.c_double),
         ("mrt_s", C.c_double * 9),
         ("D", C.c_double * (MAXM * MAXM)),
@@ -98,6 +98,7 @@ def lib():
             "lbb_run": [vp, C.c_double, i64, i64, vp, vp, vp],
             "lbb_moments": [vp, C.c_int32, vp, vp, vp],
             "lbb_time": [vp, C.c_int32, C.POINTER(i64), C.POINTER(C.c_int32)],
+            "lbb_copy_cavity": [vp, C.c_int32, vp, C.c_int32],
             "lbb_set_tile": [vp, C.c_int32, C.c_int32],
             "lbb_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
             "lbb_free": [vp],
@@ -120,7 +121,7 @@ def _check(status):
 
 
 def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scale: float = 1.0,
-                         fp16_scale_h: float | None = None) -> lb_params:
+                         fp16_scale_h: float | None = None, fused_steps: int = 0) -> lb_params:
     """Fill the C record from a workload dict (see ``workloads``)."""
     p = lb_params()
     m = wl["m"]
@@ -160,6 +161,7 @@ def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scal
             p.phi_ref[a] = float(phi_ref[a])
     p.fp16_scale = fp16_scale
     p.fp16_scale_h = fp16_scale if fp16_scale_h is None else fp16_scale_h
+    p.fused_steps = int(fused_steps)
     return p
 
 
@@ -276,13 +278,13 @@ class Solver:
 
     def __init__(self, wl: dict, phi0, u0, p0=None, storage: str = "f64", phi_ref=None,
                  fp16_scale: float = 1.0, fp16_scale_h: float | None = None, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, fused_steps: int = 0):
         import torch
 
         lib()
         self.wl = wl
         self.m, self.ny, self.nx = wl["m"], wl["ny"], wl["nx"]
-        self.params = params_from_workload(wl, storage, phi_ref, fp16_scale, fp16_scale_h)
+        self.params = params_from_workload(wl, storage, phi_ref, fp16_scale, fp16_scale_h, fused_steps)
         nbytes = lb_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
@@ -324,7 +326,7 @@ class Solver:
 
 
 # ---- batched sweep -------------------------------------------------------------
-LBB_RUNNING, LBB_CONVERGED, LBB_DIVERGED, LBB_CAP = 0, 1, 2, 3
+LBB_RUNNING, LBB_CONVERGED, LBB_DIVERGED = 0, 1, 2
 
 
 def _params_array(plist):
@@ -393,6 +395,10 @@ def lbb_time(b, i: int):
     st = C.c_int32()
     _check(lib().lbb_time(b, int(i), C.byref(s), C.byref(st)))
     return s.value, st.value
+
+
+def lbb_copy_cavity(dst, i: int, src, j: int):
+    _check(lib().lbb_copy_cavity(dst, int(i), src, int(j)))
 
 
 def lbb_set_tile(b, tile_x: int, tile_y: int):

@@ -39,6 +39,7 @@ def lib():
             "sg_layer_output": [vp, i32, vp],
             "sg_layer_input": [vp, i32, vp],
             "sg_free": [vp],
+            "sg_smooth": [vp, vp, i32, i32, i32, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -93,6 +94,17 @@ def init_weights(seed: int = 0, gain: float = 1.0):
         vec[off:off + co * 9 * ci] = w.ravel()
         off += co * 9 * ci + co
     return vec
+
+
+def smooth(d_in, d_out, stream=None):
+    """[1 2 1] x [1 2 1] filter of every [..., H, W] plane of a CUDA float32 tensor."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(d_in.device)
+    H, W = d_in.shape[-2], d_in.shape[-1]
+    planes = d_in.numel() // (H * W)
+    _check(lib().sg_smooth(C.c_void_p(d_in.data_ptr()), C.c_void_p(d_out.data_ptr()), planes, H, W,
+                           C.c_void_p(s.cuda_stream)))
 
 
 class Surrogate:

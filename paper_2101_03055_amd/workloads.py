@@ -24,15 +24,24 @@ import math
 
 import numpy as np
 
-# MRT rates for the non-hydrodynamic moments (e, eps, q) used by default;
-# the stress rates are overwritten by 1/tau_f, the conserved ones are inert.
-MRT_DEFAULT = [1.0, 1.4, 1.4, 1.0, 1.2, 1.0, 1.2, 1.0, 1.0]
+def mrt_rates(tau_f, magic=3.0 / 16.0):
+    """MRT rates tied to the viscous rate w = 1/tau_f.  The pressure scheme of
+    the incompressible model (appendix A) rests on the BGK relaxation of the
+    rest population h_0, which is made of the rho, e and eps moments only: they
+    relax at w (as do the stress moments); the energy-flux moments q (zero on
+    h_0) relax at the rate fixing (1/w - 1/2)(1/s_q - 1/2) = magic (3/16 makes
+    half-way bounce-back exact for Poiseuille flow); j rates do not enter.
+    Rates of rho, e or eps other than w (e.g. Lallemand & Luo's fixed 1.64,
+    1.54, 1.9, or rho = 1) diverged in heated cavities and Taylor-Green flow."""
+    w = 1.0 / tau_f
+    sq = 1.0 / (magic / (1.0 / w - 0.5) + 0.5)
+    return [w, w, w, 1.0, sq, 1.0, sq, w, w]
 
 
 def _base(nx, ny, m, tau_f, D, **kw):
     wl = {
         "nx": int(nx), "ny": int(ny), "m": int(m), "model": "linear", "collision": "bgk",
-        "r_kind": "step", "tau_f": float(tau_f), "rho0": 1.0, "mrt_s": list(MRT_DEFAULT),
+        "r_kind": "step", "tau_f": float(tau_f), "rho0": 1.0, "mrt_s": mrt_rates(tau_f),
         "D": np.asarray(D, dtype=np.float64).reshape(m, m).tolist(),
         "K": np.zeros((m, m)).tolist(), "F0": [0.0, 0.0], "Fphi": np.zeros((m, 2)).tolist(),
         "chi": 0.0, "beta": 0.0, "cstar": 0.3, "eps": 0.0,
@@ -217,3 +226,25 @@ def random_case(nx, ny, m=2, seed=0, fluid_bc=None, scalar_bc=None, model="linea
     p0 = 1e-3 * rng.standard_normal(size=(ny, nx))
     wl["name"] = f"random_{nx}x{ny}_s{seed}"
     return wl, phi0, u0, p0
+
+
+# ---------------------------------------------------------------------------
+# Surrogate data: one seed per cavity, the sweep's parameter law
+# ---------------------------------------------------------------------------
+def sweep_case(seed, L=128):
+    """Parameters of one cavity drawn with its own seed (sweep law, fixed L)."""
+    d = sweep_params(1, seed=seed, sizes=[L])[0]
+    d["seed"] = int(seed)
+    return d
+
+
+def normalise(pd):
+    """The surrogate's five inputs in [0, 1]: log10 Ra, Le, Nc, Sr, Df over the law's ranges."""
+    return [(np.log10(pd["Ra"]) - 3.0) / 3.0, (pd["Le"] - 1.0) / 4.0, (pd["Nc"] + 2.0) / 4.0,
+            pd["Sr"] / 0.5, pd["Df"] / 0.5]
+
+
+def ddc_case(pd, collision="bgk", u_lat=0.1):
+    """Cavity workload (record, cold initial fields) for one parameter draw."""
+    return ddc(pd["L"], Ra=pd["Ra"], Pr=pd.get("Pr", 0.71), Le=pd["Le"], Nc=pd["Nc"], Sr=pd["Sr"], Df=pd["Df"],
+               u_lat=u_lat, collision=collision)

@@ -55,7 +55,7 @@ def test_workspace_bytes_scales_with_storage():
     (lambda p: p.D.__setitem__(0, -0.01), lb.LB_EINVAL),        # eigenvalue with negative real part
     (lambda p: p.fluid_bc.__setitem__(0, 1), lb.LB_EINVAL),     # half a periodic pair
     (lambda p: setattr(p, "storage", 7), lb.LB_EINVAL),
-    (lambda p: setattr(p, "reserved", 1), lb.LB_EINVAL),
+    (lambda p: setattr(p, "fused_steps", 3), lb.LB_EINVAL),
 ])
 def test_validation_rejects(mutate, status):
     wl, *_ = W.taylor_green_blobs()

@@ -114,3 +114,36 @@ def test_autotune_picks_a_supported_tile_and_keeps_results():
         want = single(c, taken + 6)
         for g, w in zip(got, want):
             assert np.array_equal(g, w), i
+
+
+def test_copy_cavity_between_batches():
+    """FP32 batch -> FP64 batch (exact widening), then both continue like a
+    single-domain FP64 run started from the copied state."""
+    cases = mixed_cases()[:3]
+    a = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
+    a.step(21)  # odd: the source cavities are in the even-step layout
+    b = lb.Batch(cases, storage="f64")
+    for i in range(3):
+        lb.lbb_copy_cavity(b.handle, i, a.handle, i)
+    for i in range(3):
+        assert b.time(i)[0] == 21
+        ga, gb = a.moments(i), b.moments(i)
+        for x, y in zip(ga[:2], gb[:2]):
+            assert np.abs(x - y).max() <= 1e-6 * max(1.0, np.abs(y).max())
+    # the copied FP64 cavity evolves exactly like a single FP64 run loaded with the same populations
+    s = lb.Solver(*cases[1], storage="f64")
+    sa = lb.Solver(*cases[1], storage="f32", phi_ref=[0.5, 0.5])
+    sa.step(21)
+    lb.lb_copy_state(s.handle, sa.handle)
+    b.step(10)
+    s.step(10)
+    for x, y in zip(b.moments(1), s.moments()):
+        assert np.array_equal(x, y)
+
+
+def test_copy_cavity_rejects_mismatched_parameters():
+    cases = mixed_cases()
+    a = lb.Batch(cases[:2])
+    b = lb.Batch(cases[:2])
+    with pytest.raises(lb.LBError):
+        lb.lbb_copy_cavity(b.handle, 0, a.handle, 1)

@@ -97,8 +97,8 @@ def test_relaxation_matrix_reproduces_D(oracle_mod):
 
 
 def _recovery_err(O, mutation=0):
-    """Initialise at equilibrium of (phi0, u0, p0) and read the fields back:
-    Eq. sum-phi gives phi0 and Eq. sum-u gives u0 + F/2; with F = 0 the
+    """Initialise at equilibrium (fluid momentum u0 - F/2) and read the fields
+    back: Eq. sum-phi gives phi0 and Eq. sum-u gives u0; with F = 0 the
     pressure scheme of appendix A gives p0 back exactly."""
     rng = np.random.default_rng(14)
     n = 6
@@ -110,8 +110,7 @@ def _recovery_err(O, mutation=0):
         p0 = rng.uniform(-1e-3, 1e-3, (n, n))
         o = O.Oracle(wl, phi0, u0, p0, mutation=mutation)
         phi, u, p = o.moments()
-        F = np.array(F0)[:, None, None]
-        err = max(err, np.abs(phi - phi0).max(), np.abs(u - (u0 + F / 2)).max())
+        err = max(err, np.abs(phi - phi0).max(), np.abs(u - u0).max())
         if F0[0] == 0.0:
             err = max(err, np.abs(p - p0).max())
     return err
@@ -188,10 +187,12 @@ def test_uniform_reaction_ab2(oracle_mod):
 
 
 def _centroid_err(O, mutation=0):
-    """Uniform force F, periodic: u(t) = F/2 + F t exactly, and with the
-    auxiliary source G (Eq. Gi) the first moment of each species satisfies
-    J(t) = Phi F t, so the centroid moves by F t/2 + F t^2/2 exactly."""
-    n, steps = 160, 300
+    """Uniform force F, periodic, u0 = 0: the fluid velocity is u(t) = F t
+    exactly.  With the auxiliary source G (Eq. Gi) each species' first moment
+    obeys J(t) = Phi (F t - F/2) + (I - omega)^t Phi F/2, so once the
+    transient has decayed the centroid moves by F (t2^2 - t1^2)/2 between
+    t1 and t2 (without G the drift lags)."""
+    n, t1, t2 = 160, 150, 300
     wl = W._base(n, n, 2, 0.8, [[0.15, 0.03], [0.02, 0.1]])
     F = np.array([2e-5, 1e-5])
     wl["F0"] = F.tolist()
@@ -200,15 +201,21 @@ def _centroid_err(O, mutation=0):
     phi0 = np.stack([1 + np.exp(-((X - c) ** 2 + (Y - c) ** 2) / 50.0),
                      1 + 0.5 * np.exp(-((X - c - 3) ** 2 + (Y - c + 2) ** 2) / 72.0)])
     o = O.Oracle(wl, phi0, np.zeros((2, n, n)), mutation=mutation)
-    o.step(steps)
-    phi, u, _ = o.moments()
-    err = np.abs(u - (F / 2 + F * steps)[:, None, None]).max()
-    for a in range(2):
-        w0, w = phi0[a] - 1, phi[a] - 1
-        c0 = np.array([(X * w0).sum(), (Y * w0).sum()]) / w0.sum()
-        c1 = np.array([(X * w).sum(), (Y * w).sum()]) / w.sum()
-        err = max(err, np.abs(c1 - (c0 + F * steps / 2 + F * steps ** 2 / 2)).max())
-    return err
+
+    def centroids():
+        phi, u, _ = o.moments()
+        out = []
+        for a in range(2):
+            w = phi[a] - 1
+            out.append(np.array([(X * w).sum(), (Y * w).sum()]) / w.sum())
+        return np.array(out), u
+
+    o.step(t1)
+    c1, u1 = centroids()
+    o.step(t2 - t1)
+    c2, u2 = centroids()
+    err = max(np.abs(u1 - (F * t1)[:, None, None]).max(), np.abs(u2 - (F * t2)[:, None, None]).max())
+    return max(err, np.abs(c2 - c1 - F * (t2 ** 2 - t1 ** 2) / 2).max())
 
 
 def test_uniform_force_centroid(oracle_mod):
@@ -267,8 +274,8 @@ def test_half_channel_freeslip_exact(oracle_mod):
 
 
 def _plug_err(O, mutation=0):
-    """Free-slip walls at both y sides, periodic x, force along x: no shear
-    develops, the flow stays uniform with u(t) = F/2 + F t."""
+    """Free-slip walls at both y sides, periodic x, force along x, u0 = 0: no
+    shear develops, the flow stays uniform with u(t) = F t."""
     nx, ny, g, steps = 3, 8, 1e-5, 500
     wl = W._base(nx, ny, 1, 0.7, [[0.1]], F0=[g, 0.0])
     wl["fluid_bc"] = ["periodic", "periodic", "freeslip", "freeslip"]
@@ -276,7 +283,7 @@ def _plug_err(O, mutation=0):
     o = O.Oracle(wl, np.ones((1, ny, nx)), np.zeros((2, ny, nx)), mutation=mutation)
     o.step(steps)
     _, u, _ = o.moments()
-    return max(np.abs(u[0] - (g / 2 + g * steps)).max() / (g * steps), np.abs(u[1]).max())
+    return max(np.abs(u[0] - g * steps).max() / (g * steps), np.abs(u[1]).max())
 
 
 def test_freeslip_plug_flow(oracle_mod):
@@ -362,6 +369,23 @@ def test_mrt_basis_orthogonal(oracle_mod):
     assert np.allclose(G, np.diag(np.diag(G)))
     assert np.allclose(np.diag(G), [9, 36, 36, 6, 12, 6, 12, 4, 4])
     assert np.allclose(M @ Mi, np.eye(9), atol=1e-14)
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.3])
+def test_mrt_poiseuille_exact_any_tau(oracle_mod, tau):
+    """With the energy-flux rate fixed by (1/w - 1/2)(1/s_q - 1/2) = 3/16 the
+    two-relaxation-time family reproduces body-force Poiseuille flow exactly
+    under half-way bounce-back for every tau (Ginzburg's magic parameter)."""
+    nx, ny, g = 2, 16, 1e-6
+    wl = W._base(nx, ny, 1, tau, [[0.1]], F0=[g, 0.0], collision="mrt")
+    wl["fluid_bc"] = ["periodic", "periodic", "noslip", "noslip"]
+    wl["scalar_bc"] = [["periodic"]] * 2 + [["noflux"]] * 2
+    o = oracle_mod.Oracle(wl, np.ones((1, ny, nx)), np.zeros((2, ny, nx)))
+    o.step(40000)
+    _, u, _ = o.moments()
+    y = np.arange(ny) + 0.5
+    exact = g / (2 * (tau - 0.5) / 3.0) * y * (ny - y)
+    assert np.abs(u[0, :, 0] - exact).max() / exact.max() < 1e-12
 
 
 def test_mrt_taylor_green_viscosity(oracle_mod):
