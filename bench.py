@@ -1,6 +1,6 @@
 """Throughput of the fused collide-stream step on one MI355X.
 
-Workload (default): the chemotaxis-fluid plume, 512 x 256 nodes, m = 2
+Workload (headline): the chemotaxis-fluid plume, 512 x 256 nodes, m = 2
 (bacteria n, oxygen c) on D2Q5 + the D2Q9 fluid, step cut-off r(c), oxygen
 consumption source, buoyancy, free-slip/Dirichlet top, no-slip/no-flux
 bottom, periodic sides; populations stored as FP32 deviations and collided in
@@ -8,11 +8,21 @@ FP32.  One step = one lattice update of every node (the full fused update);
 the FP64 steady-state residual is evaluated every 1000 steps inside the timed
 region, as a steady solve does.  Inputs are resident in HBM before timing.
 
-Prints one JSON line (rank 0).  Extra objects: ``roofline`` (algorithmic bytes
-of the step kernel / its mean duration, against the HBM peak), ``cpu_baseline``
-(the CPU oracle on a bounded sample of the same workload), ``fp64`` (same
-workload with FP64 storage) and ``hbm_sweep`` (a periodic grid large enough to
-leave the caches, where the HBM fraction is meaningful).
+Prints one JSON line.  Besides the contract's fields:
+  roofline       algorithmic bytes of the step kernel per launch / its mean
+                 duration (HIP events on the solver's stream, back-to-back
+                 launches) against the HBM peak; `traffic` from rocprofv3
+                 FETCH_SIZE/WRITE_SIZE (profiles/*.traffic.json) while the kernel
+                 sources are unchanged, else null;
+  cpu_baseline   the FP64 CPU oracle on a bounded sample of the same workload;
+  fp64           the same workload with FP64 storage;
+  hbm_sweep      periodic 4096^2 grids (FP64/FP32/FP16 storage): working sets
+                 well beyond the caches, where the HBM fraction is meaningful;
+  batched_sweep  256 double-diffusive cavities of uneven size (64..256) in one
+                 launch per step (FP32, autotuned tile);
+  steady_warm_vs_cold  double-diffusive cavities at 128^2 solved to residual
+                 1e-8 (batched FP32 phase + FP64 finish) from rest and from the
+                 CNN surrogate's prediction (weights from the surrogate study).
 """
 from __future__ import annotations
 
@@ -29,6 +39,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS (fluid+m scalars) & HBM GB/s vs peak; wall time to steady: warm vs cold"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_chemotaxis_plume_512x256_f32.traffic.json")
+WEIGHTS = os.path.join(ROOT, "paper_2101_03055_amd", "data", "surrogate_ddc128.npz")
 
 
 def bytes_per_lu(m: int, storage: str, n_src: int) -> int:
@@ -52,7 +64,6 @@ def time_steps(solver, steps, warmup, residual_every=1000):
     e1 = torch.cuda.Event(enable_timing=True)
     done = 0
     n_res = 0
-    t0 = time.perf_counter()
     e0.record(stream)
     while done < steps:
         k = min(residual_every, steps - done)
@@ -63,21 +74,20 @@ def time_steps(solver, steps, warmup, residual_every=1000):
             n_res += 1
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3, wall, n_res
+    return e0.elapsed_time(e1) / 1e3, n_res
 
 
-def kernel_time(solver, launches):
-    """Mean duration of one step launch, HIP events on the solver's stream,
-    back-to-back launches (no host synchronisation in between)."""
+def kernel_time(step_fn, stream, launches):
+    """Mean duration of one step launch: HIP events on the launching stream
+    around back-to-back launches (no host synchronisation in between)."""
     import torch
 
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(solver.stream)
-    solver.step(launches)
-    e1.record(solver.stream)
+    e0.record(stream)
+    step_fn(launches)
+    e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / launches
 
@@ -94,8 +104,83 @@ def cpu_baseline(wl, phi0, u0, p0, budget_s=12.0):
     o.step(steps)
     el = time.perf_counter() - t0
     lu = wl["nx"] * wl["ny"] * steps
-    return {"value": lu / el / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+    return {"value": round(lu / el / 1e6, 2), "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
             "sample": f"{wl['name']}, FP64 oracle, {steps} steps from the same initial state ({el:.1f} s)"}
+
+
+def traffic_record():
+    """Counter-measured bytes per launch, if they describe the current kernel sources."""
+    try:
+        from paper_2101_03055_amd import profsum
+
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        if rec.get("source_hash") == profsum.source_hash():
+            return rec
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def hbm_sweep(W, lb, torch):
+    out = {}
+    for storage in ("f64", "f32", "f16"):
+        n = 4096
+        wlb, pb, ub, ppb = W.taylor_green_blobs(n=n, steps=0)
+        sb = lb.Solver(wlb, pb, ub, ppb, storage=storage, phi_ref=[1.0, 1.0], fp16_scale=1e3, fp16_scale_h=1e4)
+        sb.step(20)
+        kt = kernel_time(sb.step, sb.stream, 100)
+        bb = bytes_per_lu(2, storage, 0)
+        ach = bb * n * n / kt / 1e9
+        out[f"{storage}_{n}x{n}"] = {"MLUPS": round(n * n / kt / 1e6, 1), "achieved_GBs": round(ach, 1),
+                                     "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2),
+                                     "bytes_per_lu": bb}
+        del sb
+        torch.cuda.empty_cache()
+    return out
+
+
+def batched_sweep(W, lb, torch):
+    pds = W.sweep_params(256, seed=4)
+    cases = [W.ddc_case(pd) for pd in pds]
+    nodes = sum(c[0]["nx"] * c[0]["ny"] for c in cases)
+    b = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
+    tx, ty, us = b.autotune(10)
+    kt = kernel_time(b.step, b.stream, 200)
+    bb = bytes_per_lu(2, "f32", 0)
+    ach = bb * nodes / kt / 1e9
+    return {"cavities": len(cases), "nodes": nodes, "state_MB": round(nodes * 19 * 4 / 1e6, 1),
+            "tile": [tx, ty], "MLUPS": round(nodes / kt / 1e6, 1), "achieved_GBs": round(ach, 1),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2)}
+
+
+def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000):
+    """Warm vs cold steady solves (batched FP32 phase + FP64 finish to 1e-8)."""
+    from paper_2101_03055_amd import sg, surrogate_study as SS
+
+    if not os.path.exists(WEIGHTS):
+        return None
+    net = sg.Surrogate(16, 128, 128)
+    net.set_weights(np.load(WEIGHTS)["w"])
+    seeds = list(range(20000, 20000 + n_cases))
+    pds = [W.sweep_case(s, 128) for s in seeds]
+    cases = [W.ddc_case(pd) for pd in pds]
+    params = np.array([W.normalise(pd) for pd in pds], dtype=np.float32)
+    quiet = lambda s: None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = SS.predict(net, params)
+    t_pred = time.perf_counter() - t0
+    warm, fw = SS.solve_path(cases, pred, max_steps=max_steps, label="warm", log=quiet)
+    cold, fc = SS.solve_path(cases, None, max_steps=max_steps, label="cold", log=quiet)
+    ok = [i for i in range(n_cases) if warm["status"][i] == 1 and cold["status"][i] == 1]
+    return {"cases": n_cases, "L": 128, "converged_both": len(ok), "tol": 1e-8,
+            "wall_s_warm": round(warm["seconds"] + t_pred, 2), "wall_s_cold": round(cold["seconds"], 2),
+            "speedup": round(cold["seconds"] / (warm["seconds"] + t_pred), 3),
+            "steps_warm_median": float(np.median([warm["steps_total"][i] for i in ok])) if ok else None,
+            "steps_cold_median": float(np.median([cold["steps_total"][i] for i in ok])) if ok else None,
+            "warm_relL2_vs_cold_max": max((SS.rel_l2(fw[i], fc[i]) for i in ok), default=None),
+            "note": "cases that do not become steady within the cap (e.g. Nc near -1) count in both wall times"}
 
 
 def main():
@@ -128,57 +213,47 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 5}), flush=True)
         return
     wl, phi0, u0, p0 = W.chemotaxis_plume()
+    N = wl["nx"] * wl["ny"]
+    bpl = bytes_per_lu(2, "f32", 1)
     if args.mode == "pmc":
         solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
         solver.step(200)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_steps": 200, "bytes_per_launch": bytes_per_lu(2, "f32", 1) * wl["nx"] * wl["ny"]}),
-              flush=True)
+        print(json.dumps({"pmc_steps": 200, "bytes_per_launch": bpl * N}), flush=True)
         return
-    N = wl["nx"] * wl["ny"]
+
     solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
-    n_src = 1
-    el, wall, n_res = time_steps(solver, args.steps, args.warmup)
+    el, n_res = time_steps(solver, args.steps, args.warmup)
     mlups = N * args.steps / el / 1e6
-    kt = kernel_time(solver, 1000)
-    bpl = bytes_per_lu(2, "f32", n_src)
+    kt = kernel_time(solver.step, solver.stream, 1000)
     achieved = bpl * N / kt / 1e9
+    tr = traffic_record()
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded PCG64 noise on n0, paper's plume parameters)",
+        "data": "synthetic (seeded PCG64 noise on n0; the paper's plume parameters)",
         "config": {"workload": wl["name"], "nx": wl["nx"], "ny": wl["ny"], "m": 2,
-                   "storage": "f32 deviations from phi_ref = (1, 1), rho0", "collision": "bgk",
+                   "storage": "f32 deviations from phi_ref = (1, 1) and rho0", "collision": "bgk",
                    "residual_every": 1000, "residual_evals_timed": n_res},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step (even/odd AA launches alternate)",
-                     "bytes_per_launch": bpl * N, "mean_launch_us": kt * 1e6,
-                     "note": "working set 21 MB: resident in the 256 MB MALL, so achieved may exceed what HBM alone would give"},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(tr["traffic_bytes_per_launch"]) if tr else None,
+                     "kernel": "k_step (even/odd AA-pattern launches alternate)",
+                     "bytes_per_launch": bpl * N, "mean_launch_us": round(kt * 1e6, 3),
+                     "note": "21 MB working set: resident in the 256 MB MALL; hbm_sweep gives the HBM-bound case"},
     }
     if not args.no_extra:
         s64 = lb.Solver(wl, phi0, u0, p0, storage="f64")
-        el64, _, _ = time_steps(s64, 2000, 100)
-        kt64 = kernel_time(s64, 500)
-        out["fp64"] = {"value": round(N * 2000 / el64 / 1e6, 1), "unit": "MLUPS",
-                       "mean_launch_us": kt64 * 1e6,
+        el64, _ = time_steps(s64, 2000, 100)
+        kt64 = kernel_time(s64.step, s64.stream, 500)
+        out["fp64"] = {"value": round(N * 2000 / el64 / 1e6, 1), "unit": "MLUPS", "mean_launch_us": round(kt64 * 1e6, 3),
                        "achieved_GBs": round(bytes_per_lu(2, "f64", 1) * N / kt64 / 1e9, 1)}
         del s64
-        sweep = {}
-        for storage, n in (("f64", 4096), ("f32", 4096)):
-            wlb, pb, ub, ppb = W.taylor_green_blobs(n=n, steps=0)
-            sb = lb.Solver(wlb, pb, ub, ppb, storage=storage, phi_ref=[1.0, 1.0])
-            sb.step(20)
-            ktb = kernel_time(sb, 100)
-            bb = bytes_per_lu(2, storage, 0)
-            ach = bb * n * n / ktb / 1e9
-            sweep[f"{storage}_{n}x{n}"] = {"MLUPS": round(n * n / ktb / 1e6, 1), "achieved_GBs": round(ach, 1),
-                                           "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": ktb * 1e6,
-                                           "bytes_per_lu": bb}
-            del sb
-            torch.cuda.empty_cache()
-        out["hbm_sweep"] = sweep
+        out["hbm_sweep"] = hbm_sweep(W, lb, torch)
+        out["batched_sweep"] = batched_sweep(W, lb, torch)
+        torch.cuda.empty_cache()
+        out["steady_warm_vs_cold"] = steady_warm_vs_cold(W, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, phi0, u0, p0)
     print(json.dumps(out), flush=True)

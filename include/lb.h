@@ -154,6 +154,16 @@ lb_status lb_residual(lb_handle* h, double* res);
 lb_status lb_solve_steady(lb_handle* h, double tol, int64_t check_every, int64_t max_steps,
                           int64_t* steps_out, double* res_out);
 
+/* Mean inward diffusive flux of every species through a Dirichlet wall:
+ * flux[a] = -(1/D_aa) sum_b D_ab dphi_b/dn averaged along the wall, with the
+ * normal derivative per unit cavity length (lattice spacing x nodes across the
+ * cavity) by the second-order one-sided difference through the half-way wall
+ * value and the first two nodes.  For the double-diffusive cavity of Sec. 3.2
+ * (D = [[1, D_CT], [S_TC/Le, 1/Le]]) at the hot wall (side 0) these are the
+ * mean Nusselt and Sherwood numbers.  Uses the constant part of D.
+ * Synchronises the stream. */
+lb_status lb_wall_flux(lb_handle* h, int32_t side, double* flux);
+
 /* Totals: mass[a] = sum_x phi_a (a < m), mass[m] = sum_x sum_i h_i (= N rho0 for the
  * incompressible equilibrium).  FP64, deterministic.  Synchronises the stream. */
 lb_status lb_mass(lb_handle* h, double* mass);

@@ -257,7 +257,10 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     } else {
         for (int q = 0; q < 4; ++q) k.Dc[q] = T(p.D[q]);
     }
-    for (int q = 0; q < m * m; ++q) k.K[q] = T(p.K[q]);
+    for (int q = 0; q < m * m; ++q) {
+        k.K[q] = T(p.K[q]);
+        k.Dflux[q] = T(p.D[q]);
+    }
     k.F0[0] = T(p.F0[0]);
     k.F0[1] = T(p.F0[1]);
     for (int a = 0; a < m; ++a) {
@@ -482,6 +485,22 @@ out:
     if (res_out)
         for (int q = 0; q < Q; ++q) res_out[q] = res[q];
     return st;
+}
+
+lb_status lb_wall_flux(lb_handle* h, int32_t side, double* flux) {
+    if (!h || !flux) return fail(LB_EINVAL, "NULL argument");
+    if (side < 0 || side > 3) return fail(LB_EINVAL, "side must be 0..3");
+    for (int a = 0; a < h->p.m; ++a)
+        if (h->p.scalar_bc[side][a] != LB_SBC_DIRICHLET)
+            return fail(LB_EINVAL, "side %d is not a Dirichlet wall for species %d", side, a);
+    const int depth = side < 2 ? h->p.nx : h->p.ny;
+    if (depth < 2) return fail(LB_EINVAL, "need two nodes across the cavity");
+    double* dev = (double*)at(h->ws, h->L.res_off);
+    hipError_t e = launch_wall_flux(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, side, dev, h->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_wall_flux: %s", hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(flux, dev, sizeof(double) * h->p.m, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
 }
 
 lb_status lb_mass(lb_handle* h, double* mass) {

@@ -28,6 +28,7 @@ struct KParams {
     T omega[LB_MAX_M * LB_MAX_M]; // constant relaxation matrix (linear model)
     T Dc[4];              // chemotaxis: constant part of D (2 x 2)
     T K[LB_MAX_M * LB_MAX_M];
+    T Dflux[LB_MAX_M * LB_MAX_M]; // constant diffusion matrix (wall-flux diagnostics)
     T F0[2];
     T Fphi[LB_MAX_M][2];
     T chi, beta, cstar, eps;
@@ -63,6 +64,8 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
 // L.pop2_off / L.sold2_off at t + 2
 hipError_t launch_step2(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                         const KParams<float>& kf, int64_t step, hipStream_t s);
+hipError_t launch_wall_flux(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                            const KParams<float>& kf, bool odd, int side, double* out, hipStream_t s);
 hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                           const KParams<float>& kf, bool odd, double* phi, double* u, double* pr,
                           hipStream_t s);

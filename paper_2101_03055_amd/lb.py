@@ -83,6 +83,7 @@ def lib():
             "lb_load": [vp, vp, sz],
             "lb_set_tile": [vp, C.c_int32, C.c_int32],
             "lb_copy_state": [vp, vp],
+            "lb_wall_flux": [vp, C.c_int32, vp],
             "lb_solve_steady": [vp, C.c_double, i64, i64, C.POINTER(i64), vp],
             "lb_free": [vp],
         }
@@ -259,6 +260,12 @@ def lb_solve_steady(h, m: int, tol: float, check_every: int, max_steps: int):
     if st not in (LB_OK, LB_ESTATE, LB_ENONFINITE):
         _check(st)
     return steps.value, res, st
+
+
+def lb_wall_flux(h, side: int, m: int):
+    out = np.empty(m)
+    _check(lib().lb_wall_flux(h, int(side), out.ctypes.data))
+    return out
 
 
 def lb_copy_state(dst, src):

@@ -487,3 +487,60 @@ def test_planted_mistake_is_caught(oracle_mod, mutation):
 def test_battery_passes_unmutated(oracle_mod):
     res = _battery(oracle_mod, 0)
     assert all(res.values()), res
+
+
+# ---- wall-flux diagnostics (Sec. 3.2: Nu and Sh) --------------------------
+def test_wall_derivative_exact_for_quadratics():
+    """The one-sided difference through the half-way wall value is exact for
+    any quadratic profile: check all four walls against the calculus answer."""
+    from oracle import diagnostics as G
+
+    nx, ny = 12, 7
+    a, b, c = 0.3, -1.7, 2.9
+    q = lambda s: a + b * s + c * s * s
+    dq = lambda s: b + 2 * c * s
+    xs = (np.arange(nx) + 0.5) / nx
+    ys = (np.arange(ny) + 0.5) / ny
+    phx = np.tile(q(xs), (ny, 1))
+    phy = np.tile(q(ys)[:, None], (1, nx))
+    assert np.allclose(G.normal_derivative(phx, q(0.0), 0), dq(0.0), rtol=0, atol=1e-12)
+    assert np.allclose(G.normal_derivative(phx, q(1.0), 1), -dq(1.0), rtol=0, atol=1e-12)
+    assert np.allclose(G.normal_derivative(phy, q(0.0), 2), dq(0.0), rtol=0, atol=1e-12)
+    assert np.allclose(G.normal_derivative(phy, q(1.0), 3), -dq(1.0), rtol=0, atol=1e-12)
+    # a cubic is not captured: the scheme is second order, not higher
+    r = lambda s: s ** 3
+    cub = np.tile(r(xs), (ny, 1))
+    assert abs(G.normal_derivative(cub, 0.0, 0)[0]) > 1e-6
+
+
+def test_wall_flux_combines_species_by_rows_of_D():
+    """Nu = -(T_x + D_CT C_x) and Sh = -(S_TC T_x + C_x) for D = [[1, D_CT], [S_TC/Le, 1/Le]]."""
+    from oracle import diagnostics as G
+
+    nx, ny, Le, dct, stc = 10, 5, 2.0, 0.3, -0.2
+    xs = (np.arange(nx) + 0.5) / nx
+    T = np.tile(1.0 - 2.0 * xs, (ny, 1))      # dT/dx = -2
+    Cc = np.tile(1.0 - 0.5 * xs * xs, (ny, 1))  # dC/dx = 0 at the wall
+    D = np.array([[1.0, dct], [stc / Le, 1.0 / Le]]) * 0.037  # lattice scale cancels
+    nu, sh = G.wall_flux(np.stack([T, Cc]), D, [1.0, 1.0], 0)
+    assert nu == pytest.approx(2.0, abs=1e-12)
+    assert sh == pytest.approx(2.0 * stc, abs=1e-12)
+
+
+def test_conduction_cavity_nusselt_closed_form(oracle_mod):
+    """Without buoyancy the double-diffusive cavity conducts: T = C = 1 - x,
+    hence Nu = 1 + D_CT and Sh = 1 + S_TC on the hot wall and minus those on
+    the cold wall.  The oracle run to steady state must reproduce them."""
+    from oracle import diagnostics as G
+
+    wl, phi0, u0, p0 = W.ddc(16, Ra=1e3, Pr=1.0, Le=2.0, Nc=-2.0, Sr=0.1, Df=0.25, A=0.25, u_lat=0.2)
+    wl["Fphi"] = [[0.0, 0.0], [0.0, 0.0]]
+    o = oracle_mod.Oracle(wl, phi0, u0, p0)
+    o.step(30000)
+    phi, u, _ = o.moments()
+    assert np.abs(u).max() == 0.0
+    D = np.asarray(wl["D"]).reshape(2, 2)
+    hot = G.wall_flux(phi, D, wl["wall"][0], 0)
+    cold = G.wall_flux(phi, D, wl["wall"][1], 1)
+    assert hot == pytest.approx([1.25, 1.1], abs=1e-9)
+    assert cold == pytest.approx([-1.25, -1.1], abs=1e-9)
