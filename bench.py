@@ -190,9 +190,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "pmc", "copy"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch"], default="bench",
                     help="pmc: only the timed workload's step kernel (for counter runs); "
-                         "copy: a plain 1 GiB device copy to calibrate the byte counters")
+                         "copy: a plain 1 GiB device copy to calibrate the byte counters; "
+                         "sweep / batch: only the 4096^2 or the batched-cavity leg (for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -211,6 +212,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 5}), flush=True)
+        return
+    if args.mode == "sweep":
+        print(json.dumps({"hbm_sweep": hbm_sweep(W, lb, torch)}), flush=True)
+        return
+    if args.mode == "batch":
+        print(json.dumps({"batched_sweep": batched_sweep(W, lb, torch)}), flush=True)
         return
     wl, phi0, u0, p0 = W.chemotaxis_plume()
     N = wl["nx"] * wl["ny"]
