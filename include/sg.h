@@ -94,6 +94,21 @@ lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out);
 lb_status sg_smooth(const float* d_in, float* d_out, int32_t planes, int32_t height, int32_t width,
                     void* hip_stream);
 
+/* In place on `count` device field sets [count][4][height][width] (u, v, T, C):
+ * u -= <u (-1)^x> (-1)^x and v -= <v (-1)^y> (-1)^y, the means taken over
+ * the whole plane (FP64 accumulation, deterministic).  Asynchronous on
+ * hip_stream.
+ * Why: with bounce-back walls (or periodic axes of even length) the D2Q9
+ * update conserves the staggered momenta sum (-1)^y j_y and sum (-1)^x j_x up
+ * to a sign flip per step, because the collision conserves momentum (the
+ * force of Eq. force only adds F) and every population that carries c_y moves
+ * to a row of the other parity or is reflected with c_y reversed.  A warm
+ * start whose velocity has non-zero staggered sums therefore keeps an
+ * undamped period-2 oscillation; with them removed the initial state sits on
+ * the fixed point of that recurrence (the fluid is initialised at momentum
+ * u0 - F/2, see lb_init). */
+lb_status sg_destagger(float* d_fields, int32_t count, int32_t height, int32_t width, void* hip_stream);
+
 lb_status sg_free(sg_handle* h);
 
 /* Thread-local text of the last surrogate error. */

@@ -154,3 +154,30 @@ def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---- warm-start preparation ---------------------------------------------------
+def smooth(planes):
+    """Separable [1 2 1]/4 filter of every [..., H, W] plane, edge values replicated."""
+    a = np.asarray(planes, dtype=np.float64)
+    p = np.pad(a, [(0, 0)] * (a.ndim - 2) + [(1, 1), (1, 1)], mode="edge")
+    out = np.zeros_like(a)
+    wts = (0.25, 0.5, 0.25)
+    H, W = a.shape[-2:]
+    for dy in range(3):
+        for dx in range(3):
+            out += wts[dy] * wts[dx] * p[..., dy:dy + H, dx:dx + W]
+    return out
+
+
+def destagger(fields):
+    """fields [n, 4, H, W] = (u, v, T, C): remove <u (-1)^x> (-1)^x from u and
+    <v (-1)^y> (-1)^y from v (means over the plane); T and C unchanged."""
+    f = np.array(fields, dtype=np.float64, copy=True)
+    H, W = f.shape[-2:]
+    sx = np.tile((-1.0) ** np.arange(W), (H, 1))
+    sy = np.tile(((-1.0) ** np.arange(H))[:, None], (1, W))
+    for k in range(f.shape[0]):
+        f[k, 0] -= np.mean(f[k, 0] * sx) * sx
+        f[k, 1] -= np.mean(f[k, 1] * sy) * sy
+    return f

@@ -119,6 +119,34 @@ __device__ __forceinline__ bool wrap_in(int& c, int n, int periodic) {
 __device__ __forceinline__ int side_x(int c) { return c < 0 ? 0 : 1; }
 __device__ __forceinline__ int side_y(int c) { return c < 0 ? 2 : 3; }
 
+// true when no link of node (x, y) crosses a wall: interior on every walled
+// axis (a periodic axis has no walls)
+template <class T>
+__device__ __forceinline__ bool no_wall_link(const KParams<T>& kp, int x, int y) {
+    const bool okx = kp.px || ((x > 0) & (x < kp.nx - 1));
+    const bool oky = kp.py || ((y > 0) & (y < kp.ny - 1));
+    return okx & oky;
+}
+
+// node indices of the 3 x 3 neighbourhood of (x, y), wrapped on periodic
+// axes; valid for nodes with no_wall_link()
+struct Nbr {
+    long long row[3];
+    int col[3];
+    template <class T>
+    __device__ __forceinline__ Nbr(const KParams<T>& kp, int x, int y) {
+        const int nx = kp.nx, ny = kp.ny;
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        row[0] = (long long)ym * nx;
+        row[1] = (long long)y * nx;
+        row[2] = (long long)yp * nx;
+        col[0] = x == 0 ? nx - 1 : x - 1;
+        col[1] = x;
+        col[2] = x == nx - 1 ? 0 : x + 1;
+    }
+    __device__ __forceinline__ long long at(int dx, int dy) const { return row[dy + 1] + col[dx + 1]; }
+};
+
 // ---- gather ---------------------------------------------------------------
 // Canonical pre-collision populations of node (x, y).  PULL = false: the own
 // slots (state after an odd step or initialisation).  PULL = true: the state
@@ -138,16 +166,15 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
             for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
         return;
     } else {
-        const bool interior = (x > 0) & (x < nx - 1) & (y > 0) & (y < ny - 1);
-        if (__all(interior)) {  // wave-uniform choice: no lane pays for both paths
+        if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
+            Nbr nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                h[i] = ld(pop + OPP9[i] * P + n - CY9[i] * nx - CX9[i], kp, true);
+            for (int i = 0; i < 9; ++i) h[i] = ld(pop + OPP9[i] * P + nb.at(-CX9[i], -CY9[i]), kp, true);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + n - CY5[i] * nx - CX5[i], kp, false);
+                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + nb.at(-CX5[i], -CY5[i]), kp, false);
             return;
         }
 #pragma unroll
@@ -219,15 +246,15 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
             for (int i = 0; i < 5; ++i) st(pop, (9 + 5 * a + OPP5[i]) * P + n, f[a][i], kp, false, salt);
         return;
     } else {
-        const bool interior = (x > 0) & (x < nx - 1) & (y > 0) & (y < ny - 1);
-        if (__all(interior)) {  // wave-uniform choice: no lane pays for both paths
+        if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
+            Nbr nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st(pop, i * P + n + CY9[i] * nx + CX9[i], h[i], kp, true, salt);
+            for (int i = 0; i < 9; ++i) st(pop, i * P + nb.at(CX9[i], CY9[i]), h[i], kp, true, salt);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    st(pop, (9 + 5 * a + i) * P + n + CY5[i] * nx + CX5[i], f[a][i], kp, false, salt);
+                    st(pop, (9 + 5 * a + i) * P + nb.at(CX5[i], CY5[i]), f[a][i], kp, false, salt);
             return;
         }
 #pragma unroll

@@ -337,6 +337,38 @@ __global__ __launch_bounds__(256) void k_smooth(const float* __restrict__ in, fl
     out[k] = s;
 }
 
+// Removes the lattice-staggered parts of a velocity field, one workgroup per
+// field set [u, v, T, C]: u -= <u (-1)^x> (-1)^x and v -= <v (-1)^y> (-1)^y,
+// means over the whole plane, accumulated in FP64 in a fixed order.
+__global__ __launch_bounds__(256) void k_destagger(float* __restrict__ f, int H, int W) {
+    float* u = f + (long long)blockIdx.x * 4 * H * W;
+    float* v = u + (long long)H * W;
+    const int HW = H * W;
+    double su = 0.0, sv = 0.0;
+    for (int k = threadIdx.x; k < HW; k += blockDim.x) {
+        const int y = k / W, x = k % W;
+        su += (x & 1) ? -double(u[k]) : double(u[k]);
+        sv += (y & 1) ? -double(v[k]) : double(v[k]);
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = su;
+    red[1][threadIdx.x] = sv;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    const float cu = float(red[0][0] / HW), cv = float(red[1][0] / HW);
+    for (int k = threadIdx.x; k < HW; k += blockDim.x) {
+        const int y = k / W, x = k % W;
+        u[k] -= (x & 1) ? -cu : cu;
+        v[k] -= (y & 1) ? -cv : cv;
+    }
+}
+
 }  // namespace sgk
 
 // ============================================================================
@@ -702,6 +734,16 @@ lb_status sg_smooth(const float* d_in, float* d_out, int32_t planes, int32_t hei
     if (n == 0) return LB_OK;
     hipLaunchKernelGGL(k_smooth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
                        d_in, d_out, (long long)planes, height, width);
+    SGCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status sg_destagger(float* d_fields, int32_t count, int32_t height, int32_t width, void* hip_stream) {
+    if (!d_fields || count < 0 || height < 1 || width < 1) return sgfail(LB_EINVAL, "bad argument");
+    if ((long long)height * width > (1LL << 30)) return sgfail(LB_EINVAL, "plane too large");
+    if (count == 0) return LB_OK;
+    hipLaunchKernelGGL(k_destagger, dim3((unsigned)count), dim3(256), 0, static_cast<hipStream_t>(hip_stream), d_fields,
+                       height, width);
     SGCHK(hipGetLastError());
     return LB_OK;
 }

@@ -40,6 +40,7 @@ def lib():
             "sg_layer_input": [vp, i32, vp],
             "sg_free": [vp],
             "sg_smooth": [vp, vp, i32, i32, i32, vp],
+            "sg_destagger": [vp, i32, i32, i32, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -105,6 +106,16 @@ def smooth(d_in, d_out, stream=None):
     planes = d_in.numel() // (H * W)
     _check(lib().sg_smooth(C.c_void_p(d_in.data_ptr()), C.c_void_p(d_out.data_ptr()), planes, H, W,
                            C.c_void_p(s.cuda_stream)))
+
+
+def destagger(d_fields, stream=None):
+    """Remove the lattice-staggered velocity parts of CUDA float32 fields [n, 4, H, W] in place."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream(d_fields.device)
+    n, c, H, W = d_fields.shape
+    assert c == 4 and d_fields.dtype == torch.float32 and d_fields.is_contiguous()
+    _check(lib().sg_destagger(C.c_void_p(d_fields.data_ptr()), n, H, W, C.c_void_p(s.cuda_stream)))
 
 
 class Surrogate:

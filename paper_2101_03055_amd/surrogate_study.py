@@ -5,7 +5,8 @@ Pipeline (all on one GPU):
  1. dataset: cavities drawn from the sweep law at L x L (one seed each) are
     solved to steady state by the batched FP32 solver (MRT fluid); targets
     are (u / u_lat, v / u_lat, T, C), inputs the normalised parameters;
- 2. training: the CNN (sg.h) with Adam for a number of epochs;
+ 2. training: the CNN (sg.h) with Adam for a number of epochs (learning
+    rate lowered 3x after 60 % and again after 85 % of them);
  3. evaluation on held-out seeds, every path to residual 1e-8:
     - plain   : FP64 single-domain solve from rest, one cavity after the other
                 (the method as the paper runs it), on a subset;
@@ -79,27 +80,43 @@ def generate(seeds, L, tol=5e-6, max_steps=600_000, check_every=1000, log=print)
 
 
 def train(params, fields, epochs, batch=16, lr=1e-3, seed=0, log=print):
+    """Adam in three phases of decreasing learning rate (lr, lr/3, lr/10 over
+    60 %, 25 % and 15 % of the epochs); the moment estimates restart with
+    each phase."""
     import torch
 
     L = fields.shape[-1]
-    net = sg.Surrogate(batch, fields.shape[-2], L, lr=lr)
-    net.set_weights(sg.init_weights(seed))
     dp = torch.tensor(params, device="cuda")
     df = torch.tensor(fields, device="cuda")
     losses = []
     t0 = time.perf_counter()
-    per = max(1, epochs // 10)
-    for e0 in range(0, epochs, per):
-        k = min(per, epochs - e0)
-        losses += net.train_epochs(dp, df, len(params), k, seed=seed + e0).tolist()
-        log(f"  train: epoch {e0 + k}/{epochs}, loss {losses[-1]:.3e}, {time.perf_counter() - t0:.1f}s")
+    bounds = [0, int(round(0.6 * epochs)), int(round(0.85 * epochs)), epochs]
+    w = sg.init_weights(seed)
+    net = None
+    for ph, scale in enumerate((1.0, 1.0 / 3.0, 0.1)):
+        e_begin, e_end = bounds[ph], bounds[ph + 1]
+        if e_end <= e_begin:
+            continue
+        if net is not None:
+            w = net.get_weights()
+            net.close()
+        net = sg.Surrogate(batch, fields.shape[-2], L, lr=lr * scale)
+        net.set_weights(w)
+        per = max(1, (e_end - e_begin) // 5)
+        for e0 in range(e_begin, e_end, per):
+            k = min(per, e_end - e0)
+            losses += net.train_epochs(dp, df, len(params), k, seed=seed + e0).tolist()
+            log(f"  train: epoch {e0 + k}/{epochs} (lr {lr * scale:.1e}), loss {losses[-1]:.3e}, "
+                f"{time.perf_counter() - t0:.1f}s")
     return net, losses, time.perf_counter() - t0
 
 
 def predict(net, params, smooth=True):
-    """Surrogate fields [n][4][H][W]; smoothed by one [1 2 1] pass (on the
-    GPU) unless smooth is False: grid-scale noise in a warm start excites
-    lattice modes that decay very slowly."""
+    """Surrogate fields [n][4][H][W], prepared for a warm start on the GPU:
+    one [1 2 1] pass (grid-scale noise excites lattice modes that decay very
+    slowly) and removal of the lattice-staggered velocity sums (they would
+    persist as an undamped period-2 oscillation; sg_destagger).  smooth=False
+    returns the raw network output."""
     import torch
 
     n = len(params)
@@ -110,6 +127,7 @@ def predict(net, params, smooth=True):
     if smooth:
         sm = torch.empty_like(out)
         sg.smooth(out, sm)
+        sg.destagger(sm)
         out = sm
     _sync()
     return out.cpu().numpy().astype(np.float64)
@@ -158,13 +176,15 @@ def main():
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--plain", type=int, default=16, help="test cavities also solved by the plain FP64 method")
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--tol32", type=float, default=1e-5, help="residual that ends the FP32 phase")
     ap.add_argument("--data-tol", type=float, default=5e-6)
     ap.add_argument("--weights", default=None, help="trained weights (.npz): skip dataset and training")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     log = lambda s: print(s, flush=True)
-    summary = {"L": args.L, "u_lat": U_LAT, "collision": "bgk", "storage": "f32 phase + f64 finish"}
+    summary = {"L": args.L, "u_lat": U_LAT, "collision": "bgk", "storage": "f32 phase + f64 finish",
+               "tol32": args.tol32, "tol": 1e-8}
 
     def save():
         with open(os.path.join(args.out, "summary.json"), "w") as fh:
@@ -196,9 +216,9 @@ def main():
     t0 = time.perf_counter()
     pred = predict(net, tparams)
     t_pred = time.perf_counter() - t0
-    warm, f_warm = solve_path(cases, pred, label="warm", log=log)
+    warm, f_warm = solve_path(cases, pred, tol32=args.tol32, label="warm", log=log)
     warm["seconds_predict"] = t_pred
-    cold, f_cold = solve_path(cases, None, label="cold", log=log)
+    cold, f_cold = solve_path(cases, None, tol32=args.tol32, label="cold", log=log)
     ok = [i for i in range(len(cases)) if warm["status"][i] == 1 and cold["status"][i] == 1]
     summary["batched"] = {
         "cases": len(cases), "both_converged": len(ok),
@@ -209,6 +229,11 @@ def main():
         "prediction_relL2_vs_cold_median": float(np.median([rel_l2(pred[i], f_cold[i]) for i in ok])),
         "warm_relL2_vs_cold_max": max(rel_l2(f_warm[i], f_cold[i]) for i in ok),
         "warm_helps_fraction": float(np.mean([warm["steps_total"][i] < cold["steps_total"][i] for i in ok])),
+        "steps_fp32_warm_median": float(np.median([warm["steps_fp32"][i] for i in ok])),
+        "steps_fp32_cold_median": float(np.median([cold["steps_fp32"][i] for i in ok])),
+        "per_case": {"steps_warm": warm["steps_total"], "steps_cold": cold["steps_total"],
+                     "steps_fp32_warm": warm["steps_fp32"], "steps_fp32_cold": cold["steps_fp32"],
+                     "status_warm": warm["status"], "status_cold": cold["status"]},
     }
     save()
     log("plain FP64 reference on a subset")

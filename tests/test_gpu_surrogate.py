@@ -139,3 +139,28 @@ def test_predict_equals_forward_and_training_reduces_loss():
     losses = net.train_epochs(dp, df, n, 60, seed=1)
     print("losses", losses[0], losses[-1], flush=True)
     assert np.all(np.isfinite(losses)) and losses[-1] < 0.1 * losses[0]
+
+
+def test_smooth_matches_oracle():
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((3, 4, 37, 29)).astype(np.float32)   # ragged plane
+    d_in = torch.tensor(a, device="cuda")
+    d_out = torch.empty_like(d_in)
+    sg.smooth(d_in, d_out)
+    torch.cuda.synchronize()
+    want = S.smooth(a.astype(np.float64))
+    assert np.abs(d_out.cpu().numpy() - want).max() <= 1e-6 * np.abs(want).max()
+
+
+def test_destagger_matches_oracle():
+    rng = np.random.default_rng(12)
+    a = rng.standard_normal((5, 4, 128, 128)).astype(np.float32)
+    a[:, 1] += 0.3 * ((-1.0) ** np.arange(128))[:, None]          # a large staggered part
+    d = torch.tensor(a, device="cuda")
+    sg.destagger(d)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64)
+    want = S.destagger(a.astype(np.float64))
+    assert np.abs(got - want).max() <= 2e-6
+    sy = ((-1.0) ** np.arange(128))[:, None]
+    assert np.abs((got[:, 1] * sy).mean(axis=(1, 2))).max() <= 1e-7

@@ -124,3 +124,63 @@ def test_features_layout():
     assert np.allclose(f[0, :, 0, 6], (np.arange(4) + 0.5) / 4)
     assert np.allclose(f[..., 7] ** 2 + f[..., 8] ** 2, 1.0)
     assert np.allclose(f[0, 1, 3, 13], np.sin(2 * np.pi * 1.5 / 4))
+
+
+# ---- warm-start preparation: smoothing and staggered-momentum removal ------
+def test_smooth_equals_library_correlation():
+    from scipy import ndimage
+
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((3, 11, 17))
+    k = np.outer([1, 2, 1], [1, 2, 1]) / 16.0
+    want = np.stack([ndimage.correlate(x, k, mode="nearest") for x in a])
+    assert np.allclose(S.smooth(a), want, rtol=0, atol=1e-14)
+
+
+def test_smooth_kills_grid_scale_and_keeps_constants():
+    H, W = 12, 10
+    y, x = np.mgrid[0:H, 0:W]
+    assert np.abs(S.smooth(((-1.0) ** x)[None])[0][:, 1:-1]).max() < 1e-15
+    assert np.abs(S.smooth(((-1.0) ** y)[None])[0][1:-1, :]).max() < 1e-15
+    assert np.allclose(S.smooth(np.full((1, H, W), 2.5)), 2.5, rtol=0, atol=1e-15)
+    lin = (0.3 * x + 0.7 * y)[None].astype(float)
+    assert np.allclose(S.smooth(lin)[0][1:-1, 1:-1], lin[0][1:-1, 1:-1], rtol=0, atol=1e-13)
+
+
+def test_destagger_removes_only_the_staggered_sums():
+    rng = np.random.default_rng(4)
+    n, H, W = 2, 10, 14
+    f = rng.standard_normal((n, 4, H, W))
+    g = S.destagger(f)
+    y, x = np.mgrid[0:H, 0:W]
+    sx, sy = (-1.0) ** x, (-1.0) ** y
+    for k in range(n):
+        assert abs(np.sum(g[k, 0] * sx)) < 1e-12 and abs(np.sum(g[k, 1] * sy)) < 1e-12
+        assert np.array_equal(g[k, 2:], f[k, 2:])
+        du, dv = f[k, 0] - g[k, 0], f[k, 1] - g[k, 1]
+        assert np.allclose(du, du[0, 0] * sx, rtol=0, atol=1e-14)   # a pure (-1)^x pattern
+        assert np.allclose(dv, dv[0, 0] * sy, rtol=0, atol=1e-14)
+    assert np.allclose(S.destagger(g), g, rtol=0, atol=1e-14)      # idempotent
+
+
+def test_staggered_momentum_is_a_lattice_invariant(oracle_mod):
+    """The reason for the removal, pinned on the LB oracle: without force,
+    Q_y = sum (-1)^y j_y and Q_x = sum (-1)^x j_x flip sign every step exactly
+    (collision conserves momentum; streaming and bounce-back flip the parity),
+    with no-slip walls and with an even periodic axis."""
+    from paper_2101_03055_amd import workloads as W
+
+    for fb in (["noslip"] * 4, ["periodic", "periodic", "noslip", "noslip"]):
+        sb = [["noflux"] * 2] * 4 if fb[0] == "noslip" else [["periodic"] * 2] * 2 + [["noflux"] * 2] * 2
+        wl, phi0, u0, p0 = W.random_case(16, 12, seed=8, fluid_bc=fb, scalar_bc=sb, force=False)
+        o = oracle_mod.Oracle(wl, phi0, u0, p0)
+        y, x = np.mgrid[0:12, 0:16]
+        sx, sy = (-1.0) ** x, (-1.0) ** y
+        q = []
+        for t in range(6):
+            _, u, _ = o.moments()
+            q.append((np.sum(u[0] * sx), np.sum(u[1] * sy)))
+            o.step(1)
+        q = np.array(q)
+        assert np.abs(q).min() > 1e-4
+        assert np.allclose(q[1:], -q[:-1], rtol=1e-11, atol=0), fb
