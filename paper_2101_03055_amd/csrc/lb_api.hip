@@ -64,10 +64,9 @@ Layout make_layout(const lb_params& p) {
     Layout L{};
     L.N = (size_t)p.nx * (size_t)p.ny;
     L.elem = elem_bytes(p.storage);
-    // planes padded to 4 KiB plus a 1 KiB stagger so that the 19+ concurrent
-    // plane streams do not start in the same memory channel
-    const size_t pb = round_up(L.N * L.elem, 4096) + 1024;
-    L.plane = pb / L.elem;
+    // populations in blocks of 64 nodes (see pidx in lb_device.h)
+    L.plane = round_up(L.N, 64);
+    const size_t pb = round_up(L.plane * L.elem, 256);
     L.npop = 9 + 5 * (size_t)p.m;
     L.nsrc = (size_t)__builtin_popcount(source_mask(p));
     size_t off = 0;
@@ -231,7 +230,6 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     const bool shifted = p.storage != LB_STORE_F64;
     k.nx = p.nx;
     k.ny = p.ny;
-    k.plane = (long long)L.plane;
     k.px = p.fluid_bc[0] == LB_BC_PERIODIC;
     k.py = p.fluid_bc[2] == LB_BC_PERIODIC;
     for (int s = 0; s < 4; ++s) {

@@ -119,6 +119,21 @@ __device__ __forceinline__ bool wrap_in(int& c, int n, int periodic) {
 __device__ __forceinline__ int side_x(int c) { return c < 0 ? 0 : 1; }
 __device__ __forceinline__ int side_y(int c) { return c < 0 ? 2 : 3; }
 
+// Population storage: nodes (n = y nx + x) in blocks of kBlk; within a block
+// the 9 + 5m populations follow each other as runs of kBlk values (h_0..h_8,
+// then f_{a,0..4} per species).  A wavefront of 64 nodes reads or writes 64
+// consecutive values per population, and the 19+ runs of one block are
+// contiguous, so the memory system sees few long streams instead of one
+// stream per population plane.
+constexpr int kBlkShift = 6;
+constexpr int kBlk = 1 << kBlkShift;
+
+template <int M>
+__device__ __forceinline__ long long pidx(int q, long long n) {
+    constexpr int NQ = 9 + 5 * M;
+    return (((n >> kBlkShift) * NQ + q) << kBlkShift) | (n & (kBlk - 1));
+}
+
 // true when no link of node (x, y) crosses a wall: interior on every walled
 // axis (a periodic axis has no walls)
 template <class T>
@@ -154,27 +169,26 @@ struct Nbr {
 template <class S, int M, bool PULL, class T>
 __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict__ pop, int x, int y,
                                        T h[9], T f[M][5]) {
-    const long long P = kp.plane;
     const int nx = kp.nx, ny = kp.ny;
     const long long n = (long long)y * nx + x;
     if constexpr (!PULL) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = ld(pop + i * P + n, kp, true);
+        for (int i = 0; i < 9; ++i) h[i] = ld(pop + pidx<M>(i, n), kp, true);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
+            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + pidx<M>((9 + 5 * a + i), n), kp, false);
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             Nbr nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) h[i] = ld(pop + OPP9[i] * P + nb.at(-CX9[i], -CY9[i]), kp, true);
+            for (int i = 0; i < 9; ++i) h[i] = ld(pop + pidx<M>(OPP9[i], nb.at(-CX9[i], -CY9[i])), kp, true);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + nb.at(-CX5[i], -CY5[i]), kp, false);
+                    f[a][i] = ld(pop + pidx<M>((9 + 5 * a + OPP5[i]), nb.at(-CX5[i], -CY5[i])), kp, false);
             return;
         }
 #pragma unroll
@@ -208,7 +222,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                     }
                 }
             }
-            h[i] = ld(pop + pl * P + src, kp, true);
+            h[i] = ld(pop + pidx<M>(pl, src), kp, true);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -217,10 +231,10 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                 int sx = x - CX5[i], sy = y - CY5[i];
                 const bool inx = wrap_in(sx, nx, kp.px), iny = wrap_in(sy, ny, kp.py);
                 if (inx & iny) {
-                    f[a][i] = ld(pop + (9 + 5 * a + OPP5[i]) * P + (long long)sy * nx + sx, kp, false);
+                    f[a][i] = ld(pop + pidx<M>((9 + 5 * a + OPP5[i]), (long long)sy * nx + sx), kp, false);
                 } else {
                     const int side = inx ? side_y(sy) : side_x(sx);
-                    T v = ld(pop + (9 + 5 * a + i) * P + n, kp, false);
+                    T v = ld(pop + pidx<M>((9 + 5 * a + i), n), kp, false);
                     if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
                     f[a][i] = v;
                 }
@@ -234,27 +248,26 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
 template <class S, int M, bool PUSH, class T>
 __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ pop, int x, int y,
                                         const T h[9], const T f[M][5], uint32_t salt) {
-    const long long P = kp.plane;
     const int nx = kp.nx, ny = kp.ny;
     const long long n = (long long)y * nx + x;
     if constexpr (!PUSH) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st(pop, OPP9[i] * P + n, h[i], kp, true, salt);
+        for (int i = 0; i < 9; ++i) st(pop, pidx<M>(OPP9[i], n), h[i], kp, true, salt);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st(pop, (9 + 5 * a + OPP5[i]) * P + n, f[a][i], kp, false, salt);
+            for (int i = 0; i < 5; ++i) st(pop, pidx<M>((9 + 5 * a + OPP5[i]), n), f[a][i], kp, false, salt);
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             Nbr nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st(pop, i * P + nb.at(CX9[i], CY9[i]), h[i], kp, true, salt);
+            for (int i = 0; i < 9; ++i) st(pop, pidx<M>(i, nb.at(CX9[i], CY9[i])), h[i], kp, true, salt);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    st(pop, (9 + 5 * a + i) * P + nb.at(CX5[i], CY5[i]), f[a][i], kp, false, salt);
+                    st(pop, pidx<M>((9 + 5 * a + i), nb.at(CX5[i], CY5[i])), f[a][i], kp, false, salt);
             return;
         }
 #pragma unroll
@@ -288,7 +301,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     }
                 }
             }
-            st(pop, pl * P + dst, h[i], kp, true, salt);
+            st(pop, pidx<M>(pl, dst), h[i], kp, true, salt);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -297,12 +310,12 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                 int tx = x + CX5[i], ty = y + CY5[i];
                 const bool inx = wrap_in(tx, nx, kp.px), iny = wrap_in(ty, ny, kp.py);
                 if (inx & iny) {
-                    st(pop, (9 + 5 * a + i) * P + (long long)ty * nx + tx, f[a][i], kp, false, salt);
+                    st(pop, pidx<M>((9 + 5 * a + i), (long long)ty * nx + tx), f[a][i], kp, false, salt);
                 } else {
                     const int side = inx ? side_y(ty) : side_x(tx);
                     T v = f[a][i];
                     if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
-                    st(pop, (9 + 5 * a + OPP5[i]) * P + n, v, kp, false, salt);
+                    st(pop, pidx<M>((9 + 5 * a + OPP5[i]), n), v, kp, false, salt);
                 }
             }
     }

@@ -15,7 +15,6 @@ namespace lbk {
 template <class T>
 struct KParams {
     int nx, ny;
-    long long plane;      // elements per population plane
     int px, py;           // periodic in x / y
     int fbc[4];           // fluid boundary code per side
     int sbc[4][LB_MAX_M]; // scalar boundary code per side and species
@@ -41,7 +40,7 @@ struct KParams {
 struct Layout {
     size_t N;             // nodes
     size_t elem;          // bytes per stored population value
-    size_t plane;         // elements per population plane (padded)
+    size_t plane;         // nodes rounded up to whole storage blocks (64)
     size_t npop;          // population planes, 9 + 5m
     size_t nsrc;          // S_old planes
     size_t pop_off, sold_off, snap_off, stage_off, part_off, res_off, total;

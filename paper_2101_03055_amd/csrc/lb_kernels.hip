@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_step2(KParams<typename St<S>::T> kp, co
     const int bx = b % tiles_x, by = b / tiles_x;
     const int x0 = bx * TX - 2, y0 = by * TY - 2;  // global origin of the step-1 region
     const int nx = kp.nx, ny = kp.ny;
-    const long long N = (long long)nx * ny, P = kp.plane;
+    const long long N = (long long)nx * ny;
     // existence of a step-1-region node, with the side it lies beyond on each axis (-1: inside/periodic)
     auto ex1 = [&](int lx, int ly, int& ox, int& oy) -> int {
         int gx = x0 + lx, gy = y0 + ly;
@@ -162,11 +162,11 @@ __global__ __launch_bounds__(256) void k_step2(KParams<typename St<S>::T> kp, co
         const long long n = (long long)gy * nx + gx;
         T h[9], f[M][5], So[M], Sn[M];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = ld(src + i * P + n, kp, true);
+        for (int i = 0; i < 9; ++i) h[i] = ld(src + pidx<M>(i, n), kp, true);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[a][i] = ld(src + (9 + 5 * a + i) * P + n, kp, false);
+            for (int i = 0; i < 5; ++i) f[a][i] = ld(src + pidx<M>((9 + 5 * a + i), n), kp, false);
         int k = 0;
 #pragma unroll
         for (int a = 0; a < M; ++a) {
@@ -215,11 +215,11 @@ __global__ __launch_bounds__(256) void k_step2(KParams<typename St<S>::T> kp, co
         T h[9], f[M][5];
         lds_pull<T, M, NQ>(kp, buf2, G::R1X, N2, tx + 1, ty + 1, ex2, h, f);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st(dst, i * P + n, h[i], kp, true, salt);
+        for (int i = 0; i < 9; ++i) st(dst, pidx<M>(i, n), h[i], kp, true, salt);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st(dst, (9 + 5 * a + i) * P + n, f[a][i], kp, false, salt);
+            for (int i = 0; i < 5; ++i) st(dst, pidx<M>((9 + 5 * a + i), n), f[a][i], kp, false, salt);
         int k = 0;
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -242,18 +242,17 @@ __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* 
     u[0] = T(stage[M * N + n]);
     u[1] = T(stage[(M + 1) * N + n]);
     const T p = has_p0 ? T(stage[(M + 2) * N + n]) : T(0);
-    const long long P = kp.plane;
     const uint32_t salt = 0x51ed270bu;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const T phid = phi[a] - kp.phi_ref[a];
         const T iso = phid * (T(1) / T(6));
         const T adv = T(0.5) * phi[a];
-        st(pop, (9 + 5 * a + 1) * P + n, iso + adv * u[0], kp, false, salt);
-        st(pop, (9 + 5 * a + 3) * P + n, iso - adv * u[0], kp, false, salt);
-        st(pop, (9 + 5 * a + 2) * P + n, iso + adv * u[1], kp, false, salt);
-        st(pop, (9 + 5 * a + 4) * P + n, iso - adv * u[1], kp, false, salt);
-        st(pop, (9 + 5 * a + 0) * P + n, phid - T(4) * iso, kp, false, salt);
+        st(pop, pidx<M>((9 + 5 * a + 1), n), iso + adv * u[0], kp, false, salt);
+        st(pop, pidx<M>((9 + 5 * a + 3), n), iso - adv * u[0], kp, false, salt);
+        st(pop, pidx<M>((9 + 5 * a + 2), n), iso + adv * u[1], kp, false, salt);
+        st(pop, pidx<M>((9 + 5 * a + 4), n), iso - adv * u[1], kp, false, salt);
+        st(pop, pidx<M>((9 + 5 * a + 0), n), phid - T(4) * iso, kp, false, salt);
     }
     // fluid equilibrium at the momentum c_i h_i = u0 - F(phi0)/2 so that the
     // velocity of Eq. sum-u equals the prescribed u0 at t = 0
@@ -270,9 +269,9 @@ __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* 
         const T cu = T(CX9[i]) * j[0] + T(CY9[i]) * j[1];
         const T v = w9<T>(i) * (T(3) * p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
         hsum += v;
-        st(pop, i * P + n, v, kp, true, salt);
+        st(pop, pidx<M>(i, n), v, kp, true, salt);
     }
-    st(pop, 0 * P + n, kp.rho0_eff - hsum, kp, true, salt);
+    st(pop, pidx<M>(0, n), kp.rho0_eff - hsum, kp, true, salt);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -351,10 +350,10 @@ __global__ __launch_bounds__(256) void k_import(KParams<typename St<S>::T> kp, S
         if (k < plane_begin || k >= plane_begin + count) continue;
         const double v = in[(long long)(k - plane_begin) * N + n];
         if (k < 9) {
-            st(pop, k * kp.plane + n, T(v - (k == 0 ? double(kp.h0_shift) : 0.0)), kp, true, salt);
+            st(pop, pidx<M>(k, n), T(v - (k == 0 ? double(kp.h0_shift) : 0.0)), kp, true, salt);
         } else {
             const int a = (k - 9) / 5, i = (k - 9) % 5;
-            st(pop, k * kp.plane + n, T(v - double(w5<T>(i)) * double(kp.phi_ref[a])), kp, false, salt);
+            st(pop, pidx<M>(k, n), T(v - double(w5<T>(i)) * double(kp.phi_ref[a])), kp, false, salt);
         }
     }
 }
