@@ -183,6 +183,48 @@ def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000):
             "note": "cases that do not become steady within the cap (e.g. Nc near -1) count in both wall times"}
 
 
+def surrogate_bench(torch, epochs=3, samples=64):
+    """Training and inference throughput of the CNN surrogate (BF16 MFMA
+    convolutions) at batch 16 on 128 x 128, random weights and targets.
+    Algorithmic flops per training step: forward, data gradient (all layers
+    but the first) and weight gradient of every 3x3 convolution over the real
+    (unpadded) channels, 2 flops per multiply-add."""
+    from paper_2101_03055_amd import sg
+
+    B, H, Wd = 16, 128, 128
+    macs = [9 * sg.layer_info(l)[0] * sg.layer_info(l)[1] for l in range(sg.SG_LAYERS)]
+    flops_step = 2.0 * B * H * Wd * (2 * sum(macs) + sum(macs[1:]))
+    net = sg.Surrogate(B, H, Wd)
+    net.set_weights(sg.init_weights(0))
+    g = torch.Generator(device="cpu").manual_seed(0)
+    dp = torch.rand((samples, 5), generator=g).cuda()
+    df = (0.1 * torch.randn((samples, 4, H, Wd), generator=g)).cuda()
+    net.train_epochs(dp, df, samples, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    net.train_epochs(dp, df, samples, epochs)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    steps = epochs * samples // B
+    t_step = e0.elapsed_time(e1) / 1e3 / steps
+    out = torch.empty((B, 4, H, Wd), device="cuda")
+    net.predict(dp, B, out)
+    torch.cuda.synchronize()
+    e0.record(net.stream)
+    for _ in range(10):
+        net.predict(dp, B, out)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    t_pred = e0.elapsed_time(e1) / 1e3 / 10
+    flops_pred = 2.0 * B * H * Wd * sum(macs)
+    return {"batch": B, "grid": [H, Wd], "train_step_ms": round(t_step * 1e3, 3),
+            "train_TFLOPs": round(flops_step / t_step / 1e12, 1),
+            "train_frac_bf16_peak": round(flops_step / t_step / 2.5e15, 4),
+            "predict_ms_per_batch": round(t_pred * 1e3, 3),
+            "predict_TFLOPs": round(flops_pred / t_pred / 1e12, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,7 +232,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "surrogate"], default="bench",
                     help="pmc: only the timed workload's step kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy to calibrate the byte counters; "
                          "sweep / batch: only the 4096^2 or the batched-cavity leg (for profiles)")
@@ -215,6 +257,9 @@ def main():
         return
     if args.mode == "sweep":
         print(json.dumps({"hbm_sweep": hbm_sweep(W, lb, torch)}), flush=True)
+        return
+    if args.mode == "surrogate":
+        print(json.dumps({"surrogate": surrogate_bench(torch)}), flush=True)
         return
     if args.mode == "batch":
         print(json.dumps({"batched_sweep": batched_sweep(W, lb, torch)}), flush=True)
@@ -261,6 +306,7 @@ def main():
         out["batched_sweep"] = batched_sweep(W, lb, torch)
         torch.cuda.empty_cache()
         out["steady_warm_vs_cold"] = steady_warm_vs_cold(W, torch)
+        out["surrogate"] = surrogate_bench(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, phi0, u0, p0)
     print(json.dumps(out), flush=True)

@@ -294,10 +294,9 @@ struct lb_handle {
 };
 
 namespace {
-Launch default_launch(const lb_params& p) {
-    (void)p;
-    return Launch{64, 4};
-}
+// one row segment of 256 nodes per workgroup on wide grids (measured ~1.5 %
+// faster at 4096^2), 64 x 4 otherwise (measured best on 512 x 256)
+Launch default_launch(const lb_params& p) { return p.nx >= 1024 ? Launch{256, 1} : Launch{64, 4}; }
 
 void* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 

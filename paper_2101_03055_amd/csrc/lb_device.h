@@ -162,6 +162,17 @@ struct Nbr {
     __device__ __forceinline__ long long at(int dx, int dy) const { return row[dy + 1] + col[dx + 1]; }
 };
 
+// walls next to node (x, y): out_x(d) is true when x + d (d in -1, 0, 1) lies
+// beyond a wall (never on a periodic axis); likewise out_y
+struct WallFlags {
+    bool x0, x1, y0, y1;
+    template <class T>
+    __device__ __forceinline__ WallFlags(const KParams<T>& kp, int x, int y)
+        : x0(!kp.px && x == 0), x1(!kp.px && x == kp.nx - 1), y0(!kp.py && y == 0), y1(!kp.py && y == kp.ny - 1) {}
+    __device__ __forceinline__ bool out_x(int d) const { return (d < 0 && x0) || (d > 0 && x1); }
+    __device__ __forceinline__ bool out_y(int d) const { return (d < 0 && y0) || (d > 0 && y1); }
+};
+
 // ---- gather ---------------------------------------------------------------
 // Canonical pre-collision populations of node (x, y).  PULL = false: the own
 // slots (state after an odd step or initialisation).  PULL = true: the state
@@ -169,7 +180,7 @@ struct Nbr {
 template <class S, int M, bool PULL, class T>
 __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict__ pop, int x, int y,
                                        T h[9], T f[M][5]) {
-    const int nx = kp.nx, ny = kp.ny;
+    const int nx = kp.nx;
     const long long n = (long long)y * nx + x;
     if constexpr (!PULL) {
 #pragma unroll
@@ -191,34 +202,27 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                     f[a][i] = ld(pop + pidx<M>((9 + 5 * a + OPP5[i]), nb.at(-CX5[i], -CY5[i])), kp, false);
             return;
         }
+        // nodes next to a wall: every link resolved with selects (no load in a
+        // divergent branch); wall rules by side: bounce-back, specular
+        // reflection (free slip), anti-bounce-back (Dirichlet scalars)
+        const WallFlags wf(kp, x, y);
+        Nbr nb(kp, x, y);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            int sx = x - CX9[i], sy = y - CY9[i];
-            const bool inx = wrap_in(sx, nx, kp.px), iny = wrap_in(sy, ny, kp.py);
-            long long src;
-            int pl;
-            if (inx & iny) {
-                src = (long long)sy * nx + sx;
-                pl = OPP9[i];
-            } else {
-                src = n;  // bounce-back: the node's own reflected value
+            const int cx = CX9[i], cy = CY9[i];
+            const bool ox = wf.out_x(-cx), oy = wf.out_y(-cy);  // source x - c_i beyond a wall
+            long long src = nb.at(-cx, -cy);
+            int pl = OPP9[i];
+            if (ox || oy) {
+                src = n;  // bounce-back: the node's own reflected value (also corners)
                 pl = i;
-                if (inx != iny) {
-                    const int side = inx ? side_y(sy) : side_x(sx);
-                    if (kp.fbc[side] == LB_BC_FREESLIP) {
-                        if (!iny) {  // specular across a y-wall: from (x - c_x, y), direction mirrored
-                            int rx = x - CX9[i];
-                            if (wrap_in(rx, nx, kp.px)) {
-                                src = (long long)y * nx + rx;
-                                pl = OPP9[MIRY9[i]];
-                            }
-                        } else {  // across an x-wall: from (x, y - c_y)
-                            int ry = y - CY9[i];
-                            if (wrap_in(ry, ny, kp.py)) {
-                                src = (long long)ry * nx + x;
-                                pl = OPP9[MIRX9[i]];
-                            }
-                        }
+                if (ox != oy && kp.fbc[ox ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3)] == LB_BC_FREESLIP) {
+                    if (oy) {  // specular across a y-wall: from (x - c_x, y), direction mirrored
+                        src = nb.at(-cx, 0);
+                        pl = OPP9[MIRY9[i]];
+                    } else {  // across an x-wall: from (x, y - c_y)
+                        src = nb.at(0, -cy);
+                        pl = OPP9[MIRX9[i]];
                     }
                 }
             }
@@ -228,16 +232,13 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
         for (int a = 0; a < M; ++a)
 #pragma unroll
             for (int i = 0; i < 5; ++i) {
-                int sx = x - CX5[i], sy = y - CY5[i];
-                const bool inx = wrap_in(sx, nx, kp.px), iny = wrap_in(sy, ny, kp.py);
-                if (inx & iny) {
-                    f[a][i] = ld(pop + pidx<M>((9 + 5 * a + OPP5[i]), (long long)sy * nx + sx), kp, false);
-                } else {
-                    const int side = inx ? side_y(sy) : side_x(sx);
-                    T v = ld(pop + pidx<M>((9 + 5 * a + i), n), kp, false);
-                    if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
-                    f[a][i] = v;
-                }
+                const int cx = CX5[i], cy = CY5[i];
+                const bool out = wf.out_x(-cx) || wf.out_y(-cy);
+                const int side = wf.out_x(-cx) ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3);
+                const long long src = out ? n : nb.at(-cx, -cy);
+                const T v = ld(pop + pidx<M>(9 + 5 * a + (out ? i : OPP5[i]), src), kp, false);
+                const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
+                f[a][i] = dir ? -v + T(2) * w5<T>(i) * kp.wallr[side][a] : v;
             }
     }
 }
@@ -248,7 +249,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
 template <class S, int M, bool PUSH, class T>
 __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ pop, int x, int y,
                                         const T h[9], const T f[M][5], uint32_t salt) {
-    const int nx = kp.nx, ny = kp.ny;
+    const int nx = kp.nx;
     const long long n = (long long)y * nx + x;
     if constexpr (!PUSH) {
 #pragma unroll
@@ -270,34 +271,24 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     st(pop, pidx<M>((9 + 5 * a + i), nb.at(CX5[i], CY5[i])), f[a][i], kp, false, salt);
             return;
         }
+        const WallFlags wf(kp, x, y);
+        Nbr nb(kp, x, y);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            int tx = x + CX9[i], ty = y + CY9[i];
-            const bool inx = wrap_in(tx, nx, kp.px), iny = wrap_in(ty, ny, kp.py);
-            long long dst;
-            int pl;
-            if (inx & iny) {
-                dst = (long long)ty * nx + tx;
-                pl = i;
-            } else {
-                dst = n;  // bounce-back into the node's own opposite slot
+            const int cx = CX9[i], cy = CY9[i];
+            const bool ox = wf.out_x(cx), oy = wf.out_y(cy);  // target x + c_i beyond a wall
+            long long dst = nb.at(cx, cy);
+            int pl = i;
+            if (ox || oy) {
+                dst = n;  // bounce-back into the node's own opposite slot (also corners)
                 pl = OPP9[i];
-                if (inx != iny) {
-                    const int side = inx ? side_y(ty) : side_x(tx);
-                    if (kp.fbc[side] == LB_BC_FREESLIP) {
-                        if (!iny) {
-                            int rx = x + CX9[i];
-                            if (wrap_in(rx, nx, kp.px)) {
-                                dst = (long long)y * nx + rx;
-                                pl = MIRY9[i];
-                            }
-                        } else {
-                            int ry = y + CY9[i];
-                            if (wrap_in(ry, ny, kp.py)) {
-                                dst = (long long)ry * nx + x;
-                                pl = MIRX9[i];
-                            }
-                        }
+                if (ox != oy && kp.fbc[ox ? (cx > 0 ? 1 : 0) : (cy > 0 ? 3 : 2)] == LB_BC_FREESLIP) {
+                    if (oy) {
+                        dst = nb.at(cx, 0);
+                        pl = MIRY9[i];
+                    } else {
+                        dst = nb.at(0, cy);
+                        pl = MIRX9[i];
                     }
                 }
             }
@@ -307,16 +298,13 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
         for (int a = 0; a < M; ++a)
 #pragma unroll
             for (int i = 0; i < 5; ++i) {
-                int tx = x + CX5[i], ty = y + CY5[i];
-                const bool inx = wrap_in(tx, nx, kp.px), iny = wrap_in(ty, ny, kp.py);
-                if (inx & iny) {
-                    st(pop, pidx<M>((9 + 5 * a + i), (long long)ty * nx + tx), f[a][i], kp, false, salt);
-                } else {
-                    const int side = inx ? side_y(ty) : side_x(tx);
-                    T v = f[a][i];
-                    if (kp.sbc[side][a] == LB_SBC_DIRICHLET) v = -v + T(2) * w5<T>(i) * kp.wallr[side][a];
-                    st(pop, pidx<M>((9 + 5 * a + OPP5[i]), n), v, kp, false, salt);
-                }
+                const int cx = CX5[i], cy = CY5[i];
+                const bool out = wf.out_x(cx) || wf.out_y(cy);
+                const int side = wf.out_x(cx) ? (cx > 0 ? 1 : 0) : (cy > 0 ? 3 : 2);
+                const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
+                const T v = dir ? -f[a][i] + T(2) * w5<T>(i) * kp.wallr[side][a] : f[a][i];
+                const long long dst = out ? n : nb.at(cx, cy);
+                st(pop, pidx<M>(9 + 5 * a + (out ? OPP5[i] : i), dst), v, kp, false, salt);
             }
     }
 }
