@@ -44,7 +44,7 @@ constexpr int kMaxC = 128;
 constexpr int kFeat = 15;
 constexpr int kSplit = 64;      // split-K factor of the weight gradient
 constexpr int kRed = 256;       // blocks of the first pass of small reductions
-constexpr int LDSK = 40;        // LDS row pitch in bf16 (32 + 8 pad, 16-byte aligned)
+constexpr int LDSK = 40;        // LDS row pitch in bf16 of the convolution tiles (32 + 8 pad, 16-byte aligned)
 
 // ---- features ------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_features(const float* __restrict__ params, const int* __restrict__ idx,
@@ -143,51 +143,74 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const 
 }
 
 // ---- weight gradient: split-K implicit GEMM -------------------------------
-// part[s][tap][co][ci] = sum over the pixel chunks of split s of dZ[p][co] x[p + off(tap)][ci]
+// part[s][tap][co][ci] = sum over the 64-pixel chunks of split s of dZ[p][co] x[p + off(tap)][ci].
+// Both operands are channels-last, the reduction runs over pixels, so tiles are
+// transposed on the way into LDS: each thread loads 8 channels of two adjacent
+// pixels (two 16-byte loads per operand) and writes 8 packed pixel pairs
+// ([channel][pixel] layout, 32-bit stores).  The next chunk's global loads are
+// in flight while the matrix cores work on the current one.
+constexpr int LDSW = 72;  // LDS row pitch (bf16) of the 64-pixel wgrad tiles: 64 + 8 pad, 16-byte rows
+
+__device__ __forceinline__ uint32_t pack_bf16x2(bf16 lo, bf16 hi) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+}
+
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, const bf16* __restrict__ X,
                                                float* __restrict__ part, int H, int W, int P, int Ci, int Co) {
-    __shared__ __attribute__((aligned(16))) bf16 As[64 * LDSK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSK];
+    __shared__ __attribute__((aligned(16))) bf16 As[64 * LDSW];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x << 6, n0 = blockIdx.y << 6;
     const int tap = blockIdx.z % 9, s = blockIdx.z / 9;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const int chunks = P >> 5;
+    const int chunks = P >> 6;
     const int c_begin = (int)((long long)s * chunks / kSplit), c_end = (int)((long long)(s + 1) * chunks / kSplit);
-    const int sk = tid >> 3, sq = tid & 7;  // pixel in chunk (0..31), 8-channel group (0..7)
+    const int pp = tid >> 3, cg = tid & 7;  // pixel pair (0..31), 8-channel group (0..7)
     const int wr = (wave >> 1) << 5, wc = (wave & 1) << 5;
+    const bool bcol = n0 + 8 * cg < Ci;
     floatx4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const bool bcol = n0 + 8 * sq < Ci;
+    uint4 va[2], vb[2];
+    auto load = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const long long p = ((long long)c << 6) + 2 * pp + q;
+            va[q] = *reinterpret_cast<const uint4*>(dZ + p * Co + m0 + 8 * cg);
+            const int img_row = (int)(p / W), xi = (int)(p % W), yi = img_row % H;
+            const int yy = yi + dy, xx = xi + dx;
+            vb[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (bcol && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                vb[q] = *reinterpret_cast<const uint4*>(X + ((long long)(img_row + dy) * W + xx) * Ci + n0 + 8 * cg);
+        }
+    };
+    if (c_begin < c_end) load(c_begin);
     for (int c = c_begin; c < c_end; ++c) {
-        const long long p = ((long long)c << 5) + sk;
-        const int img_row = (int)(p / W), xi = (int)(p % W), yi = img_row % H;
-        // A[co][k] = dZ[p][m0 + co]
-        const uint4 va = *reinterpret_cast<const uint4*>(dZ + p * Co + m0 + 8 * sq);
-        const bf16* ea = reinterpret_cast<const bf16*>(&va);
+        const bf16* a0 = reinterpret_cast<const bf16*>(&va[0]);
+        const bf16* a1 = reinterpret_cast<const bf16*>(&va[1]);
+        const bf16* b0 = reinterpret_cast<const bf16*>(&vb[0]);
+        const bf16* b1 = reinterpret_cast<const bf16*>(&vb[1]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[(8 * sq + e) * LDSK + sk] = ea[e];
-        // B[ci][k] = x[p + off(tap)][n0 + ci]
-        const int yy = yi + dy, xx = xi + dx;
-        uint4 vb = make_uint4(0u, 0u, 0u, 0u);
-        if (bcol && yy >= 0 && yy < H && xx >= 0 && xx < W)
-            vb = *reinterpret_cast<const uint4*>(X + ((long long)(img_row + dy) * W + xx) * Ci + n0 + 8 * sq);
-        const bf16* eb = reinterpret_cast<const bf16*>(&vb);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[(8 * sq + e) * LDSK + sk] = eb[e];
+        for (int e = 0; e < 8; ++e) {
+            *reinterpret_cast<uint32_t*>(&As[(8 * cg + e) * LDSW + 2 * pp]) = pack_bf16x2(a0[e], a1[e]);
+            *reinterpret_cast<uint32_t*>(&Bs[(8 * cg + e) * LDSW + 2 * pp]) = pack_bf16x2(b0[e], b1[e]);
+        }
         __syncthreads();
+        if (c + 1 < c_end) load(c + 1);
         const int r = lane & 15, kq = (lane >> 4) * 8;
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSK + kq]);
-        const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSK + kq]);
-        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + r) * LDSK + kq]);
-        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + 16 + r) * LDSK + kq]);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 64; kk += 32) {
+            const bf16x8 x0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSW + kk + kq]);
+            const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSW + kk + kq]);
+            const bf16x8 y0 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + r) * LDSW + kk + kq]);
+            const bf16x8 y1 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + 16 + r) * LDSW + kk + kq]);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y1, acc[1][1], 0, 0, 0);
+        }
         __syncthreads();
     }
     float* dst = part + ((long long)s * 9 + tap) * Co * Ci;
@@ -217,22 +240,47 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     dW[((long long)co * 9 + tap) * Ci + ci] = s;
 }
 
-// bias gradient, two passes: part[block][co] over pixel ranges, then fixed-order sum
-__global__ __launch_bounds__(128) void k_bgrad_part(const bf16* __restrict__ dZ, long long P, int Co,
+// bias gradient, two passes: part[block][co] over contiguous pixel ranges
+// (16-byte loads of 8 channels, fixed-order reduction through LDS), then a
+// fixed-order sum over the blocks
+__global__ __launch_bounds__(256) void k_bgrad_part(const bf16* __restrict__ dZ, long long P, int Co,
                                                     float* __restrict__ part) {
-    const int co = threadIdx.x;
-    if (co >= Co) return;
+    const int groups = Co >> 3;  // 8 channels per thread; Co is 64 or 128
+    const int g = (int)threadIdx.x % groups, lp = (int)threadIdx.x / groups, per = 256 / groups;
     const long long b0 = P * blockIdx.x / gridDim.x, b1 = P * (blockIdx.x + 1) / gridDim.x;
-    float s = 0.f;
-    for (long long p = b0; p < b1; ++p) s += float(dZ[p * Co + co]);
-    part[(long long)blockIdx.x * kMaxC + co] = s;
+    float s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.f;
+    for (long long p = b0 + lp; p < b1; p += per) {
+        const uint4 v = *reinterpret_cast<const uint4*>(dZ + p * Co + 8 * g);
+        const bf16* e = reinterpret_cast<const bf16*>(&v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += float(e[k]);
+    }
+    __shared__ float red[256][9];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = s[k];
+    __syncthreads();
+    if ((int)threadIdx.x < Co) {
+        const int gg = (int)threadIdx.x >> 3, k = (int)threadIdx.x & 7;
+        float t = 0.f;
+        for (int l = 0; l < per; ++l) t += red[l * groups + gg][k];
+        part[(long long)blockIdx.x * kMaxC + threadIdx.x] = t;
+    }
 }
 __global__ __launch_bounds__(128) void k_bgrad_final(const float* __restrict__ part, int nb, int Co,
                                                      float* __restrict__ db) {
     const int co = threadIdx.x;
     if (co >= Co) return;
+    // sequential order over the blocks; loads issued 16 at a time
     float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[(long long)b * kMaxC + co];
+    for (int b = 0; b < nb; b += 16) {
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = b + k < nb ? part[(long long)(b + k) * kMaxC + co] : 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
+    }
     db[co] = s;
 }
 
@@ -269,7 +317,13 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Z, const 
 __global__ void k_mse_final(const double* __restrict__ part, int nb, double count, float* __restrict__ loss) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
+    for (int b = 0; b < nb; b += 16) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = b + k < nb ? part[b + k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
+    }
     *loss = (float)(s / count);
 }
 
@@ -518,7 +572,7 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
         hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s,
                            ptr<float>(h, h->pl.part_off), Ci, Co, grads + h->pl.woff[l]);
         SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(128), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
+        hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
         SGCHK(hipGetLastError());
         hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(128), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co,
                            grads + h->pl.boff[l]);
