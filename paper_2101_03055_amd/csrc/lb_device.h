@@ -131,7 +131,9 @@ constexpr int kBlk = 1 << kBlkShift;
 template <int M>
 __device__ __forceinline__ long long pidx(int q, long long n) {
     constexpr int NQ = 9 + 5 * M;
-    return (((n >> kBlkShift) * NQ + q) << kBlkShift) | (n & (kBlk - 1));
+    // node part first, population part last: the node part is shared by all
+    // populations of a node and the population part folds into the load offset
+    return ((n >> kBlkShift) * (NQ << kBlkShift) + (n & (kBlk - 1))) + ((long long)q << kBlkShift);
 }
 
 // true when no link of node (x, y) crosses a wall: interior on every walled
