@@ -291,11 +291,22 @@ struct lb_handle {
     int parity;          // 0: canonical layout (own slots); 1: layout left by an even step
     int has_snapshot;
     Launch lc;
+    // cached graph of kGraphSteps single-step launches (FP32/FP64, one step
+    // per launch); rebuilt when the tile shape changes
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    Launch glc{0, 0};
+    ~lb_handle() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
 };
 
 namespace {
 // one row segment of 256 nodes per workgroup on wide grids (measured ~1.5 %
 // faster at 4096^2), 64 x 4 otherwise (measured best on 512 x 256)
+constexpr int kGraphSteps = 64;  // launches per replayed step graph (even)
+
 Launch default_launch(const lb_params& p) { return p.nx >= 1024 ? Launch{256, 1} : Launch{64, 4}; }
 
 void* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
@@ -400,6 +411,33 @@ lb_status lb_step(lb_handle* h, int64_t n) {
             std::swap(h->L.pop_off, h->L.pop2_off);
             std::swap(h->L.sold_off, h->L.sold2_off);
             h->t += 2;
+        }
+    }
+    // long runs of single steps: replay a prebuilt graph of kGraphSteps
+    // launches (one host call instead of kGraphSteps), which keeps small grids
+    // from being limited by the host's launch rate
+    if (h->p.fused_steps != 2 && h->p.storage != LB_STORE_F16 && n >= kGraphSteps + (h->parity ? 1 : 0)) {
+        if (h->parity) {
+            hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, true, h->lc, h->t, h->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+            h->t += 1;
+            h->parity = 0;
+            n -= 1;
+        }
+        if (!h->gexec || h->glc.tile_x != h->lc.tile_x || h->glc.tile_y != h->lc.tile_y) {
+            if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+            if (h->graph) (void)hipGraphDestroy(h->graph);
+            h->gexec = nullptr;
+            h->graph = nullptr;
+            hipError_t e = build_step_graph(h->p, h->L, h->ws, h->kd, h->kf, h->lc, kGraphSteps, &h->graph);
+            if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph: %s", hipGetErrorString(e));
+            h->glc = h->lc;
+        }
+        for (; n >= kGraphSteps; n -= kGraphSteps) {
+            hipError_t e = hipGraphLaunch(h->gexec, h->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph launch: %s", hipGetErrorString(e));
+            h->t += kGraphSteps;
         }
     }
     for (int64_t s = 0; s < n; ++s) {

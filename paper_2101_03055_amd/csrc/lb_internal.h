@@ -63,6 +63,8 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
 // L.pop2_off / L.sold2_off at t + 2
 hipError_t launch_step2(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                         const KParams<float>& kf, int64_t step, hipStream_t s);
+hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                            const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out);
 hipError_t launch_wall_flux(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                             const KParams<float>& kf, bool odd, int side, double* out, hipStream_t s);
 hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,

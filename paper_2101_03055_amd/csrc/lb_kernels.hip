@@ -543,6 +543,56 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
     });
 }
 
+// A graph of `steps` (even) single-step launches, even parity first, each
+// node depending on the previous one.  Built node by node (no stream
+// capture), so it can be launched on any stream, including the null stream.
+// FP32/FP64 only: the FP16 stochastic-rounding salt changes every step.
+hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                            const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out) {
+    if (p.storage == LB_STORE_F16 || steps < 2 || steps % 2) return hipErrorInvalidValue;
+    const int tiles_x = (p.nx + lc.tile_x - 1) / lc.tile_x;
+    const int tiles_y = (p.ny + lc.tile_y - 1) / lc.tile_y;
+    const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)(lc.tile_x * lc.tile_y));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    e = dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
+        using T = typename St<S>::T;
+        S* pop = (S*)at(ws, L.pop_off);
+        T* sold = (T*)at(ws, L.sold_off);
+        KParams<T> kp = kpar<S>(kd, kf);
+        int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
+        uint32_t salt = 0;
+        void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &salt};
+        const bool mrt = p.collision == LB_COLL_MRT;
+        void* fe = mrt ? reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false>)
+                       : reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false>);
+        void* fo = mrt ? reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true>)
+                       : reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true>);
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < steps; ++k) {
+            hipKernelNodeParams np{};
+            np.func = (k & 1) ? fo : fe;
+            np.gridDim = grid;
+            np.blockDim = block;
+            np.sharedMemBytes = 0;
+            np.kernelParams = args;
+            np.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t ee = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            if (ee != hipSuccess) return ee;
+            prev = node;
+        }
+        return hipSuccess;
+    });
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    *out = g;
+    return hipSuccess;
+}
+
 template <class S, int M, int MODEL, int COLL, int TX, int TY>
 static hipError_t launch_step2_t(const KParams<typename St<S>::T>& kp, const Layout& L, void* ws, uint32_t salt,
                                  hipStream_t s) {
