@@ -22,7 +22,10 @@ Prints one JSON line.  Besides the contract's fields:
                  launch per step (FP32, autotuned tile);
   steady_warm_vs_cold  double-diffusive cavities at 128^2 solved to residual
                  1e-8 (batched FP32 phase + FP64 finish) from rest and from the
-                 CNN surrogate's prediction (weights from the surrogate study).
+                 CNN surrogate's prediction (weights from the surrogate study);
+  surrogate      training / inference throughput of the CNN (BF16 MFMA).
+Long runs of steps are replayed by the library as HIP graphs of 64 launches.
+Modes for profiling: --mode pmc | copy | sweep | batch | surrogate.
 """
 from __future__ import annotations
 

@@ -706,6 +706,15 @@ struct lbb_handle {
     std::vector<int2> tiles;
     std::vector<int4> ranges;
     std::vector<double> out;
+    int64_t tiles_gen = 0;           // bumped whenever the device tile list changes
+    hipGraph_t graph = nullptr;      // cached graph of kGraphSteps batched steps (FP32/FP64)
+    hipGraphExec_t gexec = nullptr;
+    int64_t g_gen = -1;
+    Launch g_lc{0, 0};
+    ~lbb_handle() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
 };
 
 namespace {
@@ -779,6 +788,7 @@ void batch_build_tiles(lbb_handle* b) {
 
 lb_status batch_upload(lbb_handle* b) {
     char* w = static_cast<char*>(b->ws);
+    b->tiles_gen += 1;
     HIPCHK(hipMemcpyAsync(w + b->cav_off, b->cav.data(), sizeof(CavRec) * b->count, hipMemcpyHostToDevice, b->stream));
     if (!b->tiles.empty())
         HIPCHK(hipMemcpyAsync(w + b->tiles_off, b->tiles.data(), sizeof(int2) * b->tiles.size(), hipMemcpyHostToDevice,
@@ -898,7 +908,39 @@ lb_status lbb_step(lbb_handle* b, int64_t n) {
     if (!b) return fail(LB_EINVAL, "handle is NULL");
     if (n < 0) return fail(LB_EINVAL, "n < 0");
     char* w = static_cast<char*>(b->ws);
-    for (int64_t s = 0; s < n; ++s) {
+    int64_t left = n;
+    // long runs: replay a prebuilt graph of kGraphSteps launches (rebuilt when
+    // the tile list or the tile shape changes)
+    if (b->p0.storage != LB_STORE_F16 && !b->tiles.empty() && left >= kGraphSteps + (b->cur_parity ? 1 : 0)) {
+        if (b->cur_parity) {
+            hipError_t e = launch_bstep(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
+                                        (const int2*)(w + b->tiles_off), (int)b->tiles.size(), true, b->lc, b->t,
+                                        b->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_step: %s", hipGetErrorString(e));
+            b->cur_parity = 0;
+            b->t += 1;
+            left -= 1;
+        }
+        if (!b->gexec || b->g_gen != b->tiles_gen || b->g_lc.tile_x != b->lc.tile_x || b->g_lc.tile_y != b->lc.tile_y) {
+            if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->gexec = nullptr;
+            b->graph = nullptr;
+            hipError_t e = build_bstep_graph(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
+                                             (const int2*)(w + b->tiles_off), (int)b->tiles.size(), b->lc, kGraphSteps,
+                                             &b->graph);
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_step graph: %s", hipGetErrorString(e));
+            b->g_gen = b->tiles_gen;
+            b->g_lc = b->lc;
+        }
+        for (; left >= kGraphSteps; left -= kGraphSteps) {
+            hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_step graph launch: %s", hipGetErrorString(e));
+            b->t += kGraphSteps;
+        }
+    }
+    for (int64_t s = 0; s < left; ++s) {
         hipError_t e = launch_bstep(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
                                     (const int2*)(w + b->tiles_off), (int)b->tiles.size(), b->cur_parity != 0, b->lc,
                                     b->t, b->stream);

@@ -156,6 +156,53 @@ hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, cons
     });
 }
 
+// Graph of `steps` (even) batched single-step launches, even parity first,
+// chained; same arguments as launch_bstep.  FP32/FP64 only.
+hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
+                             int ntiles, Launch lc, int steps, hipGraph_t* out) {
+    if (p0.storage == LB_STORE_F16 || steps < 2 || steps % 2 || ntiles <= 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)ntiles), block((unsigned)(lc.tile_x * lc.tile_y));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    e = dispatch(p0, [&]<class S, int M, int MODEL>() -> hipError_t {
+        using T = typename St<S>::T;
+        const KParams<T>* kp = static_cast<const KParams<T>*>(kparams);
+        char* w = static_cast<char*>(ws);
+        const CavRec* cv = cav;
+        const int2* tl = tiles;
+        int nt = ntiles, tx = lc.tile_x, ty = lc.tile_y;
+        uint32_t salt = 0;
+        void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &salt};
+        const bool mrt = p0.collision == LB_COLL_MRT;
+        void* fe = mrt ? reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, false>)
+                       : reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, false>);
+        void* fo = mrt ? reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, true>)
+                       : reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, true>);
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < steps; ++k) {
+            hipKernelNodeParams np{};
+            np.func = (k & 1) ? fo : fe;
+            np.gridDim = grid;
+            np.blockDim = block;
+            np.sharedMemBytes = 0;
+            np.kernelParams = args;
+            np.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t ee = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            if (ee != hipSuccess) return ee;
+            prev = node;
+        }
+        return hipSuccess;
+    });
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    *out = g;
+    return hipSuccess;
+}
+
 hipError_t launch_breduce(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
                           int ntiles, const int4* ranges, int nranges, bool odd, Launch lc, int mode, double* part,
                           double* out, hipStream_t s) {

@@ -94,6 +94,8 @@ struct CavRec {
 };
 
 // one step of every listed tile: tiles[k] = (cavity, tile index in the cavity)
+hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
+                             int ntiles, Launch lc, int steps, hipGraph_t* out);
 hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
                         int ntiles, bool odd, Launch lc, int64_t step, hipStream_t s);
 // per-tile partial sums (mode 0 residual + snapshot, 1 snapshot only, 2 mass),

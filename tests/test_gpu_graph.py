@@ -41,3 +41,21 @@ def test_graph_replays_equal_plain_launches(storage, kind):
     fg, hg = lb.lb_populations(g.handle, g.m, g.ny, g.nx)
     fe, he = lb.lb_populations(e.handle, e.m, e.ny, e.nx)
     assert np.array_equal(fg, fe) and np.array_equal(hg, he)
+
+
+def test_batched_graph_replays_equal_plain_launches():
+    cases = [W.ddc(48, Ra=1e4, Pr=0.71, Le=2.0, Nc=1.0, Sr=0.1, Df=0.1),
+             W.random_case(50, 61, seed=42, source=True, fluid_bc=["periodic", "periodic", "noslip", "noslip"],
+                           scalar_bc=[["periodic"] * 2, ["periodic"] * 2, ["noflux"] * 2, ["dirichlet"] * 2]),
+             W.ddc(32, Ra=1e3, Pr=0.71, Le=1.5, Nc=0.5, Sr=0.0, Df=0.3, A=2.0)]
+    for storage in ("f64", "f32"):
+        kw = {"storage": storage, "phi_ref": [0.5, 0.5]} if storage == "f32" else {"storage": storage}
+        g = lb.Batch(cases, **kw)
+        e = lb.Batch(cases, **kw)
+        for n in (64, 131, 70):
+            g.step(n)
+            for _ in range(n):
+                e.step(1)
+            for i in range(len(cases)):
+                for x, y in zip(g.moments(i), e.moments(i)):
+                    assert np.array_equal(x, y), (storage, n, i)
