@@ -157,8 +157,9 @@ def batched_sweep(W, lb, torch):
             "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2)}
 
 
-def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000):
-    """Warm vs cold steady solves (batched FP32 phase + FP64 finish to 1e-8)."""
+def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000, n_plain=4):
+    """Warm vs cold steady solves (batched FP32 phase + FP64 finish to 1e-8),
+    and the plain FP64 method on the first n_plain cavities both converged."""
     from paper_2101_03055_amd import sg, surrogate_study as SS
 
     if not os.path.exists(WEIGHTS):
@@ -177,13 +178,25 @@ def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000):
     warm, fw = SS.solve_path(cases, pred, max_steps=max_steps, label="warm", log=quiet)
     cold, fc = SS.solve_path(cases, None, max_steps=max_steps, label="cold", log=quiet)
     ok = [i for i in range(n_cases) if warm["status"][i] == 1 and cold["status"][i] == 1]
+    # the plain method (FP64, one cavity at a time, from rest) on the first few converged cavities
+    plain_s, plain_err = [], []
+    for i in ok[:n_plain]:
+        _, _, secs, f = SS.plain_solve(cases[i])
+        plain_s.append(secs)
+        plain_err.append(SS.rel_l2(fw[i], f))
+    per_warm = (warm["seconds"] + t_pred) / n_cases
     return {"cases": n_cases, "L": 128, "converged_both": len(ok), "tol": 1e-8,
+            "plain_fp64_s_per_case": round(float(np.mean(plain_s)), 3) if plain_s else None,
+            "warm_batched_s_per_case": round(per_warm, 3),
+            "speedup_vs_plain": round(float(np.mean(plain_s)) / per_warm, 2) if plain_s else None,
+            "warm_relL2_vs_plain_max": max(plain_err, default=None),
             "wall_s_warm": round(warm["seconds"] + t_pred, 2), "wall_s_cold": round(cold["seconds"], 2),
             "speedup": round(cold["seconds"] / (warm["seconds"] + t_pred), 3),
             "steps_warm_median": float(np.median([warm["steps_total"][i] for i in ok])) if ok else None,
             "steps_cold_median": float(np.median([cold["steps_total"][i] for i in ok])) if ok else None,
             "warm_relL2_vs_cold_max": max((SS.rel_l2(fw[i], fc[i]) for i in ok), default=None),
-            "note": "cases that do not become steady within the cap (e.g. Nc near -1) count in both wall times"}
+            "note": "cavities that do not become steady within the cap (e.g. Nc near -1) count in both batched "
+                    "wall times; per-case batched time = batch wall time / cases"}
 
 
 def surrogate_bench(torch, epochs=3, samples=64):

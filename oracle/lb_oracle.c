@@ -574,3 +574,6 @@ int orc_threads(void) {
 }
 
 size_t orc_cfg_size(void) { return sizeof(orc_cfg); }
+
+/* the chemotaxis cut-off r(c) of the record (for pin tests) */
+double orc_cutoff(const orc_cfg *cfg, double c) { return cutoff_r(cfg, c); }

@@ -86,6 +86,8 @@ def lib():
         L.orc_relaxation_matrix.argtypes = [C.c_int, dp, dp]
         L.orc_mrt_basis.argtypes = [dp, dp]
         L.orc_threads.restype = C.c_int
+        L.orc_cutoff.argtypes = [C.POINTER(OrcCfg), C.c_double]
+        L.orc_cutoff.restype = C.c_double
         assert L.orc_cfg_size() == C.sizeof(OrcCfg), "oracle record layout mismatch"
         _lib = L
     return _lib
@@ -217,6 +219,12 @@ def mrt_basis():
     Mi = np.zeros(81)
     assert lib().orc_mrt_basis(M, Mi) == 1
     return M.reshape(9, 9), Mi.reshape(9, 9)
+
+
+def cutoff(wl: dict, c: float) -> float:
+    """r(c) of the workload's cut-off (step or regularised)."""
+    cfg = make_cfg(wl)
+    return float(lib().orc_cutoff(C.byref(cfg), float(c)))
 
 
 def threads() -> int:

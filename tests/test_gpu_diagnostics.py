@@ -96,3 +96,23 @@ def test_ddc_cavity_reproduces_paper_table(Ra):
     # what enters through the hot wall leaves through the cold one
     assert -cold[0] == pytest.approx(hot[0], rel=5e-3)
     assert -cold[1] == pytest.approx(hot[1], rel=5e-3)
+
+
+# Table 3 (aspect ratio A, Ra = 1e5) and Table 4 (S_TC = D_CT, Ra = 1e5, A = 2),
+# Pr = 1, Le = 2, Nc = -2, "Present" columns: (A, S_TC = D_CT) -> (Nu, Sh)
+TABLES34 = {(0.5, 0.1): (2.2893, 4.3113), (1.0, 0.1): (2.8925, 4.9596), (4.0, 0.1): (2.6508, 4.1383),
+            (2.0, -0.2): (2.5609, 4.3020), (2.0, 0.2): (2.9715, 4.7123)}
+
+
+@pytest.mark.parametrize("A,sd", sorted(TABLES34))
+def test_ddc_cavity_aspect_ratio_and_cross_diffusion(A, sd):
+    """128 nodes across the cavity against the paper's 300; within 1 %."""
+    wl, phi0, u0, p0 = W.ddc(128, Ra=1e5, Pr=1.0, Le=2.0, Nc=-2.0, Sr=sd, Df=sd, A=A, u_lat=0.1)
+    s = lb.Solver(wl, phi0, u0, p0)
+    steps, res, st = s.solve_steady(tol=1e-9, check_every=2000, max_steps=4_000_000)
+    hot = lb.lb_wall_flux(s.handle, 0, 2)
+    nu, sh = TABLES34[(A, sd)]
+    print(f"A {A} S=D {sd}: steps {steps} Nu {hot[0]:.5f} ({nu}) Sh {hot[1]:.5f} ({sh})", flush=True)
+    assert st == lb.LB_OK, (steps, res)
+    assert hot[0] == pytest.approx(nu, rel=1e-2)
+    assert hot[1] == pytest.approx(sh, rel=1e-2)

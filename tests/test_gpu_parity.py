@@ -114,6 +114,19 @@ def test_chemotaxis_model(oracle_mod):
     assert moment_errors(o, g) <= TOL64
 
 
+def test_chemotaxis_regularised_cutoff(oracle_mod):
+    """The regularised r(c) of Sec. 3.1.2 (c* inside the range of c, so r varies smoothly)."""
+    wl, phi0, u0, p0 = W.random_case(64, 40, m=2, seed=23, model="chemotaxis",
+                                     fluid_bc=["periodic", "periodic", "noslip", "freeslip"],
+                                     scalar_bc=[["periodic"] * 2, ["periodic"] * 2, ["noflux", "noflux"],
+                                                ["noflux", "dirichlet"]])
+    wl.update({"r_kind": "smooth", "cstar": 1.0, "eps": 0.02})
+    o, g = run_pair(oracle_mod, wl, phi0, u0, p0, 151)
+    ef, eh = pop_errors(o, g)
+    assert ef <= TOL64 and eh <= TOL64
+    assert moment_errors(o, g) <= TOL64
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_mrt(oracle_mod, seed):
     wl, phi0, u0, p0 = W.random_case(50, 61, m=2, seed=30 + seed, collision="mrt",

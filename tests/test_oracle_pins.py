@@ -544,3 +544,24 @@ def test_conduction_cavity_nusselt_closed_form(oracle_mod):
     cold = G.wall_flux(phi, D, wl["wall"][1], 1)
     assert hot == pytest.approx([1.25, 1.1], abs=1e-9)
     assert cold == pytest.approx([-1.25, -1.1], abs=1e-9)
+
+
+# ---- chemotaxis cut-off r(c) (Sec. 3.1.2 regularised form, Sec. 3.1.3 step) ----
+def test_cutoff_step_and_regularised_forms(oracle_mod):
+    wl = W.random_case(8, 6, seed=3, model="chemotaxis")[0]
+    cs = 0.3
+    wl.update({"cstar": cs, "r_kind": "step"})
+    assert oracle_mod.cutoff(wl, cs) == 1.0           # tie goes to r = 1
+    assert oracle_mod.cutoff(wl, cs - 1e-12) == 0.0
+    assert oracle_mod.cutoff(wl, 0.9) == 1.0
+    eps = 0.02
+    wl.update({"r_kind": "smooth", "eps": eps})
+    assert oracle_mod.cutoff(wl, cs) == pytest.approx(0.5, abs=1e-15)
+    assert oracle_mod.cutoff(wl, cs + eps) == pytest.approx(0.5 * (1 + 2 ** -0.5), abs=1e-15)
+    for d in (1e-3, 0.01, 0.1, 0.5):                   # point symmetry about (c*, 1/2)
+        assert oracle_mod.cutoff(wl, cs + d) + oracle_mod.cutoff(wl, cs - d) == pytest.approx(1.0, abs=1e-15)
+    vals = [oracle_mod.cutoff(wl, c) for c in np.linspace(0, 1, 41)]
+    assert all(b > a for a, b in zip(vals, vals[1:]))  # strictly increasing
+    wl["eps"] = 1e-9                                   # the step is its eps -> 0 limit
+    assert oracle_mod.cutoff(wl, cs + 1e-4) == pytest.approx(1.0, abs=1e-9)
+    assert oracle_mod.cutoff(wl, cs - 1e-4) == pytest.approx(0.0, abs=1e-9)
