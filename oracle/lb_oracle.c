@@ -33,6 +33,15 @@
  *     the domain through a corner (two walls) bounces back.
  *   - MRT (an option the paper does not define) uses the Lallemand-Luo D2Q9
  *     moment basis; with all rates equal to omega it is BGK.
+ *
+ * CASE 1 (model 2, the convection cross-diffusion equation without a fluid,
+ * Sec. 2): the velocity u(x) is prescribed and constant in time; there are no
+ * fluid populations.  The auxiliary source is G_i = (I - omega/2) W_i c_i .
+ * d_t(phi u) / cs^2 with the time derivative taken by the first-order backward
+ * difference the paper points to, u (phi(t) - phi(t - dt)) / dt; phi(-dt) is
+ * phi0, so G vanishes at the first step.  For this model the h array holds,
+ * per node, u_x, u_y in planes 0, 1 and phi(t - dt) in planes 2 .. 2 + m - 1;
+ * those values stay at their node (no streaming).
  */
 #include <math.h>
 #include <stdint.h>
@@ -48,7 +57,9 @@
 typedef struct orc_cfg {
     int32_t nx, ny, m;
     int32_t model;          /* 0: linear closures  (D const, S = K phi, F = F0 + Fphi phi)
-                               1: chemotaxis closures (Sec. 3.1) */
+                               1: chemotaxis closures (Sec. 3.1)
+                               2: no fluid (Case 1 of Sec. 2): prescribed constant velocity,
+                                  linear closures without force; see CASE 1 below */
     int32_t collision;      /* 0: BGK (Eq. evolution3), 1: MRT */
     int32_t r_kind;         /* chemotaxis cut-off: 0 step, 1 regularised (Sec. 3.1.2) */
     int32_t mutation;       /* 0 = faithful; k > 0 plants mistake k (pin self-test only) */
@@ -310,6 +321,13 @@ static void node_moments(const orc_cfg *cfg, const double *f /*[m][5]*/, const d
         mc->phi[a] = 0.0;
         for (int i = 0; i < 5; ++i) mc->phi[a] += f[a * 5 + i];
     }
+    if (cfg->model == 2) { /* Case 1: prescribed velocity, no force, no pressure */
+        mc->F[0] = mc->F[1] = 0.0;
+        mc->u[0] = h[0];
+        mc->u[1] = h[1];
+        mc->p = 0.0;
+        return;
+    }
     body_force(cfg, mc->phi, mc->F);
     /* Eq. sum-u */
     double half = (cfg->mutation == 4) ? 0.0 : dt / 2.0;
@@ -361,7 +379,21 @@ static int collide_node(const orc_cfg *cfg, const double Minv[9][9], const doubl
     orc_feq(m, mc.phi, ueq, feq);
     orc_heq(mc.p, mc.u, cfg->rho0, heq);
     orc_force_pop(mc.F, Fi);
-    orc_aux_source(m, omega, mc.phi, S, mc.u, mc.F, Gi);
+    if (cfg->model == 2) {
+        /* Case 1: G_i = (I - omega/2) W_i c_i . u (phi - phi_prev) / (dt cs^2) */
+        for (int a = 0; a < m; ++a) {
+            double g[2] = {0.0, 0.0};
+            for (int b = 0; b < m; ++b) {
+                double cf = (a == b ? 1.0 : 0.0) - omega[a * m + b] / 2.0;
+                double dphi = (mc.phi[b] - h[2 + b]) / dt;
+                g[0] += cf * mc.u[0] * dphi;
+                g[1] += cf * mc.u[1] * dphi;
+            }
+            for (int i = 0; i < 5; ++i) Gi[a * 5 + i] = W5x(i, e5[i][0] * g[0] + e5[i][1] * g[1]) / cs2;
+        }
+    } else {
+        orc_aux_source(m, omega, mc.phi, S, mc.u, mc.F, Gi);
+    }
     if (cfg->mutation == 1)
         for (int k = 0; k < m * 5; ++k) Gi[k] = 0.0;
     orc_source_pop(m, S, Si);
@@ -378,6 +410,11 @@ static int collide_node(const orc_cfg *cfg, const double Minv[9][9], const doubl
         }
     for (int a = 0; a < m; ++a) Snew[a] = S[a];
 
+    if (cfg->model == 2) { /* Case 1: no fluid; remember phi(t) for the next difference */
+        for (int i = 0; i < 9; ++i) hs[i] = h[i];
+        for (int a = 0; a < m; ++a) hs[2 + a] = mc.phi[a];
+        return 1;
+    }
     /* Eq. evolution3 (BGK), or its MRT counterpart */
     double w = 1.0 / cfg->tau_f;
     double fcoef = (cfg->mutation == 5) ? (1.0 + w / 2.0) : (1.0 - w / 2.0);
@@ -449,6 +486,12 @@ int orc_init(const orc_cfg *cfg, const double *phi0, const double *u0, const dou
                 Sold[a * N + n] = S[a];
             }
             for (int i = 0; i < 9; ++i) h[i * N + n] = heq[i];
+            if (cfg->model == 2) { /* Case 1: prescribed velocity and phi(-dt) = phi0 */
+                for (int i = 0; i < 9; ++i) h[i * N + n] = 0.0;
+                h[0 * N + n] = u[0];
+                h[1 * N + n] = u[1];
+                for (int a = 0; a < m; ++a) h[(2 + a) * N + n] = phi[a];
+            }
         }
     return 1;
 }
@@ -506,12 +549,16 @@ int orc_step(const orc_cfg *cfg, double *f, double *h, double *Sold, int64_t nst
                 for (int i = 0; i < 9; ++i) hl[i] = h[i * N + n];
                 if (!collide_node(cfg, Minv, fl, hl, so, fs, hs, sn)) ok = 0;
                 for (int a = 0; a < m; ++a) Sold[a * N + n] = sn[a];
-                /* fluid streaming */
-                for (int i = 0; i < 9; ++i) {
-                    int pl;
-                    size_t dn;
-                    fluid_dest(cfg, x, y, i, &pl, &dn);
-                    h2[pl * N + dn] = hs[i];
+                /* fluid streaming (Case 1: the per-node values stay in place) */
+                if (cfg->model == 2) {
+                    for (int i = 0; i < 9; ++i) h2[i * N + n] = hs[i];
+                } else {
+                    for (int i = 0; i < 9; ++i) {
+                        int pl;
+                        size_t dn;
+                        fluid_dest(cfg, x, y, i, &pl, &dn);
+                        h2[pl * N + dn] = hs[i];
+                    }
                 }
                 /* scalar streaming: D2Q5 links cross at most one wall */
                 for (int a = 0; a < m; ++a)

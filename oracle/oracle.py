@@ -25,7 +25,7 @@ MAXM = 4
 # codes used by the oracle's record (its own; the GPU library has its own)
 FLUID = {"periodic": 0, "noslip": 1, "freeslip": 2}
 SCALAR = {"periodic": 0, "noflux": 1, "dirichlet": 2}
-MODEL = {"linear": 0, "chemotaxis": 1}
+MODEL = {"linear": 0, "chemotaxis": 1, "cde": 2}
 
 
 class OrcCfg(C.Structure):
