@@ -23,9 +23,10 @@ Prints one JSON line.  Besides the contract's fields:
   steady_warm_vs_cold  double-diffusive cavities at 128^2 solved to residual
                  1e-8 (batched FP32 phase + FP64 finish) from rest and from the
                  CNN surrogate's prediction (weights from the surrogate study);
-  surrogate      training / inference throughput of the CNN (BF16 MFMA).
+  surrogate      training / inference throughput of the CNN (BF16 MFMA);
+  cde_sweep      the no-fluid model (prescribed velocity) on 4096^2.
 Long runs of steps are replayed by the library as HIP graphs of 64 launches.
-Modes for profiling: --mode pmc | copy | sweep | batch | surrogate.
+Modes for profiling: --mode pmc | copy | sweep | batch | surrogate | cde.
 """
 from __future__ import annotations
 
@@ -143,6 +144,28 @@ def hbm_sweep(W, lb, torch):
     return out
 
 
+def cde_sweep(W, lb, torch, n=4096):
+    """Case 1 (no fluid): two species in a prescribed cellular flow on n^2,
+    periodic, FP64 and FP32.  Algorithmic bytes per lattice update: the 5m
+    populations read and written, the prescribed velocity read, the previous
+    phi read and written."""
+    out = {}
+    for storage in ("f64", "f32"):
+        wl, phi0, u0, p0 = W.cde_case(n, n, m=2, seed=1)
+        s = lb.Solver(wl, phi0, u0, p0, storage=storage, phi_ref=[1.0, 1.0])
+        s.step(20)
+        kt = kernel_time(s.step, s.stream, 100)
+        b = 8 if storage == "f64" else 4
+        bb = 2 * 10 * b + (2 + 2 * 2) * b
+        ach = bb * n * n / kt / 1e9
+        out[f"{storage}_{n}x{n}"] = {"MLUPS": round(n * n / kt / 1e6, 1), "achieved_GBs": round(ach, 1),
+                                     "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2),
+                                     "bytes_per_lu": bb}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_sweep(W, lb, torch):
     pds = W.sweep_params(256, seed=4)
     cases = [W.ddc_case(pd) for pd in pds]
@@ -248,7 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "surrogate"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "surrogate", "cde"], default="bench",
                     help="pmc: only the timed workload's step kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy to calibrate the byte counters; "
                          "sweep / batch: only the 4096^2 or the batched-cavity leg (for profiles)")
@@ -273,6 +296,9 @@ def main():
         return
     if args.mode == "sweep":
         print(json.dumps({"hbm_sweep": hbm_sweep(W, lb, torch)}), flush=True)
+        return
+    if args.mode == "cde":
+        print(json.dumps({"cde_sweep": cde_sweep(W, lb, torch)}), flush=True)
         return
     if args.mode == "surrogate":
         print(json.dumps({"surrogate": surrogate_bench(torch)}), flush=True)
@@ -320,6 +346,7 @@ def main():
         del s64
         out["hbm_sweep"] = hbm_sweep(W, lb, torch)
         out["batched_sweep"] = batched_sweep(W, lb, torch)
+        out["cde_sweep"] = cde_sweep(W, lb, torch)
         torch.cuda.empty_cache()
         out["steady_warm_vs_cold"] = steady_warm_vs_cold(W, torch)
         out["surrogate"] = surrogate_bench(torch)

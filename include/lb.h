@@ -60,8 +60,16 @@ typedef enum lb_status {
 
 /* closures */
 enum { LB_MODEL_LINEAR = 0,      /* D constant, S = K phi, F = F0 + sum_a Fphi[a] phi_a  (DDC, Sec. 3.2) */
-       LB_MODEL_CHEMOTAXIS = 1 };/* m = 2, (n, c): D = [[D00, D01 - chi r(c) n], [D10, D11]],
+       LB_MODEL_CHEMOTAXIS = 1,  /* m = 2, (n, c): D = [[D00, D01 - chi r(c) n], [D10, D11]],
                                     S = (0, -beta r(c) n), F = F0 + sum_a Fphi[a] phi_a  (Sec. 3.1) */
+       LB_MODEL_CDE = 2 };       /* Case 1 of Sec. 2, no fluid: the convection cross-diffusion equation
+                                    with a prescribed velocity (u0 of lb_init, constant in time); D
+                                    constant, S = K phi, no force (F0, Fphi must be 0).  The auxiliary
+                                    source uses d_t(phi u) = u (phi(t) - phi(t - dt)) / dt, phi(-dt) =
+                                    phi0.  Storage F64 or F32, BGK only, one step per launch, not in
+                                    batches; lb_moments returns the prescribed u and p = 0, lb_mass
+                                    returns 0 for the fluid sum, lb_populations fills h with 0;
+                                    lb_wall_flux and lb_copy_state are not available. */
 /* population storage in device memory */
 enum { LB_STORE_F64 = 0,         /* raw populations, FP64 arithmetic */
        LB_STORE_F32 = 1,         /* deviations f - W_i phi_ref, h - rho0 delta_i0 in FP32, FP32 arithmetic */

@@ -67,14 +67,17 @@ Layout make_layout(const lb_params& p) {
     // populations in blocks of 64 nodes (see pidx in lb_device.h)
     L.plane = round_up(L.N, 64);
     const size_t pb = round_up(L.plane * L.elem, 256);
-    L.npop = 9 + 5 * (size_t)p.m;
+    const bool cde = p.model == LB_MODEL_CDE;
+    L.npop = (cde ? 0 : 9) + 5 * (size_t)p.m;
     L.nsrc = (size_t)__builtin_popcount(source_mask(p));
+    L.naux = cde ? 2 + (size_t)p.m : 0;
     size_t off = 0;
     L.pop_off = off;
     off += L.npop * pb;
     off = round_up(off, 256);
     L.sold_off = off;
-    off += round_up(L.nsrc * L.N * arith_bytes(p.storage), 256);
+    L.aux_off = off + L.nsrc * L.N * arith_bytes(p.storage);
+    off += round_up((L.nsrc + L.naux) * L.N * arith_bytes(p.storage), 256);
     L.snap_off = off;
     off += round_up((size_t)(p.m + 2) * L.N * 8, 256);
     L.stage_off = off;
@@ -174,7 +177,16 @@ lb_status validate(const lb_params* p) {
     if (p->nx < 2 || p->ny < 2) return fail(LB_EINVAL, "grid %d x %d: each side must be >= 2", p->nx, p->ny);
     if ((long long)p->nx * p->ny > (1ll << 31) - 1) return fail(LB_EINVAL, "grid too large");
     if (p->m < 1 || p->m > LB_MAX_M) return fail(LB_EINVAL, "m = %d outside 1..%d", p->m, LB_MAX_M);
-    if (p->model != LB_MODEL_LINEAR && p->model != LB_MODEL_CHEMOTAXIS) return fail(LB_EINVAL, "unknown model");
+    if (p->model != LB_MODEL_LINEAR && p->model != LB_MODEL_CHEMOTAXIS && p->model != LB_MODEL_CDE)
+        return fail(LB_EINVAL, "unknown model");
+    if (p->model == LB_MODEL_CDE) {
+        if (p->storage == LB_STORE_F16) return fail(LB_EINVAL, "no-fluid model: storage must be F64 or F32");
+        if (p->collision != LB_COLL_BGK) return fail(LB_EINVAL, "no-fluid model: collision must be BGK (no fluid)");
+        if (p->fused_steps == 2) return fail(LB_EINVAL, "no-fluid model: one step per launch only");
+        if (p->F0[0] != 0.0 || p->F0[1] != 0.0) return fail(LB_EINVAL, "no-fluid model: no body force");
+        for (int a = 0; a < LB_MAX_M; ++a)
+            if (p->Fphi[a][0] != 0.0 || p->Fphi[a][1] != 0.0) return fail(LB_EINVAL, "no-fluid model: no body force");
+    }
     if (p->model == LB_MODEL_CHEMOTAXIS && p->m != 2) return fail(LB_EINVAL, "chemotaxis model needs m = 2");
     if (p->storage < LB_STORE_F64 || p->storage > LB_STORE_F16) return fail(LB_EINVAL, "unknown storage");
     if (p->collision != LB_COLL_BGK && p->collision != LB_COLL_MRT) return fail(LB_EINVAL, "unknown collision");
@@ -205,7 +217,7 @@ lb_status validate(const lb_params* p) {
     const int m = p->m;
     for (int k = 0; k < m * m; ++k)
         if (!std::isfinite(p->D[k]) || !std::isfinite(p->K[k])) return fail(LB_EINVAL, "D or K not finite");
-    if (p->model == LB_MODEL_LINEAR) {
+    if (p->model == LB_MODEL_LINEAR || p->model == LB_MODEL_CDE) {
         std::complex<double> lam[LB_MAX_M];
         eigenvalues(m, p->D, lam);
         for (int k = 0; k < m; ++k)
@@ -246,7 +258,7 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     k.rho0_eff = T(shifted ? 0.0 : p.rho0);
     k.h0_shift = T(shifted ? p.rho0 : 0.0);
     const int m = p.m;
-    if (p.model == LB_MODEL_LINEAR) {
+    if (p.model == LB_MODEL_LINEAR || p.model == LB_MODEL_CDE) {
         double A[LB_MAX_M * LB_MAX_M], om[LB_MAX_M * LB_MAX_M];
         for (int a = 0; a < m; ++a)
             for (int b = 0; b < m; ++b) A[a * m + b] = 3.0 * p.D[a * m + b] + (a == b ? 0.5 : 0.0);
@@ -307,7 +319,20 @@ namespace {
 // faster at 4096^2), 64 x 4 otherwise (measured best on 512 x 256)
 constexpr int kGraphSteps = 64;  // launches per replayed step graph (even)
 
-Launch default_launch(const lb_params& p) { return p.nx >= 1024 ? Launch{256, 1} : Launch{64, 4}; }
+// working sets up to this size (population bytes) take the non-temporal
+// population accesses: measured faster while the state fits the 256 MB MALL,
+// slower on grids far beyond it
+constexpr size_t kNtMaxBytes = size_t(64) << 20;
+
+int small_state(const lb_params& p) {
+    const size_t q = (p.model == LB_MODEL_CDE ? 0 : 9) + 5 * (size_t)p.m;
+    return q * (size_t)p.nx * (size_t)p.ny * elem_bytes(p.storage) <= kNtMaxBytes ? 1 : 0;
+}
+
+Launch default_launch(const lb_params& p) {
+    const int nt = small_state(p);
+    return p.nx >= 1024 ? Launch{256, 1, nt} : Launch{64, 4, nt};
+}
 
 void* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
@@ -330,7 +355,7 @@ uint64_t fnv(const void* data, size_t n) {
     return h;
 }
 
-size_t sold_bytes(const lb_handle* h) { return h->L.nsrc * h->L.N * arith_bytes(h->p.storage); }
+size_t sold_bytes(const lb_handle* h) { return (h->L.nsrc + h->L.naux) * h->L.N * arith_bytes(h->p.storage); }
 size_t snap_bytes(const lb_handle* h) { return (size_t)(h->p.m + 2) * h->L.N * 8; }
 size_t pop_bytes(const lb_handle* h) { return h->L.npop * h->L.plane * h->L.elem; }
 }  // namespace
@@ -383,7 +408,9 @@ lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace
     hipError_t e = hipMemcpyAsync(stage, phi0, m * N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(stage + m * N, u0, 2 * N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && p0) e = hipMemcpyAsync(stage + (m + 2) * N, p0, N * 8, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = launch_init(h->p, L, h->ws, h->kd, h->kf, p0 ? 1 : 0, h->stream);
+    if (e == hipSuccess)
+        e = h->p.model == LB_MODEL_CDE ? launch_cde_init(h->p, L, h->ws, h->kd, h->kf, h->stream)
+                                       : launch_init(h->p, L, h->ws, h->kd, h->kf, p0 ? 1 : 0, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -396,6 +423,15 @@ lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace
 lb_status lb_step(lb_handle* h, int64_t n) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (n < 0) return fail(LB_EINVAL, "n = %lld < 0", (long long)n);
+    if (h->p.model == LB_MODEL_CDE) {
+        for (int64_t s = 0; s < n; ++s) {
+            hipError_t e = launch_cde_step(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, h->lc, h->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+            h->t += 1;
+            h->parity ^= 1;
+        }
+        return LB_OK;
+    }
     if (h->p.fused_steps == 2) {
         // finish a pending AA odd step, then two steps per launch, a last single even step if n is odd
         if (h->parity && n > 0) {
@@ -450,9 +486,17 @@ lb_status lb_step(lb_handle* h, int64_t n) {
     return LB_OK;
 }
 
+// first and second reduction pass of either model
+static hipError_t reduce_any(lb_handle* h, int mode, hipStream_t s) {
+    return h->p.model == LB_MODEL_CDE ? launch_cde_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, mode, s)
+                                      : launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, mode, s);
+}
+
 lb_status lb_moments_device(lb_handle* h, double* d_phi, double* d_u, double* d_p) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
-    hipError_t e = launch_moments(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, d_phi, d_u, d_p, h->stream);
+    hipError_t e = h->p.model == LB_MODEL_CDE
+                       ? launch_cde_moments(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, d_phi, d_u, d_p, h->stream)
+                       : launch_moments(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, d_phi, d_u, d_p, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_moments_device: %s", hipGetErrorString(e));
     return LB_OK;
 }
@@ -478,7 +522,7 @@ lb_status lb_residual(lb_handle* h, double* res) {
     if (!res) return fail(LB_EINVAL, "res is NULL");
     const int Q = h->p.m + 2;
     const int mode = h->has_snapshot ? 0 : 1;
-    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, mode, h->stream);
+    hipError_t e = reduce_any(h, mode, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_residual: %s", hipGetErrorString(e));
     double out[64];
     HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (3 * Q + 1), hipMemcpyDeviceToHost,
@@ -525,6 +569,7 @@ out:
 lb_status lb_wall_flux(lb_handle* h, int32_t side, double* flux) {
     if (!h || !flux) return fail(LB_EINVAL, "NULL argument");
     if (side < 0 || side > 3) return fail(LB_EINVAL, "side must be 0..3");
+    if (h->p.model == LB_MODEL_CDE) return fail(LB_EINVAL, "lb_wall_flux: not available for the no-fluid model");
     for (int a = 0; a < h->p.m; ++a)
         if (h->p.scalar_bc[side][a] != LB_SBC_DIRICHLET)
             return fail(LB_EINVAL, "side %d is not a Dirichlet wall for species %d", side, a);
@@ -542,7 +587,7 @@ lb_status lb_mass(lb_handle* h, double* mass) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (!mass) return fail(LB_EINVAL, "mass is NULL");
     const int Q = h->p.m + 2;
-    hipError_t e = launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, 2, h->stream);
+    hipError_t e = reduce_any(h, 2, h->stream);
     if (e != hipSuccess) return fail(LB_EDEVICE, "lb_mass: %s", hipGetErrorString(e));
     double out[64];
     HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (2 * Q + 1), hipMemcpyDeviceToHost,
@@ -555,6 +600,21 @@ lb_status lb_mass(lb_handle* h, double* mass) {
 
 lb_status lb_populations(lb_handle* h, double* f, double* hpop) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (h->p.model == LB_MODEL_CDE) {  // scalar planes only; no fluid populations
+        const size_t N = h->L.N;
+        if (hpop) std::memset(hpop, 0, 9 * N * sizeof(double));
+        if (!f) return LB_OK;
+        const int chunk = h->p.m + 3, total = 5 * h->p.m;
+        double* stage = (double*)at(h->ws, h->L.stage_off);
+        for (int b = 0; b < total; b += chunk) {
+            const int cnt = std::min(chunk, total - b);
+            hipError_t e = launch_cde_export(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, b, cnt, stage, h->stream);
+            if (e != hipSuccess) return fail(LB_EDEVICE, "lb_populations: %s", hipGetErrorString(e));
+            HIPCHK(hipMemcpyAsync(f + (size_t)b * N, stage, (size_t)cnt * N * 8, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+        return LB_OK;
+    }
     const size_t N = h->L.N, m = (size_t)h->p.m;
     const int chunk = h->p.m + 3;  // planes the staging area holds
     const int total = 9 + 5 * h->p.m;
@@ -632,6 +692,8 @@ lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes) {
 
 lb_status lb_copy_state(lb_handle* dst, lb_handle* src) {
     if (!dst || !src) return fail(LB_EINVAL, "handle is NULL");
+    if (dst->p.model == LB_MODEL_CDE || src->p.model == LB_MODEL_CDE)
+        return fail(LB_EINVAL, "lb_copy_state: not available for the no-fluid model");
     lb_params a = dst->p, b = src->p;
     a.storage = b.storage = 0;
     for (int k = 0; k < LB_MAX_M; ++k) a.phi_ref[k] = b.phi_ref[k] = 0.0;
@@ -667,7 +729,7 @@ lb_status lb_set_tile(lb_handle* h, int32_t tile_x, int32_t tile_y) {
     }
     if (tile_x < 64 || tile_x % 64 || tile_y < 1 || tile_x * tile_y > 256)
         return fail(LB_EINVAL, "tile %d x %d: tile_x must be a multiple of 64, tile_x * tile_y <= 256", tile_x, tile_y);
-    h->lc = Launch{tile_x, tile_y};
+    h->lc = Launch{tile_x, tile_y, h->lc.nt};
     return LB_OK;
 }
 
@@ -826,6 +888,7 @@ lb_status lbb_workspace_bytes(const lb_params* params, int32_t count, size_t* by
         if (!same_template(params[0], params[c]))
             return fail(LB_EINVAL, "cavity %d: m, model, storage, collision and r_kind must match cavity 0", c);
         if (params[c].fused_steps == 2) return fail(LB_EINVAL, "cavity %d: the batched sweep takes one step per launch", c);
+        if (params[c].model == LB_MODEL_CDE) return fail(LB_EINVAL, "cavity %d: the no-fluid model is not batched", c);
     }
     *bytes = batch_plan(params, count, nullptr);
     return LB_OK;
@@ -868,7 +931,9 @@ lb_status lbb_init(const lb_params* params, int32_t count, void* dev_workspace, 
     b->out.assign((size_t)64 * count, 0.0);
     b->cur_parity = 0;
     b->t = 0;
-    b->lc = Launch{64, 4};
+    size_t state = 0;
+    for (int c = 0; c < count; ++c) state += b->L[c].npop * b->L[c].plane * b->L[c].elem;
+    b->lc = Launch{64, 4, state <= kNtMaxBytes ? 1 : 0};
     char* w = static_cast<char*>(b->ws);
     for (int c = 0; c < count; ++c) {
         fill_kparams(b->p[c], b->L[c], b->kd[c]);
@@ -1023,7 +1088,7 @@ lb_status lbb_set_tile(lbb_handle* b, int32_t tile_x, int32_t tile_y) {
     bool ok = false;
     for (const auto& tc : kTileCand) ok |= (tc[0] == tile_x && tc[1] == tile_y);
     if (!ok) return fail(LB_EINVAL, "tile %d x %d is not one of the supported batch tiles", tile_x, tile_y);
-    b->lc = Launch{tile_x, tile_y};
+    b->lc = Launch{tile_x, tile_y, b->lc.nt};
     batch_build_tiles(b);
     return batch_upload(b);
 }

@@ -15,7 +15,7 @@
 
 namespace lbk {
 
-template <class S, int M, int MODEL, int COLL, bool ODD>
+template <class S, int M, int MODEL, int COLL, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>* __restrict__ kps,
                                                const CavRec* __restrict__ cav, const int2* __restrict__ tiles,
                                                int ntiles, char* __restrict__ ws, int tile_x, int tile_y,
@@ -36,19 +36,34 @@ __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>*
     T* sold = reinterpret_cast<T*>(ws + cr.sold_off);
 
     T h[9], f[M][5], Sold[M], Snew[M];
-    gather<S, M, ODD>(kp, pop, x, y, h, f);
+    gather<S, M, ODD, NT>(kp, pop, x, y, h, f);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         Sold[a] = T(0);
-        if (kp.src_mask >> a & 1) Sold[a] = sold[(long long)(k++) * N + n];
+        if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
     collide<T, M, MODEL, COLL>(kp, h, f, Sold, Snew);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)
-        if (kp.src_mask >> a & 1) sold[(long long)(k++) * N + n] = Snew[a];
-    scatter<S, M, ODD>(kp, pop, x, y, h, f, salt);
+        if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold[(long long)(k++) * N + n]);
+    scatter<S, M, ODD, NT>(kp, pop, x, y, h, f, salt);
+}
+
+// the batched step kernel for a collision kind, parity and cache hint
+template <class S, int M, int MODEL>
+static const void* bstep_kernel(bool mrt, bool odd, bool nt) {
+    const void* const fns[8] = {
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, false, false>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, false, true>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, true, false>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, true, true>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, false, false>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, false, true>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, true, false>),
+        reinterpret_cast<const void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, true, true>)};
+    return fns[(mrt ? 4 : 0) + (odd ? 2 : 0) + (nt ? 1 : 0)];
 }
 
 template <class S, int M, bool ODD>
@@ -137,22 +152,13 @@ hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, cons
         using T = typename St<S>::T;
         const KParams<T>* kp = static_cast<const KParams<T>*>(kparams);
         char* w = static_cast<char*>(ws);
-        if (p0.collision == LB_COLL_MRT) {
-            if (odd)
-                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_MRT, true>), grid, block, 0, s, kp, cav, tiles, ntiles,
-                                   w, lc.tile_x, lc.tile_y, salt);
-            else
-                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_MRT, false>), grid, block, 0, s, kp, cav, tiles,
-                                   ntiles, w, lc.tile_x, lc.tile_y, salt);
-        } else {
-            if (odd)
-                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_BGK, true>), grid, block, 0, s, kp, cav, tiles, ntiles,
-                                   w, lc.tile_x, lc.tile_y, salt);
-            else
-                hipLaunchKernelGGL((k_bstep<S, M, MODEL, LB_COLL_BGK, false>), grid, block, 0, s, kp, cav, tiles,
-                                   ntiles, w, lc.tile_x, lc.tile_y, salt);
-        }
-        return hipGetLastError();
+        const CavRec* cv = cav;
+        const int2* tl = tiles;
+        int nt = ntiles, tx = lc.tile_x, ty = lc.tile_y;
+        uint32_t sl = salt;
+        void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &sl};
+        const void* fn = bstep_kernel<S, M, MODEL>(p0.collision == LB_COLL_MRT, odd, lc.nt != 0);
+        return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
 }
 
@@ -175,10 +181,8 @@ hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams,
         uint32_t salt = 0;
         void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &salt};
         const bool mrt = p0.collision == LB_COLL_MRT;
-        void* fe = mrt ? reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, false>)
-                       : reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, false>);
-        void* fo = mrt ? reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_MRT, true>)
-                       : reinterpret_cast<void*>(&k_bstep<S, M, MODEL, LB_COLL_BGK, true>);
+        void* fe = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, false, lc.nt != 0));
+        void* fo = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, true, lc.nt != 0));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
             hipKernelNodeParams np{};

@@ -64,12 +64,33 @@ struct St<_Float16> {
 
 // FP16 deviations carry one scale for the fluid planes (0..8) and one for
 // the scalar planes; FP32/FP64 are unscaled
-template <class S, class T>
+// Population loads and stores, plain or with the non-temporal hint (NT).  The
+// hint pays on launches whose working set stays in the caches (every value is
+// read once and written once per step; the plume step at 512 x 256 went from
+// 4.9 to 4.45 us) but costs bandwidth on grids far beyond them (4096^2 FP32:
+// 463 -> 500 us, the odd step's shifted accesses share cache lines between
+// neighbouring wavefronts), so the launcher chooses it by working-set size.
+template <bool NT, class S>
+__device__ __forceinline__ S load_raw(const S* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT, class S>
+__device__ __forceinline__ void store_raw(S v, S* p) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <bool NT = false, class S, class T>
 __device__ __forceinline__ T ld(const S* p, const KParams<T>& kp, bool fluid) {
     if constexpr (St<S>::scaled)
-        return T(*p) * (fluid ? kp.inv_scale_h : kp.inv_scale);
+        return T(load_raw<NT>(p)) * (fluid ? kp.inv_scale_h : kp.inv_scale);
     else
-        return T(*p);
+        return T(load_raw<NT>(p));
 }
 // 32-bit integer mixer (Wellons' "lowbias32"), used as a counter-based
 // generator for stochastic rounding
@@ -95,12 +116,12 @@ __device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t key) {
     return _Float16(__uint_as_float(b));
 }
 
-template <class S, class T>
+template <bool NT = false, class S, class T>
 __device__ __forceinline__ void st(S* base, long long idx, T v, const KParams<T>& kp, bool fluid, uint32_t salt) {
     if constexpr (St<S>::scaled)
-        base[idx] = to_half_sr(v * (fluid ? kp.scale_h : kp.scale), (uint32_t)idx * 0x9e3779b9u ^ salt);
+        store_raw<NT>(to_half_sr(v * (fluid ? kp.scale_h : kp.scale), (uint32_t)idx * 0x9e3779b9u ^ salt), base + idx);
     else
-        base[idx] = S(v);
+        store_raw<NT>(S(v), base + idx);
 }
 
 // ---- geometry helpers -------------------------------------------------------
@@ -179,29 +200,29 @@ struct WallFlags {
 // Canonical pre-collision populations of node (x, y).  PULL = false: the own
 // slots (state after an odd step or initialisation).  PULL = true: the state
 // left by an even step, read from the upstream neighbours with the wall rules.
-template <class S, int M, bool PULL, class T>
+template <class S, int M, bool PULL, bool NT = false, class T>
 __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict__ pop, int x, int y,
                                        T h[9], T f[M][5]) {
     const int nx = kp.nx;
     const long long n = (long long)y * nx + x;
     if constexpr (!PULL) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) h[i] = ld(pop + pidx<M>(i, n), kp, true);
+        for (int i = 0; i < 9; ++i) h[i] = ld<NT>(pop + pidx<M>(i, n), kp, true);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + pidx<M>((9 + 5 * a + i), n), kp, false);
+            for (int i = 0; i < 5; ++i) f[a][i] = ld<NT>(pop + pidx<M>((9 + 5 * a + i), n), kp, false);
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             Nbr nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) h[i] = ld(pop + pidx<M>(OPP9[i], nb.at(-CX9[i], -CY9[i])), kp, true);
+            for (int i = 0; i < 9; ++i) h[i] = ld<NT>(pop + pidx<M>(OPP9[i], nb.at(-CX9[i], -CY9[i])), kp, true);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    f[a][i] = ld(pop + pidx<M>((9 + 5 * a + OPP5[i]), nb.at(-CX5[i], -CY5[i])), kp, false);
+                    f[a][i] = ld<NT>(pop + pidx<M>((9 + 5 * a + OPP5[i]), nb.at(-CX5[i], -CY5[i])), kp, false);
             return;
         }
         // nodes next to a wall: every link resolved with selects (no load in a
@@ -228,7 +249,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                     }
                 }
             }
-            h[i] = ld(pop + pidx<M>(pl, src), kp, true);
+            h[i] = ld<NT>(pop + pidx<M>(pl, src), kp, true);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -238,7 +259,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                 const bool out = wf.out_x(-cx) || wf.out_y(-cy);
                 const int side = wf.out_x(-cx) ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3);
                 const long long src = out ? n : nb.at(-cx, -cy);
-                const T v = ld(pop + pidx<M>(9 + 5 * a + (out ? i : OPP5[i]), src), kp, false);
+                const T v = ld<NT>(pop + pidx<M>(9 + 5 * a + (out ? i : OPP5[i]), src), kp, false);
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 f[a][i] = dir ? -v + T(2) * w5<T>(i) * kp.wallr[side][a] : v;
             }
@@ -248,29 +269,29 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
 // ---- scatter ---------------------------------------------------------------
 // PUSH = false: even step, post-collision value of direction i to own slot
 // opp(i).  PUSH = true: odd step, to slot i of x + c_i, or by the wall rules.
-template <class S, int M, bool PUSH, class T>
+template <class S, int M, bool PUSH, bool NT = false, class T>
 __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ pop, int x, int y,
                                         const T h[9], const T f[M][5], uint32_t salt) {
     const int nx = kp.nx;
     const long long n = (long long)y * nx + x;
     if constexpr (!PUSH) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st(pop, pidx<M>(OPP9[i], n), h[i], kp, true, salt);
+        for (int i = 0; i < 9; ++i) st<NT>(pop, pidx<M>(OPP9[i], n), h[i], kp, true, salt);
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st(pop, pidx<M>((9 + 5 * a + OPP5[i]), n), f[a][i], kp, false, salt);
+            for (int i = 0; i < 5; ++i) st<NT>(pop, pidx<M>((9 + 5 * a + OPP5[i]), n), f[a][i], kp, false, salt);
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             Nbr nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st(pop, pidx<M>(i, nb.at(CX9[i], CY9[i])), h[i], kp, true, salt);
+            for (int i = 0; i < 9; ++i) st<NT>(pop, pidx<M>(i, nb.at(CX9[i], CY9[i])), h[i], kp, true, salt);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    st(pop, pidx<M>((9 + 5 * a + i), nb.at(CX5[i], CY5[i])), f[a][i], kp, false, salt);
+                    st<NT>(pop, pidx<M>((9 + 5 * a + i), nb.at(CX5[i], CY5[i])), f[a][i], kp, false, salt);
             return;
         }
         const WallFlags wf(kp, x, y);
@@ -294,7 +315,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     }
                 }
             }
-            st(pop, pidx<M>(pl, dst), h[i], kp, true, salt);
+            st<NT>(pop, pidx<M>(pl, dst), h[i], kp, true, salt);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -306,7 +327,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 const T v = dir ? -f[a][i] + T(2) * w5<T>(i) * kp.wallr[side][a] : f[a][i];
                 const long long dst = out ? n : nb.at(cx, cy);
-                st(pop, pidx<M>(9 + 5 * a + (out ? OPP5[i] : i), dst), v, kp, false, salt);
+                st<NT>(pop, pidx<M>(9 + 5 * a + (out ? OPP5[i] : i), dst), v, kp, false, salt);
             }
     }
 }
@@ -552,6 +573,7 @@ static hipError_t dispatch(const lb_params& p, Fn&& fn) {
         }
         return hipErrorInvalidValue;
     };
+    if (p.model != LB_MODEL_LINEAR && p.model != LB_MODEL_CHEMOTAXIS) return hipErrorInvalidValue;
     switch (p.storage) {
         case LB_STORE_F64: return by_m(double{});
         case LB_STORE_F32: return by_m(float{});

@@ -45,6 +45,7 @@ struct Layout {
     size_t nsrc;          // S_old planes
     size_t pop_off, sold_off, snap_off, stage_off, part_off, res_off, total;
     size_t pop2_off, sold2_off;  // second population / source arrays (two-step launches only)
+    size_t naux, aux_off;        // no-fluid model: prescribed u (2 planes) and previous phi - phi_ref (m planes)
 };
 
 constexpr int kRedBlocks = 1024;   // blocks of the first reduction pass (upper bound)
@@ -52,6 +53,7 @@ constexpr int kRedWidth = 16;      // doubles per partial record
 
 struct Launch {
     int tile_x, tile_y;
+    int nt;  // step kernels use non-temporal population accesses (small working sets)
 };
 
 // launchers (lb_kernels.hip); all return hipError_t of the launch
@@ -65,6 +67,20 @@ hipError_t launch_step2(const lb_params& p, const Layout& L, void* ws, const KPa
                         const KParams<float>& kf, int64_t step, hipStream_t s);
 hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                             const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out);
+int reduce_blocks(size_t N);
+hipError_t launch_reduce_final(int Q, const double* part, int nblocks, double* out, int mode, hipStream_t s);
+// no-fluid model (lb_cde.hip)
+hipError_t launch_cde_init(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                           const KParams<float>& kf, hipStream_t s);
+hipError_t launch_cde_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                           const KParams<float>& kf, bool odd, Launch lc, hipStream_t s);
+hipError_t launch_cde_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                              const KParams<float>& kf, bool odd, double* phi, double* u, double* pr, hipStream_t s);
+hipError_t launch_cde_export(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                             const KParams<float>& kf, bool odd, int plane_begin, int plane_count, double* out,
+                             hipStream_t s);
+hipError_t launch_cde_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                             const KParams<float>& kf, bool odd, int mode, hipStream_t s);
 hipError_t launch_wall_flux(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                             const KParams<float>& kf, bool odd, int side, double* out, hipStream_t s);
 hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,

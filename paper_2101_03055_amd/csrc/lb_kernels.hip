@@ -30,7 +30,7 @@
 namespace lbk {
 
 // ---- kernels ------------------------------------------------------------------
-template <class S, int M, int MODEL, int COLL, bool ODD>
+template <class S, int M, int MODEL, int COLL, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* __restrict__ pop,
                                               typename St<S>::T* __restrict__ sold, int tile_x, int tile_y,
                                               int tiles_x, uint32_t salt) {
@@ -42,20 +42,36 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
     if (x >= kp.nx || y >= kp.ny) return;
     const long long n = (long long)y * kp.nx + x;
 
+    const long long N = (long long)kp.nx * kp.ny;
     T h[9], f[M][5], Sold[M], Snew[M];
-    gather<S, M, ODD>(kp, pop, x, y, h, f);
+    gather<S, M, ODD, NT>(kp, pop, x, y, h, f);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         Sold[a] = T(0);
-        if (kp.src_mask >> a & 1) Sold[a] = sold[(long long)(k++) * kp.nx * kp.ny + n];
+        if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
     collide<T, M, MODEL, COLL>(kp, h, f, Sold, Snew);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)
-        if (kp.src_mask >> a & 1) sold[(long long)(k++) * kp.nx * kp.ny + n] = Snew[a];
-    scatter<S, M, ODD>(kp, pop, x, y, h, f, salt);
+        if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold[(long long)(k++) * N + n]);
+    scatter<S, M, ODD, NT>(kp, pop, x, y, h, f, salt);
+}
+
+// the step kernel for a collision kind, parity and cache hint
+template <class S, int M, int MODEL>
+static const void* step_kernel(bool mrt, bool odd, bool nt) {
+    const void* const fns[8] = {
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false, true>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, true>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false, true>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, true>)};
+    return fns[(mrt ? 4 : 0) + (odd ? 2 : 0) + (nt ? 1 : 0)];
 }
 
 // ---- two steps per launch (temporal blocking through LDS) -----------------
@@ -523,23 +539,12 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
         using T = typename St<S>::T;
         S* pop = (S*)at(ws, L.pop_off);
         T* sold = (T*)at(ws, L.sold_off);
-        const auto& kp = kpar<S>(kd, kf);
-        if (p.collision == LB_COLL_MRT) {
-            if (odd)
-                hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_MRT, true>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x, salt);
-            else
-                hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_MRT, false>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x, salt);
-        } else {
-            if (odd)
-                hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_BGK, true>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x, salt);
-            else
-                hipLaunchKernelGGL((k_step<S, M, MODEL, LB_COLL_BGK, false>), grid, block, 0, s, kp, pop, sold,
-                                   lc.tile_x, lc.tile_y, tiles_x, salt);
-        }
-        return hipGetLastError();
+        KParams<T> kp = kpar<S>(kd, kf);
+        int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
+        uint32_t sl = salt;
+        void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &sl};
+        const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, lc.nt != 0);
+        return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
 }
 
@@ -565,10 +570,8 @@ hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const
         uint32_t salt = 0;
         void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &salt};
         const bool mrt = p.collision == LB_COLL_MRT;
-        void* fe = mrt ? reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false>)
-                       : reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false>);
-        void* fo = mrt ? reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true>)
-                       : reinterpret_cast<void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true>);
+        void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, lc.nt != 0));
+        void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, lc.nt != 0));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
             hipKernelNodeParams np{};
@@ -681,6 +684,17 @@ hipError_t launch_copy_sold(const lb_params& ps, const Layout& Ls, void* wss, co
         hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, s, (const float*)src, (double*)dst, n);
     else
         hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, s, (const float*)src, (float*)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(int Q, const double* part, int nblocks, double* out, int mode, hipStream_t s) {
+    switch (Q) {
+        case 3: hipLaunchKernelGGL((k_reduce_final<3>), dim3(1), dim3(256), 0, s, part, nblocks, out, mode); break;
+        case 4: hipLaunchKernelGGL((k_reduce_final<4>), dim3(1), dim3(256), 0, s, part, nblocks, out, mode); break;
+        case 5: hipLaunchKernelGGL((k_reduce_final<5>), dim3(1), dim3(256), 0, s, part, nblocks, out, mode); break;
+        case 6: hipLaunchKernelGGL((k_reduce_final<6>), dim3(1), dim3(256), 0, s, part, nblocks, out, mode); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

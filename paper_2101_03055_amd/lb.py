@@ -20,7 +20,7 @@ LIBPATH = os.path.join(HERE, "liblbcdf.so")
 MAXM = 4
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENONFINITE, LB_ESTATE = 0, -1, -2, -3, -4, -5
-MODEL = {"linear": 0, "chemotaxis": 1}
+MODEL = {"linear": 0, "chemotaxis": 1, "cde": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 COLLISION = {"bgk": 0, "mrt": 1}
 RKIND = {"step": 0, "smooth": 1}

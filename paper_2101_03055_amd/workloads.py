@@ -229,6 +229,33 @@ def random_case(nx, ny, m=2, seed=0, fluid_bc=None, scalar_bc=None, model="linea
 
 
 # ---------------------------------------------------------------------------
+# Case 1 (no fluid): species carried by a prescribed velocity field
+# ---------------------------------------------------------------------------
+def cde_case(nx, ny, m=2, seed=0, walls=False, source=False, U=0.05):
+    """Cross-diffusing species in a prescribed, divergence-free cellular flow
+    u = U (sin(2 pi x/nx) cos(2 pi y/ny) ny/nx, -cos(2 pi x/nx) sin(2 pi y/ny))
+    (the stream function U ny/(2 pi) sin sin, sampled at cell centres).
+    walls: Dirichlet at x = 0 / nx, no flux at y = 0 / ny (the normal velocity
+    vanishes on the y walls); otherwise periodic."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    D = np.diag(rng.uniform(0.03, 0.12, size=m))
+    D += 0.2 * np.min(np.diag(D)) * rng.uniform(-1, 1, size=(m, m)) * (1 - np.eye(m))
+    wl = _base(nx, ny, m, 0.8, D, model="cde")
+    if walls:
+        wl["fluid_bc"] = ["noslip", "noslip", "noslip", "noslip"]
+        wl["scalar_bc"] = [["dirichlet"] * m, ["dirichlet"] * m, ["noflux"] * m, ["noflux"] * m]
+        wl["wall"] = rng.uniform(0.5, 1.5, size=(4, m)).tolist()
+    if source:
+        wl["K"] = (-rng.uniform(0.0, 2e-3, size=(m, m))).tolist()
+    X, Y = cell_centres(nx, ny)
+    kx, ky = 2 * np.pi * X / nx, 2 * np.pi * Y / ny
+    u0 = U * np.stack([np.sin(kx) * np.cos(ky) * ny / nx, -np.cos(kx) * np.sin(ky)])
+    phi0 = 1.0 + 0.05 * rng.standard_normal(size=(m, ny, nx))
+    wl["name"] = f"cde_{nx}x{ny}_s{seed}"
+    return wl, phi0, u0, None
+
+
+# ---------------------------------------------------------------------------
 # Surrogate data: one seed per cavity, the sweep's parameter law
 # ---------------------------------------------------------------------------
 def sweep_case(seed, L=128):

@@ -96,3 +96,28 @@ def test_init_rejects_before_touching_the_device():
 
 def test_free_null_is_ok():
     assert lb.lib().lb_free(None) == lb.LB_OK
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p: setattr(p, "storage", lb.STORAGE["f16"]) or setattr(p, "fp16_scale", 1.0) or setattr(p, "fp16_scale_h", 1.0),
+    lambda p: setattr(p, "collision", 1),
+    lambda p: setattr(p, "fused_steps", 2),
+    lambda p: p.F0.__setitem__(1, 1e-5),
+    lambda p: p.Fphi[0].__setitem__(1, 1e-5),
+])
+def test_no_fluid_model_validation(mutate):
+    wl, *_ = W.cde_case(16, 12)
+    p = lb.params_from_workload(wl)
+    assert lb.lb_workspace_bytes(p) > 0
+    mutate(p)
+    with pytest.raises(lb.LBError) as ei:
+        lb.lb_workspace_bytes(p)
+    assert ei.value.status == lb.LB_EINVAL
+
+
+def test_no_fluid_model_needs_no_fluid_planes():
+    wl, *_ = W.cde_case(64, 64)
+    b_cde = lb.lb_workspace_bytes(lb.params_from_workload(wl))
+    wl["model"] = "linear"
+    b_lin = lb.lb_workspace_bytes(lb.params_from_workload(wl))
+    assert b_cde < b_lin
