@@ -116,3 +116,21 @@ def test_ddc_cavity_aspect_ratio_and_cross_diffusion(A, sd):
     assert st == lb.LB_OK, (steps, res)
     assert hot[0] == pytest.approx(nu, rel=1e-2)
     assert hot[1] == pytest.approx(sh, rel=1e-2)
+
+
+def test_grid_convergence_towards_paper_table1():
+    """Table 1's grid study at Ra = 1e5, A = 2 (250-350 nodes across: Nu 2.913-2.917,
+    Sh 4.689-4.694): at 96 and 160 nodes across the GPU solver is within 0.5 % and
+    the finer grid is not further away."""
+    nu_ref, sh_ref = 2.9151, 4.6914
+    errs = []
+    for L in (96, 160):
+        wl, phi0, u0, p0 = W.ddc(L, Ra=1e5, Pr=1.0, Le=2.0, Nc=-2.0, Sr=0.1, Df=0.1, A=2.0, u_lat=0.1)
+        s = lb.Solver(wl, phi0, u0, p0)
+        steps, res, st = s.solve_steady(tol=1e-9, check_every=2000, max_steps=4_000_000)
+        assert st == lb.LB_OK, (L, steps, res)
+        nu, sh = lb.lb_wall_flux(s.handle, 0, 2)
+        print(f"L {L}: Nu {nu:.5f} Sh {sh:.5f}", flush=True)
+        errs.append((abs(nu / nu_ref - 1), abs(sh / sh_ref - 1)))
+    assert max(max(e) for e in errs) < 5e-3
+    assert errs[1][0] <= errs[0][0] + 2e-4 and errs[1][1] <= errs[0][1] + 2e-4
