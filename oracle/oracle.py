@@ -19,7 +19,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lb_oracle.c")
-LIB = os.path.join(HERE, "liblboracle.so")
+# LB_ORACLE_LIBRARY selects a prebuilt copy (the sanitized build of the
+# sanitizer test); it is then used as is, never rebuilt
+LIB_OVERRIDE = os.environ.get("LB_ORACLE_LIBRARY")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "liblboracle.so")
 MAXM = 4
 
 # codes used by the oracle's record (its own; the GPU library has its own)
@@ -49,6 +52,8 @@ class OrcCfg(C.Structure):
 
 def build(force: bool = False, openmp: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if LIB_OVERRIDE:
+        return LIB
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]

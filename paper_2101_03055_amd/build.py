@@ -27,18 +27,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> list[str]:
+# host-side AddressSanitizer / UndefinedBehaviorSanitizer (device code is never
+# instrumented): each flag reaches only the host compilation
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, jobs: int = 4, sanitize: bool = False, out_dir: str | None = None) -> list[str]:
+    """Compile every library.  sanitize=True builds a host-sanitized copy into
+    out_dir (for the CPU-only sanitizer test) and leaves the product build alone."""
     out = []
     for lib, srcs in LIBS.items():
         objs = []
         procs = []
         for src in srcs:
-            obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
+            obj = os.path.join(CSRC, "_build_san" if sanitize else "_build", src.replace(".hip", ".o"))
             os.makedirs(os.path.dirname(obj), exist_ok=True)
             cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-c",
                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                    "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
                    f"-I{os.path.join(ROOT, 'include')}", os.path.join(CSRC, src), "-o", obj]
+            if sanitize:
+                cmd[1:1] = SANITIZE_HOST
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append(subprocess.Popen(cmd))
@@ -46,8 +56,10 @@ def build(verbose: bool = False, jobs: int = 4) -> list[str]:
         for p in procs:
             if p.wait() != 0:
                 raise RuntimeError(f"hipcc failed building {lib}")
-        target = os.path.join(HERE, lib)
+        target = os.path.join(out_dir if sanitize else HERE, lib)
         cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", target + ".tmp"]
+        if sanitize:
+            cmd[1:1] = SANITIZE_HOST
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "liblbcdf.so")
+# LBCDF_LIBRARY selects another build of the same library (the host-sanitized
+# copy used by the sanitizer test); by default the in-tree build is loaded
+LIBPATH = os.environ.get("LBCDF_LIBRARY") or os.path.join(HERE, "liblbcdf.so")
 MAXM = 4
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ENONFINITE, LB_ESTATE = 0, -1, -2, -3, -4, -5

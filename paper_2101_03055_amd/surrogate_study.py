@@ -134,7 +134,11 @@ def predict(net, params, smooth=True):
 
 
 def solve_path(cases, init_fields, tol32=1e-5, tol=1e-8, max_steps=1_500_000, label="", log=print):
-    """Batched FP32 phase then batched FP64 finish; init_fields None = from rest."""
+    """Batched FP32 phase then batched FP64 finish; init_fields None = from rest.
+    A warm-started cavity that diverges in the FP32 phase falls back to a cold
+    start: its FP64 phase begins from rest instead of from the copied state
+    (the LB iteration stays the judge of the prediction)."""
+    cold_cases = cases
     if init_fields is not None:
         cases = [(wl, np.stack([f[2], f[3]]), np.stack([f[0], f[1]]) * U_LAT, None)
                  for (wl, _, _, _), f in zip(cases, init_fields)]
@@ -142,14 +146,20 @@ def solve_path(cases, init_fields, tol32=1e-5, tol=1e-8, max_steps=1_500_000, la
     t0 = time.perf_counter()
     b32 = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
     s32, st32, _ = run_batch(b32, tol32, 1000, max_steps, window=50000, label=label + " fp32", log=log)
-    b64 = lb.Batch(cases, storage="f64")
+    fallback = [i for i in range(len(cases)) if init_fields is not None and st32[i] == lb.LBB_DIVERGED]
+    if fallback:
+        log(f"  {label}: {len(fallback)} warm start(s) diverged; restarting them from rest")
+    b64 = lb.Batch([cold_cases[i] if i in fallback else cases[i] for i in range(len(cases))], storage="f64")
     for i in range(len(cases)):
-        lb.lbb_copy_cavity(b64.handle, i, b32.handle, i)
+        if i not in fallback:
+            lb.lbb_copy_cavity(b64.handle, i, b32.handle, i)
     s64, st64, _ = run_batch(b64, tol, 1000, max_steps, window=50000, label=label + " fp64", log=log)
     _sync()
     secs = time.perf_counter() - t0
     fields = [fields_of(b64, i) for i in range(len(cases))]
-    return {"steps_fp32": s32.tolist(), "steps_total": s64.tolist(), "status": st64.tolist(), "seconds": secs}, fields
+    steps = [int(s64[i]) + (int(s32[i]) if i in fallback else 0) for i in range(len(cases))]
+    return {"steps_fp32": s32.tolist(), "steps_total": steps, "status": st64.tolist(), "seconds": secs,
+            "fallback": fallback}, fields
 
 
 def plain_solve(case, tol=1e-8, max_steps=3_000_000):

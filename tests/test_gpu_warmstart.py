@@ -67,3 +67,21 @@ def test_prepared_prediction_has_no_staggered_velocity(predictions):
     sx = ((-1.0) ** np.arange(128))[None, :]
     for pf in pred:
         assert abs(np.mean(pf[1] * sy)) < 1e-6 and abs(np.mean(pf[0] * sx)) < 1e-6
+
+
+def test_diverging_warm_start_falls_back_to_cold(predictions):
+    """A prediction that makes the LB iteration diverge (a velocity far beyond
+    the lattice's range) is caught by the residual kernel and that cavity is
+    solved from rest instead; the other cavity keeps its warm start."""
+    pds, pred = predictions
+    cases = [W.ddc_case(pd) for pd in pds[:2]]
+    bad = np.array(pred[:2])
+    bad[1, 0] += 50.0  # u / u_lat: 5 lattice units
+    out, fields = SS.solve_path(cases, bad, max_steps=1_500_000, log=print)
+    assert out["fallback"] == [1]
+    assert out["status"] == [lb.LBB_CONVERGED, lb.LBB_CONVERGED]
+    cold = lb.Solver(*cases[1])
+    cold.solve_steady(1e-8, 1000, 3_000_000)
+    assert rel(fields[1], fields(cold)) < 1e-5
+
+
