@@ -142,6 +142,82 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const 
             }
 }
 
+// Same convolution with a workgroup tile of 128 pixels (one image row of 128
+// or half a longer one) x 64 output channels: each wavefront computes 32
+// pixels x 64 channels, so every K step issues 8 MFMAs per 6 LDS operand reads
+// (4 per 4 in k_conv).  Needs W % 128 == 0.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
+                                                 const float* __restrict__ bias, const float* __restrict__ Zprev,
+                                                 float* __restrict__ Zout, bf16* __restrict__ Yout, int H, int W,
+                                                 int Cin, int Cout, int act) {
+    __shared__ __attribute__((aligned(16))) bf16 As[128 * LDSK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_per_row = W >> 7;
+    const int img_row = blockIdx.x / tiles_per_row;  // b * H + y
+    const int x0 = (blockIdx.x % tiles_per_row) << 7;
+    const int y = img_row % H;
+    const int n0 = blockIdx.y << 6;
+    const int sj = tid >> 2, sq = tid & 3;  // rows sj and sj + 64 of A, row sj of B; 8 channels each
+    const int wr = wave << 5;
+    floatx4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int yy = y + dy;
+        const bool rowin = (yy >= 0) & (yy < H);
+        const int xa = x0 + sj + dx, xb = x0 + sj + 64 + dx;
+        const bool ina = rowin & (xa >= 0) & (xa < W), inb = rowin & (xb >= 0) & (xb < W);
+        const long long srca = ((long long)(img_row + dy) * W + xa) * Cin;
+        const long long srcb = ((long long)(img_row + dy) * W + xb) * Cin;
+        const long long wsrc = ((long long)(n0 + sj) * 9 + tap) * Cin;
+        for (int c0 = 0; c0 < Cin; c0 += 32) {
+            uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = make_uint4(0u, 0u, 0u, 0u);
+            if (ina) va = *reinterpret_cast<const uint4*>(X + srca + c0 + 8 * sq);
+            if (inb) vb = *reinterpret_cast<const uint4*>(X + srcb + c0 + 8 * sq);
+            *reinterpret_cast<uint4*>(&As[sj * LDSK + 8 * sq]) = va;
+            *reinterpret_cast<uint4*>(&As[(sj + 64) * LDSK + 8 * sq]) = vb;
+            *reinterpret_cast<uint4*>(&Bs[sj * LDSK + 8 * sq]) =
+                *reinterpret_cast<const uint4*>(Wk + wsrc + c0 + 8 * sq);
+            __syncthreads();
+            const int r = lane & 15, kq = (lane >> 4) * 8;
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSK + kq]);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSK + kq]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[(16 * j + r) * LDSK + kq]);
+                acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][j], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    }
+    const long long pbase = (long long)img_row * W + x0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = wr + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + 16 * j + (lane & 15);
+                const long long o = (pbase + m) * Cout + n;
+                const float v = acc[i][j][e];
+                if constexpr (MODE == 0) {
+                    const float z = v + bias[n];
+                    Zout[o] = z;
+                    Yout[o] = bf16(act ? silu(z) : z);
+                } else {
+                    Yout[o] = bf16(v * silu_grad(Zprev[o]));
+                }
+            }
+}
+
 // ---- weight gradient: split-K implicit GEMM -------------------------------
 // part[s][tap][co][ci] = sum over the 64-pixel chunks of split s of dZ[p][co] x[p + off(tap)][ci].
 // Both operands are channels-last, the reduction runs over pixels, so tiles are
@@ -532,11 +608,16 @@ lb_status forward(sg_handle* h, const float* d_params, int nb) {
     SGCHK(hipGetLastError());
     const bf16* x = ptr<bf16>(h, h->pl.x0_off);
     for (int l = 0; l < kLayers; ++l) {
-        const dim3 grid((unsigned)(P / 64), (unsigned)(kCoutPad[l] / 64));
-        hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, h->s, x, ptr<bf16>(h, h->pl.wk_off[l]),
-                           ptr<float>(h, h->pl.w_off) + h->pl.boff[l], (const float*)nullptr,
-                           ptr<float>(h, h->pl.z_off[l]), ptr<bf16>(h, h->pl.y_off[l]), H, W, kCinPad[l],
-                           kCoutPad[l], l + 1 < kLayers ? 1 : 0);
+        if (W % 128 == 0)
+            hipLaunchKernelGGL(k_conv128<0>, dim3((unsigned)(P / 128), (unsigned)(kCoutPad[l] / 64)), dim3(256), 0,
+                               h->s, x, ptr<bf16>(h, h->pl.wk_off[l]), ptr<float>(h, h->pl.w_off) + h->pl.boff[l],
+                               (const float*)nullptr, ptr<float>(h, h->pl.z_off[l]), ptr<bf16>(h, h->pl.y_off[l]), H,
+                               W, kCinPad[l], kCoutPad[l], l + 1 < kLayers ? 1 : 0);
+        else
+            hipLaunchKernelGGL(k_conv<0>, dim3((unsigned)(P / 64), (unsigned)(kCoutPad[l] / 64)), dim3(256), 0, h->s,
+                               x, ptr<bf16>(h, h->pl.wk_off[l]), ptr<float>(h, h->pl.w_off) + h->pl.boff[l],
+                               (const float*)nullptr, ptr<float>(h, h->pl.z_off[l]), ptr<bf16>(h, h->pl.y_off[l]), H,
+                               W, kCinPad[l], kCoutPad[l], l + 1 < kLayers ? 1 : 0);
         SGCHK(hipGetLastError());
         x = ptr<bf16>(h, h->pl.y_off[l]);
     }
@@ -579,10 +660,14 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
         SGCHK(hipGetLastError());
         if (l > 0) {
             bf16* dzn = ptr<bf16>(h, h->pl.dz_off[(L - l + 1) & 1]);
-            const dim3 grid((unsigned)(P / 64), (unsigned)(Ci / 64));
-            hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, h->s, dz, ptr<bf16>(h, h->pl.wt_off[l]),
-                               (const float*)nullptr, ptr<float>(h, h->pl.z_off[l - 1]), (float*)nullptr, dzn, H, W,
-                               Co, Ci, 0);
+            if (W % 128 == 0)
+                hipLaunchKernelGGL(k_conv128<1>, dim3((unsigned)(P / 128), (unsigned)(Ci / 64)), dim3(256), 0, h->s,
+                                   dz, ptr<bf16>(h, h->pl.wt_off[l]), (const float*)nullptr,
+                                   ptr<float>(h, h->pl.z_off[l - 1]), (float*)nullptr, dzn, H, W, Co, Ci, 0);
+            else
+                hipLaunchKernelGGL(k_conv<1>, dim3((unsigned)(P / 64), (unsigned)(Ci / 64)), dim3(256), 0, h->s, dz,
+                                   ptr<bf16>(h, h->pl.wt_off[l]), (const float*)nullptr,
+                                   ptr<float>(h, h->pl.z_off[l - 1]), (float*)nullptr, dzn, H, W, Co, Ci, 0);
             SGCHK(hipGetLastError());
             dz = dzn;
         }

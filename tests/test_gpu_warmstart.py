@@ -77,11 +77,11 @@ def test_diverging_warm_start_falls_back_to_cold(predictions):
     cases = [W.ddc_case(pd) for pd in pds[:2]]
     bad = np.array(pred[:2])
     bad[1, 0] += 50.0  # u / u_lat: 5 lattice units
-    out, fields = SS.solve_path(cases, bad, max_steps=1_500_000, log=print)
+    out, flds = SS.solve_path(cases, bad, max_steps=1_500_000, log=print)
     assert out["fallback"] == [1]
     assert out["status"] == [lb.LBB_CONVERGED, lb.LBB_CONVERGED]
     cold = lb.Solver(*cases[1])
     cold.solve_steady(1e-8, 1000, 3_000_000)
-    assert rel(fields[1], fields(cold)) < 1e-5
+    assert rel(flds[1], fields(cold)) < 1e-5
 
 
