@@ -324,9 +324,14 @@ constexpr int kGraphSteps = 64;  // launches per replayed step graph (even)
 // slower on grids far beyond it
 constexpr size_t kNtMaxBytes = size_t(64) << 20;
 
+// non-temporal hint bits (Launch::nt): even steps always (own-slot accesses,
+// aligned runs), odd steps only for small states (their shifted accesses share
+// cache lines between neighbouring wavefronts)
+int hint_bits(size_t state_bytes) { return state_bytes <= kNtMaxBytes ? 3 : 1; }
+
 int small_state(const lb_params& p) {
     const size_t q = (p.model == LB_MODEL_CDE ? 0 : 9) + 5 * (size_t)p.m;
-    return q * (size_t)p.nx * (size_t)p.ny * elem_bytes(p.storage) <= kNtMaxBytes ? 1 : 0;
+    return hint_bits(q * (size_t)p.nx * (size_t)p.ny * elem_bytes(p.storage));
 }
 
 Launch default_launch(const lb_params& p) {
@@ -933,7 +938,7 @@ lb_status lbb_init(const lb_params* params, int32_t count, void* dev_workspace, 
     b->t = 0;
     size_t state = 0;
     for (int c = 0; c < count; ++c) state += b->L[c].npop * b->L[c].plane * b->L[c].elem;
-    b->lc = Launch{64, 4, state <= kNtMaxBytes ? 1 : 0};
+    b->lc = Launch{64, 4, hint_bits(state)};
     char* w = static_cast<char*>(b->ws);
     for (int c = 0; c < count; ++c) {
         fill_kparams(b->p[c], b->L[c], b->kd[c]);

@@ -157,7 +157,7 @@ hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, cons
         int nt = ntiles, tx = lc.tile_x, ty = lc.tile_y;
         uint32_t sl = salt;
         void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &sl};
-        const void* fn = bstep_kernel<S, M, MODEL>(p0.collision == LB_COLL_MRT, odd, lc.nt != 0);
+        const void* fn = bstep_kernel<S, M, MODEL>(p0.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
 }
@@ -181,8 +181,8 @@ hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams,
         uint32_t salt = 0;
         void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &salt};
         const bool mrt = p0.collision == LB_COLL_MRT;
-        void* fe = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, false, lc.nt != 0));
-        void* fo = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, true, lc.nt != 0));
+        void* fe = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0));
+        void* fo = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
             hipKernelNodeParams np{};

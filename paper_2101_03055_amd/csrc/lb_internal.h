@@ -53,7 +53,7 @@ constexpr int kRedWidth = 16;      // doubles per partial record
 
 struct Launch {
     int tile_x, tile_y;
-    int nt;  // step kernels use non-temporal population accesses (small working sets)
+    int nt;  // non-temporal population accesses: bit 0 in even steps, bit 1 in odd steps
 };
 
 // launchers (lb_kernels.hip); all return hipError_t of the launch

@@ -543,7 +543,7 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
         int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
         uint32_t sl = salt;
         void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &sl};
-        const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, lc.nt != 0);
+        const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
 }
@@ -570,8 +570,8 @@ hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const
         uint32_t salt = 0;
         void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &salt};
         const bool mrt = p.collision == LB_COLL_MRT;
-        void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, lc.nt != 0));
-        void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, lc.nt != 0));
+        void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0));
+        void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
             hipKernelNodeParams np{};
