@@ -25,7 +25,7 @@ __device__ __forceinline__ long long cidx(int q, long long n) {
 }
 
 // canonical pre-collision scalar populations of node (x, y); PULL as in gather()
-template <class S, int M, bool PULL, class T>
+template <class S, int M, bool PULL, bool NT = false, class T>
 __device__ __forceinline__ void gather_f(const KParams<T>& kp, const S* __restrict__ pop, int x, int y,
                                          T f[M][5]) {
     const long long n = (long long)y * kp.nx + x;
@@ -33,7 +33,7 @@ __device__ __forceinline__ void gather_f(const KParams<T>& kp, const S* __restri
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) f[a][i] = ld(pop + cidx<M>(5 * a + i, n), kp, false);
+            for (int i = 0; i < 5; ++i) f[a][i] = ld<NT>(pop + cidx<M>(5 * a + i, n), kp, false);
     } else {
         Nbr nb(kp, x, y);
         if (__all(no_wall_link(kp, x, y))) {
@@ -41,7 +41,7 @@ __device__ __forceinline__ void gather_f(const KParams<T>& kp, const S* __restri
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    f[a][i] = ld(pop + cidx<M>(5 * a + OPP5[i], nb.at(-CX5[i], -CY5[i])), kp, false);
+                    f[a][i] = ld<NT>(pop + cidx<M>(5 * a + OPP5[i], nb.at(-CX5[i], -CY5[i])), kp, false);
             return;
         }
         const WallFlags wf(kp, x, y);
@@ -53,7 +53,7 @@ __device__ __forceinline__ void gather_f(const KParams<T>& kp, const S* __restri
                 const bool out = wf.out_x(-cx) || wf.out_y(-cy);
                 const int side = wf.out_x(-cx) ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3);
                 const long long src = out ? n : nb.at(-cx, -cy);
-                const T v = ld(pop + cidx<M>(5 * a + (out ? i : OPP5[i]), src), kp, false);
+                const T v = ld<NT>(pop + cidx<M>(5 * a + (out ? i : OPP5[i]), src), kp, false);
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 f[a][i] = dir ? -v + T(2) * w5<T>(i) * kp.wallr[side][a] : v;
             }
@@ -61,21 +61,21 @@ __device__ __forceinline__ void gather_f(const KParams<T>& kp, const S* __restri
 }
 
 // post-collision scalar populations of node (x, y); PUSH as in scatter()
-template <class S, int M, bool PUSH, class T>
+template <class S, int M, bool PUSH, bool NT = false, class T>
 __device__ __forceinline__ void scatter_f(const KParams<T>& kp, S* __restrict__ pop, int x, int y, const T f[M][5]) {
     const long long n = (long long)y * kp.nx + x;
     if constexpr (!PUSH) {
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st(pop, cidx<M>(5 * a + OPP5[i], n), f[a][i], kp, false, 0u);
+            for (int i = 0; i < 5; ++i) st<NT>(pop, cidx<M>(5 * a + OPP5[i], n), f[a][i], kp, false, 0u);
     } else {
         Nbr nb(kp, x, y);
         if (__all(no_wall_link(kp, x, y))) {
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
-                for (int i = 0; i < 5; ++i) st(pop, cidx<M>(5 * a + i, nb.at(CX5[i], CY5[i])), f[a][i], kp, false, 0u);
+                for (int i = 0; i < 5; ++i) st<NT>(pop, cidx<M>(5 * a + i, nb.at(CX5[i], CY5[i])), f[a][i], kp, false, 0u);
             return;
         }
         const WallFlags wf(kp, x, y);
@@ -89,7 +89,7 @@ __device__ __forceinline__ void scatter_f(const KParams<T>& kp, S* __restrict__ 
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 const T v = dir ? -f[a][i] + T(2) * w5<T>(i) * kp.wallr[side][a] : f[a][i];
                 const long long dst = out ? n : nb.at(cx, cy);
-                st(pop, cidx<M>(5 * a + (out ? OPP5[i] : i), dst), v, kp, false, 0u);
+                st<NT>(pop, cidx<M>(5 * a + (out ? OPP5[i] : i), dst), v, kp, false, 0u);
             }
     }
 }
@@ -161,7 +161,7 @@ __device__ __forceinline__ void collide_cde(const KParams<T>& kp, T f[M][5], con
     }
 }
 
-template <class S, int M, bool ODD>
+template <class S, int M, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_cde_step(KParams<typename St<S>::T> kp, S* __restrict__ pop,
                                                   typename St<S>::T* __restrict__ sold,
                                                   typename St<S>::T* __restrict__ aux, int tile_x, int tile_y,
@@ -174,24 +174,24 @@ __global__ __launch_bounds__(256) void k_cde_step(KParams<typename St<S>::T> kp,
     if (x >= kp.nx || y >= kp.ny) return;
     const long long N = (long long)kp.nx * kp.ny, n = (long long)y * kp.nx + x;
     T f[M][5], u[2], prevd[M], Sold[M], phid[M], Snew[M];
-    gather_f<S, M, ODD>(kp, pop, x, y, f);
-    u[0] = aux[n];
-    u[1] = aux[N + n];
+    gather_f<S, M, ODD, NT>(kp, pop, x, y, f);
+    u[0] = load_raw<NT>(&aux[n]);
+    u[1] = load_raw<NT>(&aux[N + n]);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        prevd[a] = aux[(2 + a) * N + n];
+        prevd[a] = load_raw<NT>(&aux[(2 + a) * N + n]);
         Sold[a] = T(0);
-        if (kp.src_mask >> a & 1) Sold[a] = sold[(long long)(k++) * N + n];
+        if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
     collide_cde<T, M>(kp, f, u, prevd, Sold, phid, Snew);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        aux[(2 + a) * N + n] = phid[a];
-        if (kp.src_mask >> a & 1) sold[(long long)(k++) * N + n] = Snew[a];
+        store_raw<NT>(phid[a], &aux[(2 + a) * N + n]);
+        if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold[(long long)(k++) * N + n]);
     }
-    scatter_f<S, M, ODD>(kp, pop, x, y, f);
+    scatter_f<S, M, ODD, NT>(kp, pop, x, y, f);
 }
 
 // equilibrium initialisation from the staged FP64 fields phi0 [M][N], u0 [2][N]
@@ -358,12 +358,16 @@ hipError_t launch_cde_step(const lb_params& p, const Layout& L, void* ws, const 
         S* pop = (S*)at(ws, L.pop_off);
         T* sold = (T*)at(ws, L.sold_off);
         T* aux = (T*)at(ws, L.aux_off);
-        if (odd)
-            hipLaunchKernelGGL((k_cde_step<S, M, true>), grid, block, 0, s, kpar<S>(kd, kf), pop, sold, aux, lc.tile_x,
-                               lc.tile_y, tiles_x);
-        else
-            hipLaunchKernelGGL((k_cde_step<S, M, false>), grid, block, 0, s, kpar<S>(kd, kf), pop, sold, aux,
-                               lc.tile_x, lc.tile_y, tiles_x);
+        const bool nt = (lc.nt >> (odd ? 1 : 0) & 1) != 0;
+        const void* const fns[4] = {reinterpret_cast<const void*>(&k_cde_step<S, M, false, false>),
+                                    reinterpret_cast<const void*>(&k_cde_step<S, M, false, true>),
+                                    reinterpret_cast<const void*>(&k_cde_step<S, M, true, false>),
+                                    reinterpret_cast<const void*>(&k_cde_step<S, M, true, true>)};
+        KParams<T> kp = kpar<S>(kd, kf);
+        int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
+        void* args[] = {&kp, &pop, &sold, &aux, &tx, &ty, &tsx};
+        hipError_t e = hipLaunchKernel(fns[(odd ? 2 : 0) + (nt ? 1 : 0)], grid, block, args, 0, s);
+        if (e != hipSuccess) return e;
         return hipGetLastError();
     });
 }

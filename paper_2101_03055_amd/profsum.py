@@ -22,7 +22,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ["csrc/lb_device.h", "csrc/lb_kernels.hip", "csrc/lb_internal.h"]
+KERNEL_SOURCES = ["csrc/lb_device.h", "csrc/lb_kernels.hip", "csrc/lb_internal.h", "csrc/lb_batch.hip", "csrc/lb_cde.hip"]
 
 
 def source_hash(files=KERNEL_SOURCES) -> str:
