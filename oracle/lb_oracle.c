@@ -19,10 +19,19 @@
  *
  * Lattice units throughout: dx = dt = 1, cs^2 = 1/3 (D2Q5 and D2Q9 tables,
  * Sec. 2).  Readings of the paper (all listed in the design notes):
- *   - lambda = I and vartheta = 0 in Eq. feq-phi (Sec. 3 fixes lambda = I;
- *     vartheta = 0 is the linear equilibrium Case 2 permits, and the only one
- *     D2Q5 can carry).
- *   - varphi = 0 in Eqs. force and sum-p (Sec. 3).
+ *   - vartheta = 0 in Eq. feq-phi (the linear equilibrium Case 2 permits, and
+ *     the only one D2Q5 can carry).  lambda is a parameter (Sec. 3 uses
+ *     lambda = I).  On D2Q5 the lambda part of Eq. feq-phi is rescaled so that
+ *     its second moment is (lambda phi - phi) cs^2 I as the moment condition
+ *     of Sec. 2.1 requires: the printed 1/(2 cs^4) assumes a lattice whose
+ *     weights satisfy sum_i W_i c_ix^2 c_iy^2 = cs^4, which D2Q5 does not
+ *     (there it gives half the required moment).
+ *   - varphi is a parameter of Eq. force (Sec. 3 uses varphi = 0).  The
+ *     pressure takes the first form of the appendix-A result,
+ *     p = cs^2/(1 - W_0) [sum_{i>0} h_i - W_0 u.u/(2 cs^2) + dt (1/omega - 1/2) F_0],
+ *     F_0 being the rest component of Eq. force (its second, expanded form
+ *     and Eq. sum-p drop the factor W_0 and disagree in sign).  varphi != 0
+ *     needs BGK (the correction uses the single fluid rate).
  *   - gamma = 0 and the first-order backward difference for d/dt S (text
  *     after Eq. source); S_old at t = 0 is S(phi0).
  *   - Initial populations: scalar equilibrium of (phi0, u0); fluid equilibrium
@@ -75,6 +84,8 @@ typedef struct orc_cfg {
     double K[ORC_MAXM * ORC_MAXM];      /* linear source S = K phi (model 0) */
     double chi, beta, cstar, eps;       /* chemotaxis: D12 -= chi r(c) n, S_c = -beta r(c) n */
     double wall[4 * ORC_MAXM];          /* Dirichlet values [side][alpha] */
+    double lam[ORC_MAXM * ORC_MAXM];    /* lambda of Eq. feq-phi, row-major (identity in Sec. 3) */
+    double varphi;                      /* varphi of Eq. force (0 in Sec. 3) */
 } orc_cfg;
 
 /* ---- lattices (Sec. 2, D2Q5 and D2Q9 tables) ---------------------------- */
@@ -218,34 +229,62 @@ static void body_force(const orc_cfg *cfg, const double *phi, double *F) {
     }
 }
 
-/* relaxation matrix from Eq. omega-D with lambda = I:
- * D = (omega^-1 - I/2) cs^2 dt  =>  omega = (D / (cs^2 dt) + I/2)^-1 */
-static int relaxation_matrix(int m, const double *Dm, double *omega) {
-    double A[ORC_MAXM * ORC_MAXM];
+/* relaxation matrix from Eq. omega-D:
+ * D = (omega^-1 - I/2) lambda cs^2 dt  =>  omega = (D lambda^-1 / (cs^2 dt) + I/2)^-1.
+ * lam_left != 0 plants the mistake lambda^-1 D (pin self-test only). */
+static int relaxation_matrix(int m, const double *Dm, const double *lam, int lam_left, double *omega) {
+    double li[ORC_MAXM * ORC_MAXM], A[ORC_MAXM * ORC_MAXM];
+    if (!mat_inverse(m, lam, li)) return 0;
     for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) A[a * m + b] = Dm[a * m + b] / (cs2 * dt) + (a == b ? 0.5 : 0.0);
+        for (int b = 0; b < m; ++b) {
+            double dl = 0.0;
+            for (int c = 0; c < m; ++c)
+                dl += lam_left ? li[a * m + c] * Dm[c * m + b] : Dm[a * m + c] * li[c * m + b];
+            A[a * m + b] = dl / (cs2 * dt) + (a == b ? 0.5 : 0.0);
+        }
     return mat_inverse(m, A, omega);
 }
 
 /* ---- equilibria, force and sources (exported for the single-node pins) -- */
 
-/* Eq. feq-phi on D2Q5 with lambda = I, vartheta = 0:
+/* Factor that gives the lambda part of Eq. feq-phi, W_i X cs^2 I:(c_i c_i - cs^2 I)/(2 cs^4),
+ * the second moment X cs^2 I the moment condition of Sec. 2.1 asks for.  Its
+ * second moment is X/(2 cs^2) sum_i W_i c_ix^2 (|c_i|^2 - 2 cs^2) per unit factor:
+ * cs^2 X on D2Q9, cs^2 X / 2 on D2Q5, so the factor is 2 here. */
+static double lam_norm(void) {
+    double mom = 0.0;
+    for (int i = 0; i < 5; ++i) {
+        double cc = e5[i][0] * e5[i][0] + e5[i][1] * e5[i][1];
+        mom += W5x(i, e5[i][0] * e5[i][0] * (cc - 2.0 * cs2)) / (2.0 * cs2);
+    }
+    return cs2 / mom;
+}
+
+/* Eq. feq-phi on D2Q5 with vartheta = 0:
  * f^eq_{i,a} = W_i [phi_a + c_i.phi_a u / cs^2
- *                   + ((lambda phi - phi)_a cs^2 I + vartheta phi_a uu):(c_i c_i - cs^2 I)/(2 cs^4)] */
-void orc_feq(int m, const double *phi, const double *u, double *feq /*[m][5]*/) {
-    const double vartheta = 0.0; /* lambda = I: (lambda phi - phi) = 0 */
-    for (int a = 0; a < m; ++a)
+ *                   + (k (lambda phi - phi)_a cs^2 I + vartheta phi_a uu):(c_i c_i - cs^2 I)/(2 cs^4)]
+ * with k = lam_norm() (k = 1 plants the mistake of the printed D2Q9 form) */
+static void feq_node(int m, const double *lam, double k, const double *phi, const double *u,
+                     double *feq /*[m][5]*/) {
+    const double vartheta = 0.0;
+    for (int a = 0; a < m; ++a) {
+        double X = -phi[a];
+        for (int b = 0; b < m; ++b) X += lam[a * m + b] * phi[b];
         for (int i = 0; i < 5; ++i) {
             double cu = e5[i][0] * u[0] + e5[i][1] * u[1];
-            /* Q:(c c - cs2 I) with Q = vartheta phi u u (the lambda part vanishes) */
-            double Q[2][2] = {{vartheta * phi[a] * u[0] * u[0], vartheta * phi[a] * u[0] * u[1]},
-                              {vartheta * phi[a] * u[1] * u[0], vartheta * phi[a] * u[1] * u[1]}};
+            double Q[2][2] = {{k * X * cs2 + vartheta * phi[a] * u[0] * u[0], vartheta * phi[a] * u[0] * u[1]},
+                              {vartheta * phi[a] * u[1] * u[0], k * X * cs2 + vartheta * phi[a] * u[1] * u[1]}};
             double contr = 0.0;
             for (int r = 0; r < 2; ++r)
                 for (int s = 0; s < 2; ++s)
                     contr += Q[r][s] * (e5[i][r] * e5[i][s] - (r == s ? cs2 : 0.0));
             feq[a * 5 + i] = W5x(i, phi[a] + phi[a] * cu / cs2 + contr / (2.0 * cs2 * cs2));
         }
+    }
+}
+
+void orc_feq(int m, const double *lam, const double *phi, const double *u, double *feq /*[m][5]*/) {
+    feq_node(m, lam, lam_norm(), phi, u, feq);
 }
 
 /* Eq. heq with sigma_0 = (W_0 - 1) p / cs^2 + rho0, sigma_i = W_i p / cs^2 */
@@ -261,9 +300,15 @@ void orc_heq(double p, const double *u, double rho0, double *heq /*[9]*/) {
     }
 }
 
-/* Eq. force with varphi = 0: F_i = W_i c_i.F / cs^2 */
-void orc_force_pop(const double *F, double *Fi /*[9]*/) {
-    for (int i = 0; i < 9; ++i) Fi[i] = W9x(i, e9[i][0] * F[0] + e9[i][1] * F[1]) / cs2;
+/* Eq. force: F_i = W_i [c_i.F / cs^2 + varphi (uF + Fu):(c_i c_i - cs^2 I)/(2 cs^4)] */
+void orc_force_pop(const double *F, const double *u, double varphi, double *Fi /*[9]*/) {
+    for (int i = 0; i < 9; ++i) {
+        double T2 = 0.0;
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < 2; ++s)
+                T2 += (u[r] * F[s] + F[r] * u[s]) * (e9[i][r] * e9[i][s] - (r == s ? cs2 : 0.0));
+        Fi[i] = W9x(i, (e9[i][0] * F[0] + e9[i][1] * F[1]) / cs2 + varphi * T2 / (2.0 * cs2 * cs2));
+    }
 }
 
 /* Eq. Gi: G_{i,a} = sum_b (delta_ab - omega_ab / 2) W_i c_i.(u S_b + phi_b F) / cs^2 */
@@ -289,8 +334,8 @@ void orc_source_pop(int m, const double *S, double *Si /*[m][5]*/) {
 }
 
 /* relaxation matrix for a constant D (exported for the pins) */
-int orc_relaxation_matrix(int m, const double *Dm, double *omega) {
-    return relaxation_matrix(m, Dm, omega);
+int orc_relaxation_matrix(int m, const double *Dm, const double *lam, double *omega) {
+    return relaxation_matrix(m, Dm, lam, 0, omega);
 }
 
 /* Lallemand-Luo basis and its inverse (exported for the pins) */
@@ -336,13 +381,18 @@ static void node_moments(const orc_cfg *cfg, const double *f /*[m][5]*/, const d
         for (int i = 0; i < 9; ++i) s += e9[i][d] * h[i];
         mc->u[d] = s + half * mc->F[d];
     }
-    /* Eq. sum-p with varphi = 0 */
+    /* pressure, appendix A: p = cs2/(1 - W_0) [sum_{i>0} h_i - W_0 u.u/(2 cs2)
+     * + dt (1/omega - 1/2) F_0], F_0 the rest component of Eq. force (0 for varphi = 0) */
     double s = 0.0;
     for (int i = 1; i < 9; ++i) s += h[i];
     double uu = mc->u[0] * mc->u[0] + mc->u[1] * mc->u[1];
     double w0term = (cfg->mutation == 6) ? 0.0 : W9x(0, uu) / (2.0 * cs2);
+    double Fi[9];
+    orc_force_pop(mc->F, mc->u, cfg->varphi, Fi);
+    double corr = dt * (cfg->tau_f - 0.5) * Fi[0];
+    if (cfg->mutation == 13) corr = -corr;
     /* cs2 / (1 - W_0) with W_0 = 4/9 */
-    mc->p = cs2 * W9den[0] / (W9den[0] - W9num[0]) * (s - w0term);
+    mc->p = cs2 * W9den[0] / (W9den[0] - W9num[0]) * (s - w0term + corr);
 }
 
 /* ---- collision of one node ----------------------------------------------- */
@@ -360,7 +410,7 @@ static int collide_node(const orc_cfg *cfg, const double Minv[9][9], const doubl
         for (int a = 0; a < m; ++a)
             for (int b = 0; b < m; ++b) A[a * m + b] = Dm[a * m + b] / cs2 + (a == b ? 1.0 : 0.0);
         if (!mat_inverse(m, A, omega)) return 0;
-    } else if (!relaxation_matrix(m, Dm, omega)) {
+    } else if (!relaxation_matrix(m, Dm, cfg->lam, cfg->mutation == 12, omega)) {
         return 0;
     }
     if (cfg->mutation == 2) { /* planted: transposed relaxation matrix */
@@ -376,9 +426,9 @@ static int collide_node(const orc_cfg *cfg, const double Minv[9][9], const doubl
     double feq[ORC_MAXM * 5], heq[9], Fi[9], Gi[ORC_MAXM * 5], Si[ORC_MAXM * 5], Si_old[ORC_MAXM * 5];
     double ueq[2] = {mc.u[0], mc.u[1]};
     if (cfg->mutation == 8) { ueq[0] = -ueq[0]; ueq[1] = -ueq[1]; }
-    orc_feq(m, mc.phi, ueq, feq);
+    feq_node(m, cfg->lam, (cfg->mutation == 11) ? 1.0 : lam_norm(), mc.phi, ueq, feq);
     orc_heq(mc.p, mc.u, cfg->rho0, heq);
-    orc_force_pop(mc.F, Fi);
+    orc_force_pop(mc.F, mc.u, (cfg->mutation == 14) ? 0.0 : cfg->varphi, Fi);
     if (cfg->model == 2) {
         /* Case 1: G_i = (I - omega/2) W_i c_i . u (phi - phi_prev) / (dt cs^2) */
         for (int a = 0; a < m; ++a) {
@@ -464,6 +514,7 @@ int orc_init(const orc_cfg *cfg, const double *phi0, const double *u0, const dou
              double *f, double *h, double *Sold) {
     int nx = cfg->nx, ny = cfg->ny, m = cfg->m;
     size_t N = (size_t)nx * ny;
+    if (cfg->varphi != 0.0 && cfg->collision != 0) return 0; /* the p correction is BGK's */
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t n = nidx(cfg, x, y);
@@ -472,7 +523,7 @@ int orc_init(const orc_cfg *cfg, const double *phi0, const double *u0, const dou
             u[0] = u0[n];
             u[1] = u0[N + n];
             double p = p0 ? p0[n] : 0.0;
-            orc_feq(m, phi, u, feq);
+            feq_node(m, cfg->lam, lam_norm(), phi, u, feq);
             /* fluid: equilibrium at the momentum sum c_i h_i = u0 - (dt/2) F(phi0), so that
              * Eq. sum-u returns the prescribed u0 at t = 0 */
             double F[2], j[2];

@@ -47,6 +47,8 @@ class OrcCfg(C.Structure):
         ("K", C.c_double * (MAXM * MAXM)),
         ("chi", C.c_double), ("beta", C.c_double), ("cstar", C.c_double), ("eps", C.c_double),
         ("wall", C.c_double * (4 * MAXM)),
+        ("lam", C.c_double * (MAXM * MAXM)),
+        ("varphi", C.c_double),
     ]
 
 
@@ -78,17 +80,17 @@ def lib():
         L.orc_init.argtypes = [C.POINTER(OrcCfg), dp, dp, C.c_void_p, dp, dp, dp]
         L.orc_step.argtypes = [C.POINTER(OrcCfg), dp, dp, dp, C.c_int64]
         L.orc_moments.argtypes = [C.POINTER(OrcCfg), dp, dp, dp, dp, dp]
-        L.orc_feq.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_feq.argtypes = [C.c_int, dp, dp, dp, dp]
         L.orc_feq.restype = None
         L.orc_heq.argtypes = [C.c_double, dp, C.c_double, dp]
         L.orc_heq.restype = None
-        L.orc_force_pop.argtypes = [dp, dp]
+        L.orc_force_pop.argtypes = [dp, dp, C.c_double, dp]
         L.orc_force_pop.restype = None
         L.orc_aux_source.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_aux_source.restype = None
         L.orc_source_pop.argtypes = [C.c_int, dp, dp]
         L.orc_source_pop.restype = None
-        L.orc_relaxation_matrix.argtypes = [C.c_int, dp, dp]
+        L.orc_relaxation_matrix.argtypes = [C.c_int, dp, dp, dp]
         L.orc_mrt_basis.argtypes = [dp, dp]
         L.orc_threads.restype = C.c_int
         L.orc_cutoff.argtypes = [C.POINTER(OrcCfg), C.c_double]
@@ -138,6 +140,11 @@ def make_cfg(wl: dict, mutation: int = 0) -> OrcCfg:
     for s in range(4):
         for a in range(m):
             c.wall[s * MAXM + a] = wall[s, a]
+    lam = np.asarray(wl.get("lam", np.eye(m)), dtype=np.float64).reshape(m, m)
+    for a in range(m):
+        for b in range(m):
+            c.lam[a * m + b] = lam[a, b]
+    c.varphi = wl.get("varphi", 0.0)
     return c
 
 
@@ -158,7 +165,8 @@ class Oracle:
         self._p0 = None if p0 is None else np.ascontiguousarray(p0, dtype=np.float64).reshape(ny, nx)
         pp = None if self._p0 is None else self._p0.ctypes.data_as(C.c_void_p)
         ok = self.L.orc_init(C.byref(self.cfg), phi0, u0, pp, self.f, self.h, self.Sold)
-        assert ok == 1
+        if ok != 1:
+            raise ValueError("oracle: unsupported configuration (varphi != 0 needs BGK)")
         self.t = 0
 
     def step(self, n: int):
@@ -177,11 +185,17 @@ class Oracle:
 
 
 # ---- single-node functions (for the moment-identity pins) -------------------
-def feq(phi, u):
-    phi = np.ascontiguousarray(phi, dtype=np.float64)
-    out = np.zeros(len(phi) * 5)
-    lib().orc_feq(len(phi), phi, np.ascontiguousarray(u, dtype=np.float64), out)
-    return out.reshape(len(phi), 5)
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ravel()
+
+
+def feq(phi, u, lam=None):
+    """Eq. feq-phi (vartheta = 0); lam defaults to the identity."""
+    m = len(phi)
+    lam = np.eye(m) if lam is None else lam
+    out = np.zeros(m * 5)
+    lib().orc_feq(m, _f64(lam), _f64(phi), _f64(u), out)
+    return out.reshape(m, 5)
 
 
 def heq(p, u, rho0):
@@ -190,9 +204,10 @@ def heq(p, u, rho0):
     return out
 
 
-def force_pop(F):
+def force_pop(F, u=(0.0, 0.0), varphi=0.0):
+    """Eq. force at velocity u with the parameter varphi."""
     out = np.zeros(9)
-    lib().orc_force_pop(np.ascontiguousarray(F, dtype=np.float64), out)
+    lib().orc_force_pop(_f64(F), _f64(u), float(varphi), out)
     return out
 
 
@@ -211,11 +226,13 @@ def source_pop(S):
     return out.reshape(m, 5)
 
 
-def relaxation_matrix(D):
+def relaxation_matrix(D, lam=None):
+    """Eq. omega-D; lam defaults to the identity."""
     D = np.ascontiguousarray(D, dtype=np.float64)
     m = D.shape[0]
+    lam = np.eye(m) if lam is None else lam
     out = np.zeros(m * m)
-    assert lib().orc_relaxation_matrix(m, D.ravel(), out) == 1
+    assert lib().orc_relaxation_matrix(m, D.ravel(), _f64(lam), out) == 1
     return out.reshape(m, m)
 
 

@@ -57,6 +57,23 @@ def test_scalar_moment_conditions(oracle_mod):
             assert np.allclose(G @ E5, M1G, rtol=1e-14, atol=1e-17)
 
 
+def test_scalar_moment_conditions_with_lambda(oracle_mod):
+    """Sec. 2.1 moment conditions for a general lambda: sum f^eq = phi,
+    sum c f^eq = phi u, sum cc f^eq = cs2 (lambda phi) I on D2Q5 (vartheta = 0)."""
+    O = oracle_mod
+    rng = np.random.default_rng(21)
+    for m in (1, 2, 3, 4):
+        for _ in range(5):
+            phi = rng.uniform(0.2, 2.0, m)
+            u = rng.uniform(-0.1, 0.1, 2)
+            lam = np.eye(m) + 0.3 * rng.uniform(-1, 1, (m, m))
+            feq = O.feq(phi, u, lam)
+            assert np.allclose(feq.sum(1), phi, rtol=0, atol=2e-15)
+            assert np.allclose(feq @ E5, np.outer(phi, u), rtol=0, atol=2e-15)
+            second = np.einsum("ai,ir,is->ars", feq, E5, E5)
+            assert np.allclose(second, (lam @ phi)[:, None, None] * CS2 * np.eye(2), rtol=0, atol=4e-15)
+
+
 def test_fluid_moment_conditions(oracle_mod):
     """Eq. momentNS: sum h^eq = rho0, sum c h^eq = u, sum cc h^eq = p I + uu,
     sum ccc h^eq = cs2 (u_a d_bg + u_b d_ag + u_g d_ab); sum F_i = 0,
@@ -78,6 +95,12 @@ def test_fluid_moment_conditions(oracle_mod):
         Fi = O.force_pop(F)
         assert abs(Fi.sum()) < 1e-18 and np.allclose(Fi @ E9, F, atol=1e-18)
         assert np.allclose(np.einsum("i,ir,is->rs", Fi, E9, E9), 0, atol=1e-18)
+        # general varphi: sum cc F_i = varphi (uF + Fu)
+        for varphi in (1.0, 0.37):
+            Fi = O.force_pop(F, u, varphi)
+            assert abs(Fi.sum()) < 1e-18 and np.allclose(Fi @ E9, F, atol=1e-18)
+            UF = np.outer(u, F) + np.outer(F, u)
+            assert np.allclose(np.einsum("i,ir,is->rs", Fi, E9, E9), varphi * UF, rtol=0, atol=1e-19)
 
 
 def test_relaxation_matrix_reproduces_D(oracle_mod):
@@ -94,6 +117,20 @@ def test_relaxation_matrix_reproduces_D(oracle_mod):
     # config-1 matrix: omega printed with 5 decimals in the workload recipe
     om = O.relaxation_matrix(np.array([[0.01, 0.002], [0.001, 0.01]]))
     assert np.allclose(om, [[1.88691, -0.02136], [-0.01068, 1.88691]], atol=1e-5)
+
+
+def test_relaxation_matrix_with_lambda(oracle_mod):
+    """Eq. omega-D with a general lambda: D = (omega^-1 - I/2) lambda cs2 dt,
+    with lambda and D chosen not to commute (so lambda's side matters)."""
+    O = oracle_mod
+    rng = np.random.default_rng(22)
+    for m in (2, 3, 4):
+        D = np.diag(rng.uniform(0.05, 0.3, m)) + 0.02 * rng.uniform(-1, 1, (m, m))
+        lam = np.eye(m) + 0.2 * rng.uniform(-1, 1, (m, m))
+        om = O.relaxation_matrix(D, lam)
+        back = (np.linalg.inv(om) - 0.5 * np.eye(m)) @ lam * CS2
+        assert np.allclose(back, D, rtol=1e-12, atol=1e-16)
+        assert not np.allclose(D @ lam, lam @ D)
 
 
 def _recovery_err(O, mutation=0):
@@ -328,6 +365,82 @@ def test_gaussian_pulse_second_order(oracle_mod):
     assert 3.5 < e1 / e2 < 4.5
 
 
+LAM_PULSE = [[0.6, 0.3], [-0.1, 1.2]]
+
+
+def _pulse_lam_err(O, n, sigma, steps, mutation=0):
+    """The Gaussian-pulse closed form with lambda != I (not commuting with D):
+    the scheme must still recover d_t phi = div(D grad phi) (Eq. omega-D)."""
+    D = np.array([[0.1, 0.03], [0.02, 0.05]])
+    lam, P = np.linalg.eig(D)
+    wl = W._base(n, n, 2, 0.8, D, lam=LAM_PULSE)
+    X, Y = W.cell_centres(n, n)
+    amps = [0.5, 0.3]
+    psi0 = np.stack([_gauss(X, Y, n / 2, n / 2, sigma ** 2, n, amps[k]) for k in range(2)])
+    o = O.Oracle(wl, np.einsum("ak,kyx->ayx", P, psi0) + 1.0, np.zeros((2, n, n)), mutation=mutation)
+    o.step(steps)
+    phi, _, _ = o.moments()
+    psit = np.stack([_gauss(X, Y, n / 2, n / 2, sigma ** 2 + 2 * lam[k] * steps, n,
+                            amps[k] * sigma ** 2 / (sigma ** 2 + 2 * lam[k] * steps)) for k in range(2)])
+    exact = np.einsum("ak,kyx->ayx", P, psit) + 1.0
+    return np.abs(phi - exact).max() / np.abs(exact - 1).max()
+
+
+def test_gaussian_pulse_with_lambda_second_order(oracle_mod):
+    e1 = _pulse_lam_err(oracle_mod, 64, 4.0, 200)
+    e2 = _pulse_lam_err(oracle_mod, 128, 8.0, 800)
+    assert e1 < 7e-3 and e2 < 1.8e-3
+    assert 3.5 < e1 / e2 < 4.5
+
+
+def _accel_err(O, varphi=1.0, mutation=0, steps=100):
+    """Uniform flow under a uniform force in a periodic box: u(t) = u0 + F t
+    exactly, and with the pressure of appendix A (which adds dt (1/omega - 1/2)
+    F_0 to the rest-population balance) the rest population h_0 stays exactly
+    constant: its equilibrium is h_0 - dt (1/omega - 1/2) F_0, so the relaxation
+    removes exactly what the forcing adds.  Any sign or factor slip in the
+    varphi terms (Eq. force or the pressure) makes h_0 drift."""
+    n, tau = 4, 0.8
+    F = [2e-4, -1e-4]
+    wl = W._base(n, n, 1, tau, [[0.1]], F0=F, varphi=varphi)
+    u0 = np.zeros((2, n, n))
+    u0[0], u0[1] = 0.02, 0.01
+    o = O.Oracle(wl, np.ones((1, n, n)), u0, mutation=mutation)
+    h00 = o.h[0].copy()
+    o.step(steps)
+    _, u, _ = o.moments()
+    du = max(np.abs(u[0] - (0.02 + steps * F[0])).max(), np.abs(u[1] - (0.01 + steps * F[1])).max())
+    return max(np.abs(o.h[0] - h00).max(), du)
+
+
+def test_uniform_acceleration_rest_population_invariant(oracle_mod):
+    for varphi in (0.0, 1.0, 0.5):
+        assert _accel_err(oracle_mod, varphi) < 1e-14
+
+
+def test_momentum_flux_error_term_of_varphi(oracle_mod):
+    """Appendix A (the stress of the forced D2Q9 scheme): sum cc h^ne +
+    (dt/2) varphi (uF + Fu) = dt (varphi - 1)/omega (uF + Fu) + viscous part.
+    In uniformly accelerated flow the viscous part is zero, so the off-diagonal
+    component must follow the first term: it vanishes for varphi = 1."""
+    O = oracle_mod
+    n, tau, steps = 4, 0.8, 200
+    F = np.array([2e-5, -1e-5])
+    for varphi in (0.0, 0.5, 1.0):
+        wl = W._base(n, n, 1, tau, [[0.1]], F0=F.tolist(), varphi=varphi)
+        u0 = np.zeros((2, n, n))
+        u0[0], u0[1] = 0.05, 0.03
+        o = O.Oracle(wl, np.ones((1, n, n)), u0)
+        o.step(steps)
+        _, u, _ = o.moments()
+        h, uu = o.h[:, 0, 0], u[:, 0, 0]
+        UFxy = uu[0] * F[1] + F[0] * uu[1]
+        R = (h * E9[:, 0] * E9[:, 1]).sum() - uu[0] * uu[1] + 0.5 * varphi * UFxy
+        want = (varphi - 1.0) * tau * UFxy
+        # the remainder is O(F^2): (dt/omega) F_x F_y and rounding
+        assert abs(R - want) <= 2 * tau * abs(F[0] * F[1]) + 1e-17, (varphi, R, want)
+
+
 def _tg_err(O, n, collision="bgk"):
     """Taylor-Green vortex: u decays as exp(-2 nu k^2 t), nu = (tau - 1/2) cs2."""
     tau = 0.8
@@ -462,6 +575,10 @@ MUTATIONS = {
     8: "advective term of f^eq with the wrong sign",
     9: "free-slip wall treated as bounce-back",
     10: "relaxation matrix built with I instead of I/2 and cs2 dropped",
+    11: "lambda part of f^eq with the printed D2Q9 normalisation (half the second moment on D2Q5)",
+    12: "lambda on the wrong side of D in the relaxation matrix",
+    13: "varphi pressure correction with the wrong sign",
+    14: "varphi term of the discrete force dropped",
 }
 
 
@@ -475,6 +592,8 @@ def _battery(O, mutation):
         "poiseuille": _poiseuille_err(O, "noslip", mutation) < 1e-12,
         "plug": _plug_err(O, mutation) < 1e-12,
         "pulse": _pulse_err(O, 64, 4.0, 200, mutation) < 7e-3,
+        "pulse_lambda": _pulse_lam_err(O, 64, 4.0, 200, mutation) < 7e-3,
+        "accel_varphi": _accel_err(O, 1.0, mutation) < 1e-14,
     }
 
 
