@@ -111,6 +111,19 @@ typedef struct lb_params {
     double phi_ref[LB_MAX_M];    /* reference level subtracted in reduced-precision storage */
     double fp16_scale;           /* multiplier of the scalar deviations in LB_STORE_F16 (> 0) */
     double fp16_scale_h;         /* multiplier of the fluid deviations in LB_STORE_F16 (> 0) */
+    double lam[LB_MAX_M * LB_MAX_M]; /* lambda of Eq. feq-phi, row-major m x m; all zeros means the
+                                    identity (Sec. 3).  With lambda != I the relaxation matrix is
+                                    omega = (3 D lambda^-1 + I/2)^-1 (Eq. omega-D) and the D2Q5
+                                    equilibrium gains (lambda phi - phi)_a x (-2/3, 1/6, 1/6, 1/6, 1/6):
+                                    the lambda part of Eq. feq-phi scaled so that its second moment
+                                    is cs^2 (lambda phi - phi) I (Sec. 2.1), twice the printed
+                                    D2Q9 form.  LINEAR and CDE models only; the eigenvalues of lambda
+                                    need real parts in (0, 3/2) (positive rest weight) and those of
+                                    D lambda^-1 positive real parts */
+    double varphi;               /* varphi of Eq. force (0 in Sec. 3): F_i gains
+                                    varphi W_i (uF + Fu):(c_i c_i - cs^2 I)/(2 cs^4) and the pressure
+                                    dt (1/omega - 1/2) F_0 inside the bracket of appendix A.  BGK only;
+                                    not for the no-fluid model */
 } lb_params;
 
 typedef struct lb_handle lb_handle;
@@ -137,7 +150,7 @@ lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace
 lb_status lb_step(lb_handle* h, int64_t n);
 
 /* Macroscopic fields at the current time (Eq. sum): phi [m][ny][nx], u [2][ny][nx]
- * (u = sum_i c_i h_i + F/2), p [ny][nx] (appendix A, varphi = 0).  Host arrays;
+ * (u = sum_i c_i h_i + F/2), p [ny][nx] (appendix A, with the varphi term).  Host arrays;
  * any may be NULL.  Synchronises the stream. */
 lb_status lb_moments(lb_handle* h, double* phi, double* u, double* p);
 

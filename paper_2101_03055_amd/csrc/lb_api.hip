@@ -172,6 +172,36 @@ bool invert(int m, const double* A, double* out) {
     return true;
 }
 
+// lambda of Eq. feq-phi as given (all zeros: the identity); returns whether it differs from I
+bool lambda_matrix(const lb_params& p, double* lam) {
+    const int m = p.m;
+    bool zero = true, ident = true;
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            const double v = p.lam[a * m + b];
+            zero = zero && v == 0.0;
+            ident = ident && v == (a == b ? 1.0 : 0.0);
+        }
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) lam[a * m + b] = zero ? (a == b ? 1.0 : 0.0) : p.lam[a * m + b];
+    return !(zero || ident);
+}
+
+// D lambda^-1 (Eq. omega-D: omega^-1 = 3 D lambda^-1 + I/2); false if lambda is singular
+bool d_lambda_inv(const lb_params& p, double* out) {
+    const int m = p.m;
+    double lam[LB_MAX_M * LB_MAX_M], li[LB_MAX_M * LB_MAX_M];
+    lambda_matrix(p, lam);
+    if (!invert(m, lam, li)) return false;
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < m; ++c) s += p.D[a * m + c] * li[c * m + b];
+            out[a * m + b] = s;
+        }
+    return true;
+}
+
 lb_status validate(const lb_params* p) {
     if (!p) return fail(LB_EINVAL, "params is NULL");
     if (p->nx < 2 || p->ny < 2) return fail(LB_EINVAL, "grid %d x %d: each side must be >= 2", p->nx, p->ny);
@@ -216,13 +246,32 @@ lb_status validate(const lb_params* p) {
                 return fail(LB_EINVAL, "mrt_s[%d] = %g outside (0, 2)", k, p->mrt_s[k]);
     const int m = p->m;
     for (int k = 0; k < m * m; ++k)
-        if (!std::isfinite(p->D[k]) || !std::isfinite(p->K[k])) return fail(LB_EINVAL, "D or K not finite");
+        if (!std::isfinite(p->D[k]) || !std::isfinite(p->K[k]) || !std::isfinite(p->lam[k]))
+            return fail(LB_EINVAL, "D, K or lambda not finite");
+    if (!std::isfinite(p->varphi)) return fail(LB_EINVAL, "varphi not finite");
+    if (p->varphi != 0.0 && p->collision != LB_COLL_BGK)
+        return fail(LB_EINVAL, "varphi != 0 needs BGK (its pressure correction uses the single fluid rate)");
+    if (p->varphi != 0.0 && p->model == LB_MODEL_CDE) return fail(LB_EINVAL, "no-fluid model: varphi must be 0");
+    double lamm[LB_MAX_M * LB_MAX_M];
+    const bool lam_on = lambda_matrix(*p, lamm);
+    if (lam_on && p->model == LB_MODEL_CHEMOTAXIS)
+        return fail(LB_EINVAL, "chemotaxis model: lambda must be the identity");
+    if (lam_on) {
+        std::complex<double> ev[LB_MAX_M];
+        eigenvalues(m, lamm, ev);
+        for (int k = 0; k < m; ++k)
+            if (!(ev[k].real() > 0.0 && ev[k].real() < 1.5))
+                return fail(LB_EINVAL, "lambda has an eigenvalue with real part %g outside (0, 3/2): "
+                            "the rest weight of the equilibrium would not be positive", ev[k].real());
+    }
     if (p->model == LB_MODEL_LINEAR || p->model == LB_MODEL_CDE) {
+        double dl[LB_MAX_M * LB_MAX_M];
+        if (!d_lambda_inv(*p, dl)) return fail(LB_EINVAL, "lambda is singular");
         std::complex<double> lam[LB_MAX_M];
-        eigenvalues(m, p->D, lam);
+        eigenvalues(m, dl, lam);
         for (int k = 0; k < m; ++k)
             if (!(lam[k].real() > 0.0))
-                return fail(LB_EINVAL, "D has an eigenvalue with real part %g <= 0: eig(omega) leaves (0, 2)",
+                return fail(LB_EINVAL, "D lambda^-1 has an eigenvalue with real part %g <= 0: eig(omega) leaves (0, 2)",
                             lam[k].real());
     } else {
         if (!(p->D[0] > 0.0 && p->D[3] > 0.0)) return fail(LB_EINVAL, "chemotaxis: D00, D11 must be > 0");
@@ -259,11 +308,21 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     k.h0_shift = T(shifted ? p.rho0 : 0.0);
     const int m = p.m;
     if (p.model == LB_MODEL_LINEAR || p.model == LB_MODEL_CDE) {
-        double A[LB_MAX_M * LB_MAX_M], om[LB_MAX_M * LB_MAX_M];
+        // Eq. omega-D: omega = (3 D lambda^-1 + I/2)^-1 (lambda = I: (3 D + I/2)^-1)
+        double A[LB_MAX_M * LB_MAX_M], om[LB_MAX_M * LB_MAX_M], dl[LB_MAX_M * LB_MAX_M];
+        double lam[LB_MAX_M * LB_MAX_M];
+        k.lam_on = lambda_matrix(p, lam) ? 1 : 0;
+        if (k.lam_on) {
+            d_lambda_inv(p, dl);
+        } else {
+            for (int q = 0; q < m * m; ++q) dl[q] = p.D[q];
+        }
         for (int a = 0; a < m; ++a)
-            for (int b = 0; b < m; ++b) A[a * m + b] = 3.0 * p.D[a * m + b] + (a == b ? 0.5 : 0.0);
+            for (int b = 0; b < m; ++b) A[a * m + b] = 3.0 * dl[a * m + b] + (a == b ? 0.5 : 0.0);
         invert(m, A, om);
         for (int q = 0; q < m * m; ++q) k.omega[q] = T(om[q]);
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) k.lamm[a * m + b] = T(lam[a * m + b] - (a == b ? 1.0 : 0.0));
     } else {
         for (int q = 0; q < 4; ++q) k.Dc[q] = T(p.D[q]);
     }
@@ -287,6 +346,8 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     k.inv_scale = T(p.storage == LB_STORE_F16 ? 1.0 / p.fp16_scale : 1.0);
     k.scale_h = T(p.storage == LB_STORE_F16 ? p.fp16_scale_h : 1.0);
     k.inv_scale_h = T(p.storage == LB_STORE_F16 ? 1.0 / p.fp16_scale_h : 1.0);
+    k.varphi = T(p.varphi);
+    k.vp_p = T((p.tau_f - 0.5) * (4.0 / 3.0) * p.varphi);
 }
 
 }  // namespace

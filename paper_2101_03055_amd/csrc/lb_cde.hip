@@ -133,7 +133,9 @@ __device__ __forceinline__ void collide_cde(const KParams<T>& kp, T f[M][5], con
     T feq[M][5], wsrc[M][5];
 #pragma unroll
     for (int b = 0; b < M; ++b) {
-        const T iso = phid[b] * (T(1) / T(6));
+        T pd = phid[b];
+        if (kp.lam_on) pd += lam_excess<T, M>(kp, phi, b);  // lambda != I (D2Q5 form)
+        const T iso = pd * (T(1) / T(6));
         const T adv = T(0.5) * phi[b];
         feq[b][1] = iso + adv * u[0];
         feq[b][3] = iso - adv * u[0];
@@ -215,7 +217,9 @@ __global__ __launch_bounds__(256) void k_cde_init(KParams<typename St<S>::T> kp,
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const T phid = phi[a] - kp.phi_ref[a];
-        const T iso = phid * (T(1) / T(6));
+        T pd = phid;
+        if (kp.lam_on) pd += lam_excess<T, M>(kp, phi, a);
+        const T iso = pd * (T(1) / T(6));
         const T adv = T(0.5) * phi[a];
         st(pop, cidx<M>(5 * a + 1, n), iso + adv * u[0], kp, false, 0u);
         st(pop, cidx<M>(5 * a + 3, n), iso - adv * u[0], kp, false, 0u);

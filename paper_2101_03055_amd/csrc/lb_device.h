@@ -370,8 +370,20 @@ __device__ __forceinline__ void macro(const KParams<T>& kp, const T h[9], const 
     mc.u[1] = jy + T(0.5) * mc.F[1];
     const T s = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
     const T usq = mc.u[0] * mc.u[0] + mc.u[1] * mc.u[1];
-    // p = cs2/(1 - W0) [sum_{i>0} h_i - W0 u.u/(2 cs2)] = (3/5)(s - (2/3) u.u)
-    mc.p = T(0.6) * (s - (T(2) / T(3)) * usq);
+    // p = cs2/(1 - W0) [sum_{i>0} h_i - W0 u.u/(2 cs2) + (1/omega - 1/2) F_0] (appendix A)
+    //   = (3/5)(s - (2/3) u.u - (tau_f - 1/2)(4/3) varphi u.F)
+    T corr = T(0);
+    if (kp.varphi != T(0)) corr = kp.vp_p * (mc.u[0] * mc.F[0] + mc.u[1] * mc.F[1]);
+    mc.p = T(0.6) * ((s - (T(2) / T(3)) * usq) - corr);
+}
+
+// (lambda phi - phi)_b of Eq. feq-phi: zero unless lambda != I
+template <class T, int M>
+__device__ __forceinline__ T lam_excess(const KParams<T>& kp, const T phi[M], int b) {
+    T x = T(0);
+#pragma unroll
+    for (int c = 0; c < M; ++c) x += kp.lamm[b * M + c] * phi[c];
+    return x;
 }
 
 // ---- the node update ------------------------------------------------------
@@ -433,14 +445,19 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
     }
 
     // scalar matrix collision (Eq. evolution12), f^eq of Eq. feq-phi with
-    // lambda = I, vartheta = 0 in deviation form: W_i (phid + 3 phi c.u).
-    // The rest direction takes the remainder, f^eq_0 = phid - sum_{i>0} f^eq_i
-    // (and likewise for W_i S): with rounded weights sum_i W_i != 1, which
-    // would create or destroy mass by the same fraction at every step.
+    // vartheta = 0 in deviation form: W_i (phid + 3 phi c.u), plus (lambda phi -
+    // phi)/6 on the moving directions when lambda != I (the D2Q5 form whose
+    // second moment is cs2 (lambda phi - phi)).  The rest direction takes the
+    // remainder, f^eq_0 = phid - sum_{i>0} f^eq_i (and likewise for W_i S):
+    // with rounded weights sum_i W_i != 1, which would create or destroy mass
+    // by the same fraction at every step.
     T feq[M][5], wsrc[M][5];
 #pragma unroll
     for (int b = 0; b < M; ++b) {
-        const T iso = mc.phid[b] * (T(1) / T(6));
+        T pd = mc.phid[b];
+        if constexpr (MODEL != LB_MODEL_CHEMOTAXIS)
+            if (kp.lam_on) pd += lam_excess<T, M>(kp, mc.phi, b);
+        const T iso = pd * (T(1) / T(6));
         const T adv = T(0.5) * mc.phi[b];  // 3 W_i phi for i > 0
         feq[b][1] = iso + adv * mc.u[0];
         feq[b][3] = iso - adv * mc.u[0];
@@ -467,7 +484,7 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
         }
     }
 
-    // fluid: h^eq of Eq. heq, F_i of Eq. force with varphi = 0
+    // fluid: h^eq of Eq. heq, F_i of Eq. force
     const T usq = mc.u[0] * mc.u[0] + mc.u[1] * mc.u[1];
     // h^eq_0 = rho0 - sum_{i>0} h^eq_i (Eq. momentNS: sum_i h^eq_i = rho0), which
     // equals sigma_0 - W_0 u.u/(2 cs2) of Eq. heq without a rounding bias
@@ -485,6 +502,16 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
     for (int i = 0; i < 9; ++i) {
         const T cF = T(CX9[i]) * mc.F[0] + T(CY9[i]) * mc.F[1];
         Fi[i] = T(3) * w9<T>(i) * cF;
+    }
+    if (kp.varphi != T(0)) {
+        // varphi W_i (uF + Fu):(c c - cs2 I)/(2 cs2^2) = varphi W_i (9 (c.u)(c.F) - 3 u.F)
+        const T uF = mc.u[0] * mc.F[0] + mc.u[1] * mc.F[1];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T cF = T(CX9[i]) * mc.F[0] + T(CY9[i]) * mc.F[1];
+            const T cu = T(CX9[i]) * mc.u[0] + T(CY9[i]) * mc.u[1];
+            Fi[i] += kp.varphi * w9<T>(i) * (T(9) * cu * cF - T(3) * uF);
+        }
     }
     const T w = kp.omega_f;
     if constexpr (COLL == LB_COLL_BGK) {

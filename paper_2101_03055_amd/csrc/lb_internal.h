@@ -35,6 +35,10 @@ struct KParams {
     T phi_ref[LB_MAX_M];
     T scale, inv_scale;   // storage scale of the scalar planes (F16 only; 1 otherwise)
     T scale_h, inv_scale_h; // storage scale of the fluid planes (F16 only; 1 otherwise)
+    int lam_on;           // lambda != I in the scalar equilibrium (linear and no-fluid models)
+    T lamm[LB_MAX_M * LB_MAX_M]; // lambda - I, row-major
+    T varphi;             // varphi of Eq. force (0: the force term of Sec. 3)
+    T vp_p;               // pressure correction per u.F: (tau_f - 1/2) (4/3) varphi
 };
 
 struct Layout {

@@ -262,7 +262,10 @@ __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* 
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         const T phid = phi[a] - kp.phi_ref[a];
-        const T iso = phid * (T(1) / T(6));
+        T pd = phid;
+        if constexpr (MODEL != LB_MODEL_CHEMOTAXIS)
+            if (kp.lam_on) pd += lam_excess<T, M>(kp, phi, a);
+        const T iso = pd * (T(1) / T(6));
         const T adv = T(0.5) * phi[a];
         st(pop, pidx<M>((9 + 5 * a + 1), n), iso + adv * u[0], kp, false, salt);
         st(pop, pidx<M>((9 + 5 * a + 3), n), iso - adv * u[0], kp, false, salt);

@@ -54,6 +54,8 @@ class lb_params(C.Structure):
         ("phi_ref", C.c_double * MAXM),
         ("fp16_scale", C.c_double),
         ("fp16_scale_h", C.c_double),
+        ("lam", C.c_double * (MAXM * MAXM)),
+        ("varphi", C.c_double),
     ]
 
 
@@ -165,6 +167,12 @@ def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scal
     p.fp16_scale = fp16_scale
     p.fp16_scale_h = fp16_scale if fp16_scale_h is None else fp16_scale_h
     p.fused_steps = int(fused_steps)
+    if "lam" in wl:
+        lam = np.asarray(wl["lam"], dtype=np.float64).reshape(m, m)
+        for a in range(m):
+            for b in range(m):
+                p.lam[a * m + b] = lam[a, b]
+    p.varphi = float(wl.get("varphi", 0.0))
     return p
 
 

@@ -121,3 +121,48 @@ def test_no_fluid_model_needs_no_fluid_planes():
     wl["model"] = "linear"
     b_lin = lb.lb_workspace_bytes(lb.params_from_workload(wl))
     assert b_cde < b_lin
+
+
+def _set_lam(p, m, lam):
+    for a in range(m):
+        for b in range(m):
+            p.lam[a * m + b] = lam[a][b]
+
+
+def test_lambda_and_varphi_accepted():
+    wl, *_ = W.taylor_green_blobs()
+    p = lb.params_from_workload(wl)
+    _set_lam(p, 2, [[0.6, 0.3], [-0.1, 1.2]])
+    p.varphi = 1.0
+    assert lb.lb_workspace_bytes(p) > 0
+    wl, *_ = W.cde_case(16, 12)
+    p = lb.params_from_workload(wl)
+    _set_lam(p, wl["m"], np.eye(wl["m"]) * 0.9)
+    assert lb.lb_workspace_bytes(p) > 0
+
+
+@pytest.mark.parametrize("case", ["singular", "rest_weight", "negative", "chemotaxis", "mrt_varphi",
+                                  "cde_varphi", "nonfinite"])
+def test_lambda_and_varphi_validation(case):
+    if case == "chemotaxis":
+        wl, *_ = W.random_case(16, 12, m=2, seed=1, model="chemotaxis")
+    elif case == "cde_varphi":
+        wl, *_ = W.cde_case(16, 12)
+    else:
+        wl, *_ = W.taylor_green_blobs()
+    p = lb.params_from_workload(wl)
+    m = wl["m"]
+    lam = {"singular": [[1.0, 1.0], [1.0, 1.0]], "rest_weight": [[1.6, 0.0], [0.0, 1.0]],
+           "negative": [[1.0, 0.0], [0.0, -0.5]], "chemotaxis": [[0.9, 0.0], [0.0, 1.0]]}.get(case)
+    if lam is not None:
+        _set_lam(p, m, lam)
+    if case == "mrt_varphi":
+        p.collision = 1
+        p.varphi = 1.0
+    if case == "cde_varphi":
+        p.varphi = 1.0
+    if case == "nonfinite":
+        p.varphi = float("nan")
+    with pytest.raises(lb.LBError) as ei:
+        lb.lb_workspace_bytes(p)
+    assert ei.value.status == lb.LB_EINVAL
