@@ -290,3 +290,83 @@ def ddc_case(pd, collision="bgk", u_lat=0.1):
     """Cavity workload (record, cold initial fields) for one parameter draw."""
     return ddc(pd["L"], Ra=pd["Ra"], Pr=pd.get("Pr", 0.71), Le=pd["Le"], Nc=pd["Nc"], Sr=pd["Sr"], Df=pd["Df"],
                u_lat=u_lat, collision=collision)
+
+
+# ---------------------------------------------------------------------------
+# Three dimensions (D3Q7 scalars, D3Q19 fluid): records carry nz, 6 sides
+# (x-, x+, y-, y+, z-, z+), F0[3], Fphi[m][3]; fields phi0[m][nz][ny][nx],
+# u0[3][nz][ny][nx], p0[nz][ny][nx]
+# ---------------------------------------------------------------------------
+def base3(nx, ny, nz, m, tau_f, D, **kw):
+    wl = {
+        "dim": 3, "nx": int(nx), "ny": int(ny), "nz": int(nz), "m": int(m), "tau_f": float(tau_f), "rho0": 1.0,
+        "D": np.asarray(D, dtype=np.float64).reshape(m, m).tolist(), "K": np.zeros((m, m)).tolist(),
+        "F0": [0.0, 0.0, 0.0], "Fphi": np.zeros((m, 3)).tolist(),
+        "fluid_bc": ["periodic"] * 6, "scalar_bc": [["periodic"] * m for _ in range(6)],
+        "wall": np.zeros((6, m)).tolist(),
+    }
+    wl.update(kw)
+    return wl
+
+
+def cell_centres3(nx, ny, nz):
+    """X, Y, Z of the cell centres, each shaped [nz][ny][nx]."""
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    return x, y, z
+
+
+def random_case3(nx, ny, nz, m=2, seed=0, fluid_bc=None, scalar_bc=None, force=True, source=False, amp=0.05):
+    """A small random 3-D case: smooth-ish random fields, SPD-dominant D."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    D = np.diag(rng.uniform(0.02, 0.15, size=m))
+    D += 0.2 * np.min(np.diag(D)) * rng.uniform(-1, 1, size=(m, m)) * (1 - np.eye(m))
+    wl = base3(nx, ny, nz, m, float(rng.uniform(0.6, 1.2)), D)
+    if fluid_bc is not None:
+        wl["fluid_bc"] = list(fluid_bc)
+    if scalar_bc is not None:
+        wl["scalar_bc"] = [list(r) for r in scalar_bc]
+    wl["wall"] = rng.uniform(0.5, 1.5, size=(6, m)).tolist()
+    if force:
+        wl["F0"] = rng.uniform(-2e-5, 2e-5, size=3).tolist()
+        wl["Fphi"] = rng.uniform(-2e-5, 2e-5, size=(m, 3)).tolist()
+    if source:
+        wl["K"] = (-rng.uniform(0.0, 2e-3, size=(m, m))).tolist()
+    shape = (nz, ny, nx)
+
+    def smooth(a):  # cheap periodic smoothing so the fields are not pure noise
+        for ax in (-1, -2, -3):
+            a = 0.25 * (np.roll(a, 1, ax) + 2 * a + np.roll(a, -1, ax))
+        return a
+
+    phi0 = 1.0 + amp * np.stack([smooth(rng.standard_normal(shape)) for _ in range(m)])
+    u0 = 0.02 * np.stack([smooth(rng.standard_normal(shape)) for _ in range(3)])
+    p0 = 1e-3 * smooth(rng.standard_normal(shape))
+    wl["name"] = f"random3_{nx}x{ny}x{nz}_s{seed}"
+    return wl, phi0, u0, p0
+
+
+def taylor_green3(n=256, m=2, seed=1, tau_f=0.8, U0=0.02, sigma=None, D=((0.01, 0.002), (0.001, 0.01))):
+    """Periodic n^3 box: the 3-D Taylor-Green vortex
+    u = U0 sin kx cos ky cos kz, v = -U0 cos kx sin ky cos kz, w = 0,
+    p0 = (U0^2/16)(cos 2kx + cos 2ky)(cos 2kz + 2), carrying m cross-diffusing
+    Gaussian blobs (centres drawn with the seed, minimum image)."""
+    sigma = n / 10.0 if sigma is None else sigma
+    D = np.asarray(D, dtype=np.float64)[:m, :m]
+    wl = base3(n, n, n, m, tau_f, D)
+    X, Y, Z = cell_centres3(n, n, n)
+    k = 2.0 * math.pi / n
+    u0 = np.stack([U0 * np.sin(k * X) * np.cos(k * Y) * np.cos(k * Z),
+                   -U0 * np.cos(k * X) * np.sin(k * Y) * np.cos(k * Z),
+                   np.zeros_like(X)])
+    p0 = (U0 * U0 / 16.0) * (np.cos(2 * k * X) + np.cos(2 * k * Y)) * (np.cos(2 * k * Z) + 2.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = rng.uniform(0.0, n, size=(m, 3))
+    phi0 = np.empty((m, n, n, n))
+    for a in range(m):
+        d2 = np.zeros_like(X)
+        for c, C_ in zip((X, Y, Z), centres[a]):
+            dd = (c - C_ + n / 2) % n - n / 2
+            d2 += dd * dd
+        phi0[a] = 1.0 + np.exp(-d2 / (2 * sigma * sigma))
+    wl["name"] = f"taylor_green3_{n}^3"
+    return wl, phi0, u0, p0

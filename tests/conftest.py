@@ -18,3 +18,10 @@ def oracle_mod():
     from oracle import oracle as O
     O.build()
     return O
+
+
+@pytest.fixture(scope="session")
+def oracle3_mod():
+    from oracle import oracle3 as O3
+    O3.build()
+    return O3
