@@ -24,9 +24,10 @@ Prints one JSON line.  Besides the contract's fields:
                  1e-8 (batched FP32 phase + FP64 finish) from rest and from the
                  CNN surrogate's prediction (weights from the surrogate study);
   surrogate      training / inference throughput of the CNN (BF16 MFMA);
-  cde_sweep      the no-fluid model (prescribed velocity) on 4096^2.
-Long runs of steps are replayed by the library as HIP graphs of 64 launches.
-Modes for profiling: --mode pmc | copy | sweep | batch | surrogate | cde.
+  cde_sweep      the no-fluid model (prescribed velocity) on 4096^2;
+  sweep_3d       the 3-D path (D3Q7 + D3Q19) on a periodic 256^3 box.
+Long runs of 2-D steps are replayed by the library as HIP graphs of 64 launches.
+Modes for profiling: --mode pmc | copy | sweep | batch | surrogate | cde | 3d.
 """
 from __future__ import annotations
 
@@ -166,6 +167,31 @@ def cde_sweep(W, lb, torch, n=4096):
     return out
 
 
+def sweep_3d(W, torch, n=256):
+    """The 3-D path (D3Q7 scalars + D3Q19 fluid, m = 2): periodic Taylor-Green
+    vortex carrying two Gaussian blobs on n^3, FP64 and FP32.  Algorithmic
+    bytes per lattice update: the 19 + 7m populations read and written."""
+    from paper_2101_03055_amd import lb3
+
+    out = {}
+    wl, phi0, u0, p0 = W.taylor_green3(n)
+    for storage in ("f64", "f32"):
+        s = lb3.Solver3(wl, phi0, u0, p0, storage=storage, phi_ref=[1.0, 1.0])
+        s.step(4)
+        kt = kernel_time(s.step, s.stream, 40)
+        b = 8 if storage == "f64" else 4
+        bb = 2 * (19 + 7 * 2) * b
+        N = n ** 3
+        ach = bb * N / kt / 1e9
+        out[f"{storage}_{n}^3"] = {"MLUPS": round(N / kt / 1e6, 1), "achieved_GBs": round(ach, 1),
+                                   "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2),
+                                   "bytes_per_lu": bb}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_sweep(W, lb, torch):
     pds = W.sweep_params(256, seed=4)
     cases = [W.ddc_case(pd) for pd in pds]
@@ -271,7 +297,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "surrogate", "cde"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "surrogate", "cde", "3d"], default="bench",
                     help="pmc: only the timed workload's step kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy to calibrate the byte counters; "
                          "sweep / batch: only the 4096^2 or the batched-cavity leg (for profiles)")
@@ -302,6 +328,9 @@ def main():
         return
     if args.mode == "surrogate":
         print(json.dumps({"surrogate": surrogate_bench(torch)}), flush=True)
+        return
+    if args.mode == "3d":
+        print(json.dumps({"sweep_3d": sweep_3d(W, torch)}), flush=True)
         return
     if args.mode == "batch":
         print(json.dumps({"batched_sweep": batched_sweep(W, lb, torch)}), flush=True)
@@ -348,6 +377,7 @@ def main():
         out["batched_sweep"] = batched_sweep(W, lb, torch)
         out["cde_sweep"] = cde_sweep(W, lb, torch)
         torch.cuda.empty_cache()
+        out["sweep_3d"] = sweep_3d(W, torch)
         out["steady_warm_vs_cold"] = steady_warm_vs_cold(W, torch)
         out["surrogate"] = surrogate_bench(torch)
     if not args.no_cpu:

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBS = {
-    "liblbcdf.so": ["lb_kernels.hip", "lb_batch.hip", "lb_cde.hip", "lb_api.hip", "sg_kernels.hip"],
+    "liblbcdf.so": ["lb_kernels.hip", "lb_batch.hip", "lb_cde.hip", "lb_api.hip", "sg_kernels.hip", "lb3.hip"],
 }
 ARCH = os.environ.get("LBCDF_OFFLOAD_ARCH", "gfx950")
 

@@ -11,8 +11,8 @@ plus what the equations fix: the bacteria total is conserved (no-flux walls,
 no source), and the initial data are mirror symmetric about x = 0, which the
 scheme preserves up to rounding (the lattice is symmetric under x -> -x).
 
-``python -m paper_2101_03055_amd.plume_study --out DIR`` writes summary.json
-(and fields.npz with the snapshots) to DIR.
+``python -m paper_2101_03055_amd.plume_study --out DIR`` runs the cases of
+CASES and writes summary.json (and the snapshots, fields_<case>.npz) to DIR.
 """
 from __future__ import annotations
 
@@ -64,8 +64,15 @@ def snapshot(phi, u, y, dx, n_total0):
     }
 
 
-def run(nx=256, ny=128, dt=1e-7, storage="f64", times=TIMES, out=None):
-    wl, phi0, u0, p0 = W.chemotaxis_sinusoidal(nx, ny, dt)
+# (label, nx, ny, dt, a): the paper's grid and step on [-3, 3] (Secs. 3.1.1,
+# 3.1.3), the same at half the spacing (same dt/dx^2), and a [-1, 1] box
+CASES = (("paper_6x1_dx0.02", 300, 50, 2.5e-7, 3.0),
+         ("refined_6x1_dx0.01", 600, 100, 6.25e-8, 3.0),
+         ("narrow_2x1_dx0.0078", 256, 128, 1e-7, 1.0))
+
+
+def run(nx=300, ny=50, dt=2.5e-7, a=3.0, storage="f64", times=TIMES, out=None, label=None):
+    wl, phi0, u0, p0 = W.chemotaxis_sinusoidal(nx, ny, dt, a)
     dx = 1.0 / ny
     y = (np.arange(ny) + 0.5) * dx
     s = lb.Solver(wl, phi0, u0, p0, storage=storage, phi_ref=None if storage == "f64" else [0.75, 1.0])
@@ -85,28 +92,29 @@ def run(nx=256, ny=128, dt=1e-7, storage="f64", times=TIMES, out=None):
         fields[f"c_t{t}"] = phi[1].astype(np.float32)
         print(json.dumps(rec), flush=True)
     summary = {
-        "case": wl["name"], "nx": nx, "ny": ny, "dx": dx, "dt": dt, "storage": storage,
+        "case": label or wl["name"], "nx": nx, "ny": ny, "domain_x": [-a, a], "dx": dx, "dt": dt, "storage": storage,
         "tau_f": wl["tau_f"], "tau_n": 0.5 + 3 * wl["D"][0][0], "tau_c": 0.5 + 3 * wl["D"][1][1],
         "parameters": {"alpha": 10.0, "beta": 10.0, "delta": 5.0, "gamma": 1000.0, "Sc": 500.0, "cstar": 0.3},
         "snapshots": snaps,
     }
     if out:
         os.makedirs(out, exist_ok=True)
-        with open(os.path.join(out, "summary.json"), "w") as fh:
-            json.dump(summary, fh, indent=1)
-        np.savez_compressed(os.path.join(out, "fields.npz"), **fields)
+        np.savez_compressed(os.path.join(out, f"fields_{summary['case']}.npz"), **fields)
     return summary
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=None)
-    ap.add_argument("--nx", type=int, default=256)
-    ap.add_argument("--ny", type=int, default=128)
-    ap.add_argument("--dt", type=float, default=1e-7)
     ap.add_argument("--storage", default="f64")
     args = ap.parse_args()
-    run(args.nx, args.ny, args.dt, args.storage, out=args.out)
+    results = []
+    for label, nx, ny, dt, a in CASES:
+        print(f"== {label}: {nx} x {ny}, dt {dt}, x in [-{a}, {a}]", flush=True)
+        results.append(run(nx, ny, dt, a, args.storage, out=args.out, label=label))
+    if args.out:
+        with open(os.path.join(args.out, "summary.json"), "w") as fh:
+            json.dump({"cases": results}, fh, indent=1)
 
 
 if __name__ == "__main__":

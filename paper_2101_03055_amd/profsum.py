@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     ap.add_argument("--copy-kernel", default="__amd_rocclr_copyBuffer")
     ap.add_argument("--note", default="")
+    ap.add_argument("--sources", default=None,
+                    help="comma-separated kernel sources (under the package) hashed into the traffic record")
     args = ap.parse_args()
 
     stats = kernel_stats(args.stats)
@@ -107,7 +109,9 @@ def main():
             lines.append(f"Mean calibrated traffic per `{args.kernel}` launch: {mean:.0f} B" +
                          (f" ({mean / args.bytes_per_launch:.3f} x algorithmic)." if args.bytes_per_launch else "."))
             out_json = {"kernel": args.kernel, "traffic_bytes_per_launch": mean, "fetch_factor": ff,
-                        "write_factor": fw, "source_hash": source_hash(), "command": args.command}
+                        "write_factor": fw,
+                        "source_hash": source_hash(args.sources.split(",")) if args.sources else source_hash(),
+                        "command": args.command}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", args.name + ".md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")

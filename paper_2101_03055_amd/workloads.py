@@ -127,15 +127,19 @@ def chemotaxis_plume(nx=512, ny=256, seed=2, ratio=6.25e-4, alpha=10.0, beta=20.
     return wl, phi0, u0, p0
 
 
-def chemotaxis_sinusoidal(nx=256, ny=128, dt=1e-7, alpha=10.0, beta=10.0, delta=5.0, gamma=1000.0,
+def chemotaxis_sinusoidal(nx=300, ny=50, dt=2.5e-7, a=3.0, alpha=10.0, beta=10.0, delta=5.0, gamma=1000.0,
                           Sc=500.0):
     """Plumes from a sinusoidally modulated layer (Sec. 3.1.3, beta = 10,
-    gamma = 1000) on [-1, 1] x [0, 1], dx = 1/ny:
+    gamma = 1000) on [-a, a] x [0, 1], dx = 1/ny (nx = 2 a ny):
     n0 = 1 where y > 0.499 - 0.01 sin((x - 1.5) pi), 0.5 below; c0 = 1, u0 = 0
-    (cell centres).  Deterministic: no random draw."""
+    (cell centres).  Deterministic: no random draw.  The defaults are the
+    domain [-3, 3] x [0, 1], dx = 0.02 and dt = 2.5e-7 that the paper states
+    for its chemotaxis runs (Secs. 3.1.1 and 3.1.3)."""
     dx = 1.0 / ny
+    if abs(nx * dx - 2.0 * a) > 1e-9:
+        raise ValueError("nx must equal 2 a ny")
     X, Y = cell_centres(nx, ny)
-    x, y = -1.0 + X * dx, Y * dx
+    x, y = -a + X * dx, Y * dx
     n0 = np.where(y > 0.499 - 0.01 * np.sin((x - 1.5) * math.pi), 1.0, 0.5)
     wl, phi0, u0, p0 = chemotaxis(nx, ny, dx, dt, alpha, beta, delta, gamma, Sc, n0)
     wl["name"] = f"chemotaxis_sinusoidal_{nx}x{ny}"

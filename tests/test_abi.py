@@ -17,10 +17,10 @@ def declared(header):
     with open(os.path.join(ROOT, "include", header)) as fh:
         text = fh.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:lb|sg|lbb)_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:lb|sg|lbb|lb3)_[a-z_0-9]+)\s*\(", text)))
 
 
-@pytest.mark.parametrize("header", ["lb.h", "sg.h"])
+@pytest.mark.parametrize("header", ["lb.h", "sg.h", "lb3.h"])
 def test_library_exports_every_declared_symbol(header):
     L = lb.lib()
     names = declared(header)
@@ -166,3 +166,62 @@ def test_lambda_and_varphi_validation(case):
     with pytest.raises(lb.LBError) as ei:
         lb.lb_workspace_bytes(p)
     assert ei.value.status == lb.LB_EINVAL
+
+
+# ---- 3-D library (include/lb3.h) ------------------------------------------
+def test_lb3_params_record_matches():
+    from paper_2101_03055_amd import lb3
+    assert lb3.lib().lb3_params_bytes() == C.sizeof(lb3.lb3_params)
+
+
+@pytest.mark.parametrize("case", ["tau", "m", "grid", "half_pair", "freeslip", "f16", "eig", "nonfinite",
+                                  "scalar_periodic_mismatch"])
+def test_lb3_validation_rejects(case):
+    from paper_2101_03055_amd import lb3
+    wl, *_ = W.random_case3(12, 10, 8, m=2, seed=3)
+    p = lb3.params_from_workload(wl)
+    assert lb3.lb3_workspace_bytes(p) > 0
+    if case == "tau":
+        p.tau_f = 0.5
+    elif case == "m":
+        p.m = 5
+    elif case == "grid":
+        p.nz = 1
+    elif case == "half_pair":
+        p.fluid_bc[4] = 1
+    elif case == "freeslip":
+        p.fluid_bc[4] = p.fluid_bc[5] = 2
+    elif case == "f16":
+        p.storage = 2
+    elif case == "eig":
+        p.D[0] = -0.2
+    elif case == "nonfinite":
+        p.F0[2] = float("inf")
+    elif case == "scalar_periodic_mismatch":
+        p.fluid_bc[4] = p.fluid_bc[5] = 1
+    with pytest.raises(lb.LBError) as ei:
+        lb3.lb3_workspace_bytes(p)
+    assert ei.value.status == lb.LB_EINVAL
+    assert lb3.lib().lb3_last_error()
+
+
+def test_lb3_init_rejects_before_touching_the_device():
+    from paper_2101_03055_amd import lb3
+    wl, phi0, u0, p0 = W.random_case3(12, 10, 8, m=2, seed=3)
+    p = lb3.params_from_workload(wl)
+    n = lb3.lb3_workspace_bytes(p)
+    h = C.c_void_p()
+    L = lb3.lib()
+    phi0 = np.ascontiguousarray(phi0)
+    u0 = np.ascontiguousarray(u0)
+    assert L.lb3_init(C.byref(p), None, n, None, phi0.ctypes.data, u0.ctypes.data, None, C.byref(h)) == lb.LB_EINVAL
+    assert L.lb3_init(C.byref(p), C.c_void_p(0x1008), n, None, phi0.ctypes.data, u0.ctypes.data, None,
+                      C.byref(h)) == lb.LB_EINVAL
+    assert L.lb3_init(C.byref(p), C.c_void_p(0x10000), n - 1, None, phi0.ctypes.data, u0.ctypes.data, None,
+                      C.byref(h)) == lb.LB_ENOMEM
+    bad = phi0.copy()
+    bad[0, 1, 2, 3] = np.nan
+    assert L.lb3_init(C.byref(p), C.c_void_p(0x10000), n, None, bad.ctypes.data, u0.ctypes.data, None,
+                      C.byref(h)) == lb.LB_ENONFINITE
+    assert not h.value
+    assert L.lb3_free(None) == lb.LB_OK

@@ -1,0 +1,123 @@
+"""The 3-D path (include/lb3.h: D3Q7 scalars, D3Q19 fluid) against the 3-D
+oracle on the same seeded inputs, through the C ABI.  FP64 to 1e-11 (fluid
+populations normwise per plane, scalar populations pointwise, moments
+normwise per field), on ragged grids that span several workgroups, with
+periodic axes, walls on every face (edges and corners included) and mixed
+boundary sets, both AA parities."""
+import numpy as np
+import pytest
+
+from paper_2101_03055_amd import lb3, workloads as W
+from test_gpu_parity import plane_errors
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-11
+
+BC3 = {
+    "periodic": (["periodic"] * 6, [["periodic", "periodic"]] * 6),
+    "box_walls": (["noslip"] * 6, [["dirichlet", "noflux"], ["dirichlet", "dirichlet"], ["noflux", "noflux"],
+                                   ["noflux", "dirichlet"], ["dirichlet", "noflux"], ["noflux", "dirichlet"]]),
+    "channel_z": (["periodic"] * 4 + ["noslip"] * 2,
+                  [["periodic"] * 2] * 4 + [["dirichlet", "noflux"], ["noflux", "dirichlet"]]),
+    "duct_x": (["periodic", "periodic", "noslip", "noslip", "noslip", "noslip"],
+               [["periodic"] * 2] * 2 + [["noflux", "dirichlet"], ["dirichlet", "noflux"], ["noflux", "noflux"],
+                                         ["dirichlet", "dirichlet"]]),
+}
+
+
+def run3(oracle3_mod, case, steps, storage="f64", **kw):
+    wl, phi0, u0, p0 = case
+    o = oracle3_mod.Oracle3(wl, phi0, u0, p0)
+    g = lb3.Solver3(wl, phi0, u0, p0, storage=storage, **kw)
+    o.step(steps)
+    g.step(steps)
+    return o, g
+
+
+def errors3(o, g):
+    f, h = g.populations()
+    ef = plane_errors(f.reshape(-1, *f.shape[-2:]), o.f.reshape(-1, *o.f.shape[-2:]))
+    eh = max(np.abs(h[i] - o.h[i]).max() / max(np.abs(o.h[i]).max(), 1e-300) for i in range(19))
+    phi, u, p = g.moments()
+    po, uo, pro = o.moments()
+    em = max([np.abs(phi[a] - po[a]).max() / np.abs(po[a]).max() for a in range(phi.shape[0])] +
+             [np.abs(u[d] - uo[d]).max() / max(np.abs(uo[d]).max(), 1e-300) for d in range(3)] +
+             [np.abs(p - pro).max() / max(np.abs(pro).max(), 1e-300)])
+    return ef, eh, em
+
+
+@pytest.mark.parametrize("bc", sorted(BC3))
+@pytest.mark.parametrize("steps", [37, 60])
+def test_matches_oracle_fp64(oracle3_mod, bc, steps):
+    fb, sb = BC3[bc]
+    case = W.random_case3(21, 13, 11, m=2, seed=5, fluid_bc=fb, scalar_bc=sb, force=True, source=True)
+    o, g = run3(oracle3_mod, case, steps)
+    ef, eh, em = errors3(o, g)
+    print(f"3-D {bc} {steps} steps: f {ef:.2e} h {eh:.2e} moments {em:.2e}", flush=True)
+    assert ef <= TOL64 and eh <= TOL64 and em <= TOL64
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_species_count(oracle3_mod, m):
+    fb, sb = BC3["box_walls"]
+    sb = [[r[0]] * m for r in sb]
+    case = W.random_case3(19, 17, 9, m=m, seed=6 + m, fluid_bc=fb, scalar_bc=sb, source=True)
+    o, g = run3(oracle3_mod, case, 41)
+    ef, eh, em = errors3(o, g)
+    assert ef <= TOL64 and eh <= TOL64 and em <= TOL64
+
+
+def test_wide_grid_wall_tiles(oracle3_mod):
+    """nx >= 256 takes 256 x 1 workgroups; a ragged z extent and walls on y/z."""
+    fb, sb = BC3["duct_x"]
+    case = W.random_case3(300, 7, 5, m=2, seed=8, fluid_bc=fb, scalar_bc=sb)
+    o, g = run3(oracle3_mod, case, 25)
+    ef, eh, em = errors3(o, g)
+    assert ef <= TOL64 and eh <= TOL64 and em <= TOL64
+
+
+@pytest.mark.parametrize("tile", [(64, 1), (32, 2), (64, 4), (128, 2)])
+def test_tile_shapes_identical(tile):
+    fb, sb = BC3["box_walls"]
+    case = W.random_case3(21, 13, 11, m=2, seed=5, fluid_bc=fb, scalar_bc=sb, source=True)
+    a = lb3.Solver3(*case)
+    b = lb3.Solver3(*case)
+    b.set_tile(*tile)
+    a.step(23)
+    b.step(23)
+    for x, y in zip(a.moments(), b.moments()):
+        assert np.array_equal(x, y), tile
+
+
+def test_mass_conserved_and_matches_oracle(oracle3_mod):
+    case = W.random_case3(24, 20, 16, m=2, seed=9, force=True)
+    o, g = run3(oracle3_mod, case, 0)
+    m0 = g.mass()
+    g.step(101)
+    o.step(101)
+    m1 = g.mass()
+    assert np.all(np.abs(m1 - m0) <= 1e-12 * np.abs(m0))
+    want = [o.f[a].sum() for a in range(2)] + [o.h.sum()]
+    assert np.allclose(m1, want, rtol=1e-12, atol=0)
+    assert g.t == 101
+
+
+def test_fp32_close_to_oracle(oracle3_mod):
+    fb, sb = BC3["channel_z"]
+    case = W.random_case3(24, 20, 16, m=2, seed=10, fluid_bc=fb, scalar_bc=sb, force=True, source=True)
+    o, g = run3(oracle3_mod, case, 200, storage="f32", phi_ref=[1.0, 1.0])
+    phi, u, _ = g.moments()
+    po, uo, _ = o.moments()
+    ephi = max(np.abs(phi[a] - po[a]).max() / np.abs(po[a]).max() for a in range(2))
+    eu = max(np.abs(u[d] - uo[d]).max() / np.abs(uo[d]).max() for d in range(3))
+    print(f"3-D fp32: phi {ephi:.2e} u {eu:.2e}", flush=True)
+    assert ephi <= 2e-6 and eu <= 2e-4
+
+
+def test_larger_box_against_oracle(oracle3_mod):
+    """A box of 123 k nodes (several hundred workgroups) for a few steps."""
+    fb, sb = BC3["box_walls"]
+    case = W.random_case3(64, 48, 40, m=2, seed=11, fluid_bc=fb, scalar_bc=sb, force=True, source=True)
+    o, g = run3(oracle3_mod, case, 12)
+    ef, eh, em = errors3(o, g)
+    assert ef <= TOL64 and eh <= TOL64 and em <= TOL64
