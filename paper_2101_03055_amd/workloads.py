@@ -21,6 +21,7 @@ u0[2][ny][nx], p0[ny][nx]; node (i, j) sits at the cell centre
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 
@@ -374,3 +375,34 @@ def taylor_green3(n=256, m=2, seed=1, tau_f=0.8, U0=0.02, sigma=None, D=((0.01, 
         phi0[a] = 1.0 + np.exp(-d2 / (2 * sigma * sigma))
     wl["name"] = f"taylor_green3_{n}^3"
     return wl, phi0, u0, p0
+
+
+# ---------------------------------------------------------------------------
+# Named configurations (JSON files in configs/): each names a generator of
+# this module, its arguments and the run settings
+# ---------------------------------------------------------------------------
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def config_names():
+    return sorted(f[:-5] for f in os.listdir(CONFIG_DIR) if f.endswith(".json"))
+
+
+def load_config(name: str):
+    """(config dict, cases): cases is a list of (record, phi0, u0, p0) for the
+    generators that build fields, or of parameter draws for the surrogate's
+    seed ranges (built cavity by cavity by its study)."""
+    import json
+
+    path = name if name.endswith(".json") else os.path.join(CONFIG_DIR, name + ".json")
+    with open(path) as fh:
+        cfg = json.load(fh)
+    gen, kw = cfg["workload"], cfg.get("kwargs", {})
+    if gen == "sweep":
+        cases = [ddc_case(pd) for pd in sweep_params(**kw)]
+    elif gen == "sweep_case":
+        lo, hi = cfg["seeds"]["test"]
+        cases = [sweep_case(s, **kw) for s in range(lo, hi)]
+    else:
+        cases = [globals()[gen](**kw)]
+    return cfg, cases
