@@ -106,20 +106,30 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // binary16 with stochastic rounding: adding uniform random bits below the 10
 // kept mantissa bits to the magnitude and truncating rounds up with
 // probability equal to the discarded fraction, so increments smaller than
-// half an ulp survive in expectation.  The random bits depend only on the
-// element index and the step (salt), so runs are reproducible.  Values below
-// the binary16 normal range fall back to round-to-nearest.
-__device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t key) {
+// half an ulp survive in expectation.  Values below the binary16 normal range
+// fall back to round-to-nearest.  dither: 13 random bits.
+__device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t dither) {
     if (!(fabsf(v) >= 6.103515625e-05f) || !(fabsf(v) < 65504.0f)) return _Float16(v);
     uint32_t b = __float_as_uint(v);
-    b = (b + (mix32(key) & 0x1fffu)) & ~0x1fffu;
+    b = (b + dither) & ~0x1fffu;
     return _Float16(__uint_as_float(b));
+}
+
+// The dither of element idx in a step with salt s (a lowbias32 hash of the
+// step number): the top 13 bits of (idx xor s) times the 32-bit golden-ratio
+// constant (Knuth's multiplicative hashing).  For every element it is uniform
+// over steps (xor with a uniform salt, then a bijection of the 32-bit words);
+// within a step, neighbouring elements get golden-ratio-spaced values.  Runs
+// are reproducible.  One integer multiply per value: the full lowbias32 mix
+// per value cost three, and made the FP16 step arithmetic-bound.
+__device__ __forceinline__ uint32_t sr_dither(long long idx, uint32_t salt) {
+    return (((uint32_t)idx ^ salt) * 0x9e3779b9u) >> 19;
 }
 
 template <bool NT = false, class S, class T>
 __device__ __forceinline__ void st(S* base, long long idx, T v, const KParams<T>& kp, bool fluid, uint32_t salt) {
     if constexpr (St<S>::scaled)
-        store_raw<NT>(to_half_sr(v * (fluid ? kp.scale_h : kp.scale), (uint32_t)idx * 0x9e3779b9u ^ salt), base + idx);
+        store_raw<NT>(to_half_sr(v * (fluid ? kp.scale_h : kp.scale), sr_dither(idx, salt)), base + idx);
     else
         store_raw<NT>(S(v), base + idx);
 }
