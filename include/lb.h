@@ -86,7 +86,8 @@ enum { LB_SBC_PERIODIC = 0, LB_SBC_NOFLUX = 1 /* half-way bounce-back */,
        LB_SBC_DIRICHLET = 2 /* anti-bounce-back, value wall[side][a] */ };
 
 typedef struct lb_params {
-    int32_t nx, ny;              /* grid, each >= 2 */
+    int32_t nx, ny;              /* grid, each >= 2, nx ny < 2^31 and (nx + 64)(9 + 5m) < 2^31
+                                    (LB_EINVAL otherwise) */
     int32_t m;                   /* number of scalars, 1..4 (2 for the chemotaxis model) */
     int32_t model;               /* LB_MODEL_* */
     int32_t storage;             /* LB_STORE_* */

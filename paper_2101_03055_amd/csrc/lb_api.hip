@@ -207,6 +207,9 @@ lb_status validate(const lb_params* p) {
     if (p->nx < 2 || p->ny < 2) return fail(LB_EINVAL, "grid %d x %d: each side must be >= 2", p->nx, p->ny);
     if ((long long)p->nx * p->ny > (1ll << 31) - 1) return fail(LB_EINVAL, "grid too large");
     if (p->m < 1 || p->m > LB_MAX_M) return fail(LB_EINVAL, "m = %d outside 1..%d", p->m, LB_MAX_M);
+    // neighbour offsets within a row are formed in 32-bit arithmetic
+    if (((long long)p->nx + 64) * (9 + 5 * p->m) > (1ll << 31) - 1)
+        return fail(LB_EINVAL, "grid %d wide: (nx + 64) (9 + 5m) must stay below 2^31", p->nx);
     if (p->model != LB_MODEL_LINEAR && p->model != LB_MODEL_CHEMOTAXIS && p->model != LB_MODEL_CDE)
         return fail(LB_EINVAL, "unknown model");
     if (p->model == LB_MODEL_CDE) {

@@ -106,24 +106,26 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // binary16 with stochastic rounding: adding uniform random bits below the 10
 // kept mantissa bits to the magnitude and truncating rounds up with
 // probability equal to the discarded fraction, so increments smaller than
-// half an ulp survive in expectation.  Values below the binary16 normal range
-// fall back to round-to-nearest.  dither: 13 random bits.
-__device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t dither) {
-    if (!(fabsf(v) >= 6.103515625e-05f) || !(fabsf(v) < 65504.0f)) return _Float16(v);
-    uint32_t b = __float_as_uint(v);
-    b = (b + dither) & ~0x1fffu;
-    return _Float16(__uint_as_float(b));
+// half an ulp survive in expectation.  gfx950 does this in one instruction
+// (v_cvt_sr_f16_f32), which takes the top 13 bits of its 32-bit random word as
+// the dither (checked on the GPU against the add-and-truncate definition: equal
+// on every binary16-normal value; subnormal results are dithered too).
+__device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t rnd) {
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t z = {_Float16(0), _Float16(0)};
+    return __builtin_amdgcn_cvt_sr_f16_f32(z, v, rnd, false)[0];
 }
 
-// The dither of element idx in a step with salt s (a lowbias32 hash of the
-// step number): the top 13 bits of (idx xor s) times the 32-bit golden-ratio
-// constant (Knuth's multiplicative hashing).  For every element it is uniform
-// over steps (xor with a uniform salt, then a bijection of the 32-bit words);
-// within a step, neighbouring elements get golden-ratio-spaced values.  Runs
-// are reproducible.  One integer multiply per value: the full lowbias32 mix
-// per value cost three, and made the FP16 step arithmetic-bound.
+// The random word of element idx in a step with salt s (a lowbias32 hash of
+// the step number): (idx xor s) times the 32-bit golden-ratio constant
+// (Knuth's multiplicative hashing), whose top bits serve as the dither.  For
+// every element it is uniform over steps (xor with a uniform salt, then a
+// bijection of the 32-bit words); within a step, neighbouring elements get
+// golden-ratio-spaced values.  Runs are reproducible.  One integer multiply
+// per value: the full lowbias32 mix per value cost three, and made the FP16
+// step arithmetic-bound.
 __device__ __forceinline__ uint32_t sr_dither(long long idx, uint32_t salt) {
-    return (((uint32_t)idx ^ salt) * 0x9e3779b9u) >> 19;
+    return ((uint32_t)idx ^ salt) * 0x9e3779b9u;
 }
 
 template <bool NT = false, class S, class T>
@@ -160,7 +162,7 @@ constexpr int kBlkShift = 6;
 constexpr int kBlk = 1 << kBlkShift;
 
 template <int M>
-__device__ __forceinline__ long long pidx(int q, long long n) {
+__host__ __device__ __forceinline__ long long pidx(int q, long long n) {
     constexpr int NQ = 9 + 5 * M;
     // node part first, population part last: the node part is shared by all
     // populations of a node and the population part folds into the load offset
@@ -182,7 +184,7 @@ struct Nbr {
     long long row[3];
     int col[3];
     template <class T>
-    __device__ __forceinline__ Nbr(const KParams<T>& kp, int x, int y) {
+    __host__ __device__ __forceinline__ Nbr(const KParams<T>& kp, int x, int y) {
         const int nx = kp.nx, ny = kp.ny;
         const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
         row[0] = (long long)ym * nx;
@@ -192,7 +194,47 @@ struct Nbr {
         col[1] = x;
         col[2] = x == nx - 1 ? 0 : x + 1;
     }
-    __device__ __forceinline__ long long at(int dx, int dy) const { return row[dy + 1] + col[dx + 1]; }
+    __host__ __device__ __forceinline__ long long at(int dx, int dy) const { return row[dy + 1] + col[dx + 1]; }
+};
+
+// Element offsets (population 0) of the 3 x 3 neighbourhood of (x, y) in the
+// blocked layout, wrapped on periodic axes; valid for nodes with
+// no_wall_link(), and for the node itself and its in-domain neighbours
+// otherwise.  Same value as pidx<M>(0, n') for the neighbour n', computed
+// with 32-bit node arithmetic: for the first node R of a row, the neighbour
+// R + c lies in block (R >> 6) + ((R & 63) + c) >> 6 at lane ((R & 63) + c) & 63,
+// so one 64-bit product per row ((R >> 6) times the block size) and a 24-bit
+// product per neighbour replace a 64-bit multiply per neighbour.  Needs
+// nx * ny < 2^31 and nx * (9 + 5m) + 64 (9 + 5m) < 2^31 (checked by the host).
+template <int M>
+struct NbrE {
+    static constexpr int Q = (9 + 5 * M) << kBlkShift;  // values per block
+    long long rb[3];  // rows y - 1, y, y + 1: element offset of the block holding the row's first node
+    int rm[3];        // lane of the row's first node in that block
+    int col[3];       // columns x - 1, x, x + 1
+    template <class T>
+    __host__ __device__ __forceinline__ NbrE(const KParams<T>& kp, int x, int y) {
+        const int nx = kp.nx, ny = kp.ny;
+        const int r1 = y * nx;
+        const int r0 = y == 0 ? (ny - 1) * nx : r1 - nx;
+        const int r2 = y == ny - 1 ? 0 : r1 + nx;
+        rb[0] = (long long)(r0 >> kBlkShift) * Q;
+        rb[1] = (long long)(r1 >> kBlkShift) * Q;
+        rb[2] = (long long)(r2 >> kBlkShift) * Q;
+        rm[0] = r0 & (kBlk - 1);
+        rm[1] = r1 & (kBlk - 1);
+        rm[2] = r2 & (kBlk - 1);
+        col[0] = x == 0 ? nx - 1 : x - 1;
+        col[1] = x;
+        col[2] = x == nx - 1 ? 0 : x + 1;
+    }
+    __host__ __device__ __forceinline__ long long at(int dx, int dy) const {
+        const int t = rm[dy + 1] + col[dx + 1];
+        // both factors below 2^24 (masks are no-ops under the host's limits): a
+        // full-rate 24-bit multiply on the GPU
+        const unsigned blk = (unsigned)(t >> kBlkShift) & 0xffffffu;
+        return rb[dy + 1] + (long long)(blk * (unsigned)Q + (unsigned)(t & (kBlk - 1)));
+    }
 };
 
 // walls next to node (x, y): out_x(d) is true when x + d (d in -1, 0, 1) lies
@@ -225,21 +267,21 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
-            Nbr nb(kp, x, y);
+            const NbrE<M> nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) h[i] = ld<NT>(pop + pidx<M>(OPP9[i], nb.at(-CX9[i], -CY9[i])), kp, true);
+            for (int i = 0; i < 9; ++i) h[i] = ld<NT>(pop + nb.at(-CX9[i], -CY9[i]) + ((long long)(OPP9[i]) << kBlkShift), kp, true);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    f[a][i] = ld<NT>(pop + pidx<M>((9 + 5 * a + OPP5[i]), nb.at(-CX5[i], -CY5[i])), kp, false);
+                    f[a][i] = ld<NT>(pop + nb.at(-CX5[i], -CY5[i]) + ((long long)(9 + 5 * a + OPP5[i]) << kBlkShift), kp, false);
             return;
         }
         // nodes next to a wall: every link resolved with selects (no load in a
         // divergent branch); wall rules by side: bounce-back, specular
         // reflection (free slip), anti-bounce-back (Dirichlet scalars)
         const WallFlags wf(kp, x, y);
-        Nbr nb(kp, x, y);
+        const NbrE<M> nb(kp, x, y);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const int cx = CX9[i], cy = CY9[i];
@@ -247,7 +289,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
             long long src = nb.at(-cx, -cy);
             int pl = OPP9[i];
             if (ox || oy) {
-                src = n;  // bounce-back: the node's own reflected value (also corners)
+                src = nb.at(0, 0);  // bounce-back: the node's own reflected value (also corners)
                 pl = i;
                 if (ox != oy && kp.fbc[ox ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3)] == LB_BC_FREESLIP) {
                     if (oy) {  // specular across a y-wall: from (x - c_x, y), direction mirrored
@@ -259,7 +301,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                     }
                 }
             }
-            h[i] = ld<NT>(pop + pidx<M>(pl, src), kp, true);
+            h[i] = ld<NT>(pop + src + ((long long)(pl) << kBlkShift), kp, true);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -268,8 +310,8 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                 const int cx = CX5[i], cy = CY5[i];
                 const bool out = wf.out_x(-cx) || wf.out_y(-cy);
                 const int side = wf.out_x(-cx) ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3);
-                const long long src = out ? n : nb.at(-cx, -cy);
-                const T v = ld<NT>(pop + pidx<M>(9 + 5 * a + (out ? i : OPP5[i]), src), kp, false);
+                const long long src = out ? nb.at(0, 0) : nb.at(-cx, -cy);
+                const T v = ld<NT>(pop + src + ((long long)(9 + 5 * a + (out ? i : OPP5[i])) << kBlkShift), kp, false);
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 f[a][i] = dir ? -v + T(2) * w5<T>(i) * kp.wallr[side][a] : v;
             }
@@ -294,18 +336,18 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
-            Nbr nb(kp, x, y);
+            const NbrE<M> nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st<NT>(pop, pidx<M>(i, nb.at(CX9[i], CY9[i])), h[i], kp, true, salt);
+            for (int i = 0; i < 9; ++i) st<NT>(pop, nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), h[i], kp, true, salt);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    st<NT>(pop, pidx<M>((9 + 5 * a + i), nb.at(CX5[i], CY5[i])), f[a][i], kp, false, salt);
+                    st<NT>(pop, nb.at(CX5[i], CY5[i]) + ((long long)(9 + 5 * a + i) << kBlkShift), f[a][i], kp, false, salt);
             return;
         }
         const WallFlags wf(kp, x, y);
-        Nbr nb(kp, x, y);
+        const NbrE<M> nb(kp, x, y);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const int cx = CX9[i], cy = CY9[i];
@@ -313,7 +355,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
             long long dst = nb.at(cx, cy);
             int pl = i;
             if (ox || oy) {
-                dst = n;  // bounce-back into the node's own opposite slot (also corners)
+                dst = nb.at(0, 0);  // bounce-back into the node's own opposite slot (also corners)
                 pl = OPP9[i];
                 if (ox != oy && kp.fbc[ox ? (cx > 0 ? 1 : 0) : (cy > 0 ? 3 : 2)] == LB_BC_FREESLIP) {
                     if (oy) {
@@ -325,7 +367,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     }
                 }
             }
-            st<NT>(pop, pidx<M>(pl, dst), h[i], kp, true, salt);
+            st<NT>(pop, dst + ((long long)(pl) << kBlkShift), h[i], kp, true, salt);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -336,8 +378,8 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                 const int side = wf.out_x(cx) ? (cx > 0 ? 1 : 0) : (cy > 0 ? 3 : 2);
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 const T v = dir ? -f[a][i] + T(2) * w5<T>(i) * kp.wallr[side][a] : f[a][i];
-                const long long dst = out ? n : nb.at(cx, cy);
-                st<NT>(pop, pidx<M>(9 + 5 * a + (out ? OPP5[i] : i), dst), v, kp, false, salt);
+                const long long dst = out ? nb.at(0, 0) : nb.at(cx, cy);
+                st<NT>(pop, dst + ((long long)(9 + 5 * a + (out ? OPP5[i] : i)) << kBlkShift), v, kp, false, salt);
             }
     }
 }
