@@ -118,12 +118,11 @@ __device__ __forceinline__ _Float16 to_half_sr(float v, uint32_t rnd) {
 
 // The random word of element idx in a step with salt s (a lowbias32 hash of
 // the step number): (idx xor s) times the 32-bit golden-ratio constant
-// (Knuth's multiplicative hashing), whose top bits serve as the dither.  For
-// every element it is uniform over steps (xor with a uniform salt, then a
-// bijection of the 32-bit words); within a step, neighbouring elements get
-// golden-ratio-spaced values.  Runs are reproducible.  One integer multiply
-// per value: the full lowbias32 mix per value cost three, and made the FP16
-// step arithmetic-bound.
+// (Knuth's multiplicative hashing), whose top bits serve as the dither; used
+// by the set-up kernels and the two-steps-per-launch kernel (the single-step
+// kernels use the per-node words of sr_node below).  Uniform over steps for
+// every element (xor with a uniform salt, then a bijection of the 32-bit
+// words); reproducible.
 __device__ __forceinline__ uint32_t sr_dither(long long idx, uint32_t salt) {
     return ((uint32_t)idx ^ salt) * 0x9e3779b9u;
 }
@@ -134,6 +133,28 @@ __device__ __forceinline__ void st(S* base, long long idx, T v, const KParams<T>
         store_raw<NT>(to_half_sr(v * (fluid ? kp.scale_h : kp.scale), sr_dither(idx, salt)), base + idx);
     else
         store_raw<NT>(S(v), base + idx);
+}
+
+// The random words of the values a node stores in a step with salt s: value q
+// of node n takes (32 n + q + s) times the golden-ratio constant, i.e. one
+// multiply per node and one add per value (an integer multiply per value
+// was a sixth of the FP16 step's issue time).  Within a step the words of
+// distinct values are distinct terms of the golden-ratio (Weyl) sequence, so
+// their top bits are evenly spread; over steps each word is uniform (the salt
+// is a hash of the step number and multiplication by an odd constant is a
+// bijection).  Runs are reproducible.
+__device__ __forceinline__ uint32_t sr_node(long long n, uint32_t salt) {
+    return ((uint32_t)n * 32u + salt) * 0x9e3779b9u;
+}
+__device__ __forceinline__ uint32_t sr_word(uint32_t node_word, int q) { return node_word + (uint32_t)q * 0x9e3779b9u; }
+
+// store of one population value; rnd is the stochastic-rounding word (FP16)
+template <bool NT = false, class S, class T>
+__device__ __forceinline__ void st_r(S* p, T v, const KParams<T>& kp, bool fluid, uint32_t rnd) {
+    if constexpr (St<S>::scaled)
+        store_raw<NT>(to_half_sr(v * (fluid ? kp.scale_h : kp.scale), rnd), p);
+    else
+        store_raw<NT>(S(v), p);
 }
 
 // ---- geometry helpers -------------------------------------------------------
@@ -326,24 +347,26 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                                         const T h[9], const T f[M][5], uint32_t salt) {
     const int nx = kp.nx;
     const long long n = (long long)y * nx + x;
+    const uint32_t rw = sr_node(n, salt);  // FP16 only: random words of this node's values
     if constexpr (!PUSH) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st<NT>(pop, pidx<M>(OPP9[i], n), h[i], kp, true, salt);
+        for (int i = 0; i < 9; ++i) st_r<NT>(pop + pidx<M>(OPP9[i], n), h[i], kp, true, sr_word(rw, i));
 #pragma unroll
         for (int a = 0; a < M; ++a)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) st<NT>(pop, pidx<M>((9 + 5 * a + OPP5[i]), n), f[a][i], kp, false, salt);
+            for (int i = 0; i < 5; ++i) st_r<NT>(pop + pidx<M>((9 + 5 * a + OPP5[i]), n), f[a][i], kp, false, sr_word(rw, 9 + 5 * a + i));
         return;
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             const NbrE<M> nb(kp, x, y);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st<NT>(pop, nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), h[i], kp, true, salt);
+            for (int i = 0; i < 9; ++i) st_r<NT>(pop + nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), h[i], kp, true, sr_word(rw, i));
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
-                    st<NT>(pop, nb.at(CX5[i], CY5[i]) + ((long long)(9 + 5 * a + i) << kBlkShift), f[a][i], kp, false, salt);
+                    st_r<NT>(pop + nb.at(CX5[i], CY5[i]) + ((long long)(9 + 5 * a + i) << kBlkShift), f[a][i], kp, false,
+                         sr_word(rw, 9 + 5 * a + i));
             return;
         }
         const WallFlags wf(kp, x, y);
@@ -367,7 +390,7 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     }
                 }
             }
-            st<NT>(pop, dst + ((long long)(pl) << kBlkShift), h[i], kp, true, salt);
+            st_r<NT>(pop + dst + ((long long)(pl) << kBlkShift), h[i], kp, true, sr_word(rw, i));
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -379,7 +402,8 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 const T v = dir ? -f[a][i] + T(2) * w5<T>(i) * kp.wallr[side][a] : f[a][i];
                 const long long dst = out ? nb.at(0, 0) : nb.at(cx, cy);
-                st<NT>(pop, dst + ((long long)(9 + 5 * a + (out ? OPP5[i] : i)) << kBlkShift), v, kp, false, salt);
+                st_r<NT>(pop + dst + ((long long)(9 + 5 * a + (out ? OPP5[i] : i)) << kBlkShift), v, kp, false,
+                        sr_word(rw, 9 + 5 * a + i));
             }
     }
 }
@@ -503,7 +527,12 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
     // remainder, f^eq_0 = phid - sum_{i>0} f^eq_i (and likewise for W_i S):
     // with rounded weights sum_i W_i != 1, which would create or destroy mass
     // by the same fraction at every step.
-    T feq[M][5], wsrc[M][5];
+    // The non-equilibrium part f - f^eq is formed first (with omega close to 2
+    // the expanded (1 - omega) f + omega f^eq loses accuracy in FP32); the
+    // source and auxiliary-source terms are node constants per species and
+    // direction, W_i src_a + 3 W_i c_i . g_a = src_a/6 +- g_a,x/2 or +- g_a,y/2
+    // on the moving directions.
+    T feq[M][5], add[M][5];
 #pragma unroll
     for (int b = 0; b < M; ++b) {
         T pd = mc.phid[b];
@@ -517,22 +546,24 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
         feq[b][4] = iso - adv * mc.u[1];
         feq[b][0] = mc.phid[b] - T(4) * iso;
         const T s6 = src[b] * (T(1) / T(6));
-        wsrc[b][1] = wsrc[b][2] = wsrc[b][3] = wsrc[b][4] = s6;
-        wsrc[b][0] = src[b] - T(4) * s6;
+        const T gx = T(0.5) * g[b][0], gy = T(0.5) * g[b][1];
+        add[b][1] = s6 + gx;
+        add[b][3] = s6 - gx;
+        add[b][2] = s6 + gy;
+        add[b][4] = s6 - gy;
+        add[b][0] = src[b] - T(4) * s6;
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const T wi = w5<T>(i);
         T neq[M];
 #pragma unroll
         for (int b = 0; b < M; ++b) neq[b] = f[b][i] - feq[b][i];
 #pragma unroll
         for (int a = 0; a < M; ++a) {
-            T coll = T(0);
+            T acc = f[a][i] + add[a][i];
 #pragma unroll
-            for (int b = 0; b < M; ++b) coll += om[a][b] * neq[b];
-            const T cg = T(CX5[i]) * g[a][0] + T(CY5[i]) * g[a][1];
-            f[a][i] = f[a][i] - coll + wsrc[a][i] + T(3) * wi * cg;
+            for (int b = 0; b < M; ++b) acc -= om[a][b] * neq[b];
+            f[a][i] = acc;
         }
     }
 
