@@ -97,13 +97,14 @@ def kernel_time(step_fn, stream, launches):
     return e0.elapsed_time(e1) / 1e3 / launches
 
 
-def cpu_baseline(wl, phi0, u0, p0, budget_s=12.0):
+def cpu_baseline(wl, phi0, u0, p0, budget_s=15.0):
     from oracle import oracle as O
 
     o = O.Oracle(wl, phi0, u0, p0)
+    o.step(5)  # thread start-up, first touch
     t0 = time.perf_counter()
-    o.step(2)
-    dt = max(time.perf_counter() - t0, 1e-6) / 2
+    o.step(20)
+    dt = max(time.perf_counter() - t0, 1e-6) / 20
     steps = max(2, int(budget_s / dt))
     t0 = time.perf_counter()
     o.step(steps)

@@ -87,8 +87,8 @@ __device__ __forceinline__ void store_raw(S v, S* p) {
 
 template <bool NT = false, class S, class T>
 __device__ __forceinline__ T ld(const S* p, const KParams<T>& kp, bool fluid) {
-    if constexpr (St<S>::scaled)
-        return T(load_raw<NT>(p)) * (fluid ? kp.inv_scale_h : kp.inv_scale);
+    if constexpr (St<S>::scaled)  // fma with a zero addend: one mixed-precision fma (f16 operand) on gfx950
+        return __builtin_fmaf(T(load_raw<NT>(p)), fluid ? kp.inv_scale_h : kp.inv_scale, T(0));
     else
         return T(load_raw<NT>(p));
 }
@@ -477,7 +477,11 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
         const T b = T(3) * (kp.Dc[1] - kp.chi * r * mc.phi[0]);
         const T c = T(3) * kp.Dc[2];
         const T d = T(3) * kp.Dc[3] + T(0.5);
-        const T idet = T(1) / (a * d - b * c);
+        T idet;
+        if constexpr (std::is_same_v<T, float>)
+            idet = __builtin_amdgcn_rcpf(a * d - b * c);  // 1-ulp reciprocal: the FP32 paths carry ~1e-7 anyway
+        else
+            idet = T(1) / (a * d - b * c);
         om[0][0] = d * idet;
         om[0][1] = -b * idet;
         om[1][0] = -c * idet;
