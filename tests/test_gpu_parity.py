@@ -139,11 +139,13 @@ def test_mrt(oracle_mod, seed):
 
 
 def test_chemotaxis_plume_full_size(oracle_mod):
-    """512 x 256 plume workload at its full size (oracle on all host cores)."""
+    """512 x 256 plume workload at its full size, 1000 steps (the GPU side
+    through its replayed step graphs and default tiles, as benchmarked; the
+    oracle on all host cores)."""
     wl, phi0, u0, p0 = W.chemotaxis_plume()
-    o, g = run_pair(oracle_mod, wl, phi0, u0, p0, 200)
+    o, g = run_pair(oracle_mod, wl, phi0, u0, p0, 1000)
     ef, eh = pop_errors(o, g)
-    print(f"plume 512x256 200 steps: f {ef:.2e} h {eh:.2e}", flush=True)
+    print(f"plume 512x256 1000 steps: f {ef:.2e} h {eh:.2e}", flush=True)
     assert ef <= TOL64 and eh <= TOL64
     assert moment_errors(o, g) <= TOL64
 
