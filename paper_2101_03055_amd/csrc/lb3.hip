@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/lb3.h"
+#include "lb3_index.h"
 #include "lb_device.h"
 
 namespace lb3k {
@@ -61,35 +62,6 @@ struct K3 {
     T F0[3];
     T Fphi[LB_MAX_M][3];
     T phi_ref[LB_MAX_M];
-};
-
-constexpr int kBlk = 64;
-template <int M>
-__device__ __forceinline__ long long p3(int q, long long n) {
-    constexpr int NQ = 19 + 7 * M;
-    return ((n >> 6) * (NQ << 6) + (n & (kBlk - 1))) + ((long long)q << 6);
-}
-
-// 3 x 3 x 3 neighbourhood, wrapped on periodic axes (on a walled axis the
-// wrapped index is never used: links through a wall take the node itself)
-struct Nb3 {
-    long long xo[3], yo[3], zo[3];
-    template <class T>
-    __device__ __forceinline__ Nb3(const K3<T>& kp, int x, int y, int z) {
-        const long long sx = 1, sy = kp.nx, sz = (long long)kp.nx * kp.ny;
-        xo[0] = (x == 0 ? kp.nx - 1 : x - 1) * sx;
-        xo[1] = x * sx;
-        xo[2] = (x == kp.nx - 1 ? 0 : x + 1) * sx;
-        yo[0] = (y == 0 ? kp.ny - 1 : y - 1) * sy;
-        yo[1] = y * sy;
-        yo[2] = (y == kp.ny - 1 ? 0 : y + 1) * sy;
-        zo[0] = (z == 0 ? kp.nz - 1 : z - 1) * sz;
-        zo[1] = z * sz;
-        zo[2] = (z == kp.nz - 1 ? 0 : z + 1) * sz;
-    }
-    __device__ __forceinline__ long long at(int dx, int dy, int dz) const {
-        return zo[dz + 1] + yo[dy + 1] + xo[dx + 1];
-    }
 };
 
 struct Walls3 {
@@ -136,16 +108,16 @@ __device__ __forceinline__ void gather3(const K3<T>& kp, const S* __restrict__ p
 #pragma unroll
             for (int i = 0; i < 7; ++i) f[a][i] = ld3<NT, S, T>(pop + p3<M>(19 + 7 * a + i, n));
     } else {
-        const Nb3 nb(kp, x, y, z);
+        const Nb3E<M> nb(kp, x, y, z);
         if (__all(interior(kp, x, y, z))) {
 #pragma unroll
             for (int i = 0; i < 19; ++i)
-                h[i] = ld3<NT, S, T>(pop + p3<M>(OPP19[i], nb.at(-CX19[i], -CY19[i], -CZ19[i])));
+                h[i] = ld3<NT, S, T>(pop + nb.at(-CX19[i], -CY19[i], -CZ19[i]) + ((long long)(OPP19[i]) << 6));
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
-                    f[a][i] = ld3<NT, S, T>(pop + p3<M>(19 + 7 * a + OPP7[i], nb.at(-CX7[i], -CY7[i], -CZ7[i])));
+                    f[a][i] = ld3<NT, S, T>(pop + nb.at(-CX7[i], -CY7[i], -CZ7[i]) + ((long long)(19 + 7 * a + OPP7[i]) << 6));
             return;
         }
         const Walls3 w(kp, x, y, z);
@@ -154,8 +126,8 @@ __device__ __forceinline__ void gather3(const K3<T>& kp, const S* __restrict__ p
             // the upstream node x - c_i beyond a wall (face or edge): bounce-back,
             // the node's own value of direction opp(i), kept in its slot i
             const bool out = w.out(0, -CX19[i]) || w.out(1, -CY19[i]) || w.out(2, -CZ19[i]);
-            const long long src = out ? n : nb.at(-CX19[i], -CY19[i], -CZ19[i]);
-            h[i] = ld3<NT, S, T>(pop + p3<M>(out ? i : OPP19[i], src));
+            const long long src = out ? nb.at(0, 0, 0) : nb.at(-CX19[i], -CY19[i], -CZ19[i]);
+            h[i] = ld3<NT, S, T>(pop + src + ((long long)(out ? i : OPP19[i]) << 6));
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -165,8 +137,8 @@ __device__ __forceinline__ void gather3(const K3<T>& kp, const S* __restrict__ p
                 const bool ox = w.out(0, -cx), oy = w.out(1, -cy), oz = w.out(2, -cz);
                 const bool out = ox || oy || oz;
                 const int side = ox ? (cx > 0 ? 0 : 1) : (oy ? (cy > 0 ? 2 : 3) : (cz > 0 ? 4 : 5));
-                const long long src = out ? n : nb.at(-cx, -cy, -cz);
-                const T v = ld3<NT, S, T>(pop + p3<M>(19 + 7 * a + (out ? i : OPP7[i]), src));
+                const long long src = out ? nb.at(0, 0, 0) : nb.at(-cx, -cy, -cz);
+                const T v = ld3<NT, S, T>(pop + src + ((long long)(19 + 7 * a + (out ? i : OPP7[i])) << 6));
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 f[a][i] = dir ? -v + T(0.25) * kp.wallr[side][a] : v;  // 2 W_i phi_w, W_i = 1/8
             }
@@ -185,22 +157,22 @@ __device__ __forceinline__ void scatter3(const K3<T>& kp, S* __restrict__ pop, i
 #pragma unroll
             for (int i = 0; i < 7; ++i) st3<NT>(pop + p3<M>(19 + 7 * a + OPP7[i], n), f[a][i]);
     } else {
-        const Nb3 nb(kp, x, y, z);
+        const Nb3E<M> nb(kp, x, y, z);
         if (__all(interior(kp, x, y, z))) {
 #pragma unroll
-            for (int i = 0; i < 19; ++i) st3<NT>(pop + p3<M>(i, nb.at(CX19[i], CY19[i], CZ19[i])), h[i]);
+            for (int i = 0; i < 19; ++i) st3<NT>(pop + nb.at(CX19[i], CY19[i], CZ19[i]) + ((long long)(i) << 6), h[i]);
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
-                for (int i = 0; i < 7; ++i) st3<NT>(pop + p3<M>(19 + 7 * a + i, nb.at(CX7[i], CY7[i], CZ7[i])), f[a][i]);
+                for (int i = 0; i < 7; ++i) st3<NT>(pop + nb.at(CX7[i], CY7[i], CZ7[i]) + ((long long)(19 + 7 * a + i) << 6), f[a][i]);
             return;
         }
         const Walls3 w(kp, x, y, z);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const bool out = w.out(0, CX19[i]) || w.out(1, CY19[i]) || w.out(2, CZ19[i]);
-            const long long dst = out ? n : nb.at(CX19[i], CY19[i], CZ19[i]);
-            st3<NT>(pop + p3<M>(out ? OPP19[i] : i, dst), h[i]);
+            const long long dst = out ? nb.at(0, 0, 0) : nb.at(CX19[i], CY19[i], CZ19[i]);
+            st3<NT>(pop + dst + ((long long)(out ? OPP19[i] : i) << 6), h[i]);
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -212,8 +184,8 @@ __device__ __forceinline__ void scatter3(const K3<T>& kp, S* __restrict__ pop, i
                 const int side = ox ? (cx > 0 ? 1 : 0) : (oy ? (cy > 0 ? 3 : 2) : (cz > 0 ? 5 : 4));
                 const bool dir = out && kp.sbc[side][a] == LB_SBC_DIRICHLET;
                 const T v = dir ? -f[a][i] + T(0.25) * kp.wallr[side][a] : f[a][i];
-                const long long dst = out ? n : nb.at(cx, cy, cz);
-                st3<NT>(pop + p3<M>(19 + 7 * a + (out ? OPP7[i] : i), dst), v);
+                const long long dst = out ? nb.at(0, 0, 0) : nb.at(cx, cy, cz);
+                st3<NT>(pop + dst + ((long long)(19 + 7 * a + (out ? OPP7[i] : i)) << 6), v);
             }
     }
 }
@@ -639,6 +611,9 @@ lb_status validate3(const lb3_params* p) {
         return fail3(LB_EINVAL, "grid %d x %d x %d: each side must be >= 2", p->nx, p->ny, p->nz);
     if ((long long)p->nx * p->ny * p->nz > (1ll << 31) - 1) return fail3(LB_EINVAL, "grid too large");
     if (p->m < 1 || p->m > LB_MAX_M) return fail3(LB_EINVAL, "m = %d outside 1..%d", p->m, LB_MAX_M);
+    // neighbour offsets within a row are formed in 32-bit arithmetic
+    if (((long long)p->nx + 64) * (19 + 7 * p->m) > (1ll << 31) - 1)
+        return fail3(LB_EINVAL, "grid %d wide: (nx + 64) (19 + 7m) must stay below 2^31", p->nx);
     if (p->storage != LB_STORE_F64 && p->storage != LB_STORE_F32) return fail3(LB_EINVAL, "storage must be F64 or F32");
     if (!(p->tau_f > 0.5) || !std::isfinite(p->tau_f)) return fail3(LB_EINVAL, "tau_f = %g must be > 1/2", p->tau_f);
     if (!std::isfinite(p->rho0)) return fail3(LB_EINVAL, "rho0 not finite");

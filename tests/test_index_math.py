@@ -7,7 +7,8 @@ product per row); `tests/native/nbr_check.hip` compiles the same device
 header for the host and compares every offset with the plain 64-bit index of
 the wrapped neighbour node, on ragged grids (all nodes), a 4096^2 grid, the
 largest grid and the widest grid the library accepts (edge rows and columns),
-for m = 1..4.  The limits themselves are checked through lb_init validation.
+for m = 1..4; likewise the 3-D path's offsets (ragged boxes, 256^3, the
+largest and the widest boxes).  The limits themselves are checked through lb_init validation.
 """
 import os
 import shutil
@@ -39,6 +40,7 @@ def test_neighbour_offsets_match_blocked_index(tmp_path):
     assert out.returncode == 0, out.stdout[-2000:]
     assert "all neighbour offsets agree" in out.stdout
     assert out.stdout.count("ok M=") == 4 * 13
+    assert out.stdout.count("ok 3-D M=") == 4 * 10
 
 
 @pytest.mark.parametrize("m,nx,ok", [(2, 2 ** 31 // 19 - 64 - 1, True), (2, 2 ** 31 // 19 - 64 + 1, False),
