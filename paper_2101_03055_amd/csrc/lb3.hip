@@ -226,8 +226,21 @@ __device__ __forceinline__ void macro3(const K3<T>& kp, const T h[19], const T f
 }
 
 // ---- the node update: Eqs. evolution12 (D3Q7) and evolution3 (D3Q19, BGK) -------
-template <class T, int M>
+// CONS (FP32 storage): the scalar rest populations take the remainder of
+// each species' post-collision mass in FP64 (sum_i f*_a,i = sum_i f_a,i + src_a
+// up to one final rounding), as in the 2-D kernels.
+template <class T, int M, bool CONS = false>
 __device__ __forceinline__ void collide3(const K3<T>& kp, T h[19], T f[M][7], const T Sold[M], T Snew[M]) {
+    double mass_in[M];
+    if constexpr (CONS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) s += (double)f[a][i];
+            mass_in[a] = s;
+        }
+    }
     Mac3<T, M> mc;
     macro3<T, M>(kp, h, f, mc);
     T S[M];
@@ -254,7 +267,7 @@ __device__ __forceinline__ void collide3(const K3<T>& kp, T h[19], T f[M][7], co
     }
     // f^eq (Eq. feq-phi, lambda = I, vartheta = 0) in deviation form: W_i (phid + 4 phi c.u);
     // the rest direction takes the remainder so that mass is exact
-    T feq[M][7], wsrc[M][7];
+    T feq[M][7], wsrc[M][7], srcv[M];
 #pragma unroll
     for (int b = 0; b < M; ++b) {
         const T iso = mc.phid[b] * T(0.125);
@@ -267,6 +280,7 @@ __device__ __forceinline__ void collide3(const K3<T>& kp, T h[19], T f[M][7], co
         feq[b][6] = iso - adv * mc.u[2];
         feq[b][0] = mc.phid[b] - T(6) * iso;
         const T src = T(1.5) * S[b] - T(0.5) * Sold[b];  // dt S_i + (dt/2)(S_i - S_i(t - dt)) over W_i
+        srcv[b] = src;
         Snew[b] = S[b];
         const T s8 = src * T(0.125);
 #pragma unroll
@@ -285,6 +299,15 @@ __device__ __forceinline__ void collide3(const K3<T>& kp, T h[19], T f[M][7], co
             for (int b = 0; b < M; ++b) coll += kp.omega[a * M + b] * neq[b];
             const T cg = T(CX7[i]) * g[a][0] + T(CY7[i]) * g[a][1] + T(CZ7[i]) * g[a][2];
             f[a][i] = f[a][i] - coll + wsrc[a][i] + T(0.5) * cg;
+        }
+    }
+    if constexpr (CONS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            double moving = 0.0;
+#pragma unroll
+            for (int i = 1; i < 7; ++i) moving += (double)f[a][i];
+            f[a][0] = T((mass_in[a] + (double)srcv[a]) - moving);
         }
     }
     // fluid: h^eq of Eq. heq (rest value by difference: sum_i h^eq = rho0), F_i = 3 W_i c.F
@@ -334,7 +357,7 @@ __global__ __launch_bounds__(256) void k3_step(K3<typename St<S>::T> kp, S* __re
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) So[a] = (kp.src_mask >> a & 1) ? load_raw<NT>(sold + (long long)(k++) * N + n) : T(0);
-    collide3<T, M>(kp, h, f, So, Sn);
+    collide3<T, M, std::is_same_v<S, float>>(kp, h, f, So, Sn);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)

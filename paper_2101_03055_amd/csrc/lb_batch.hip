@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>*
         Sold[a] = T(0);
         if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
-    collide<T, M, MODEL, COLL>(kp, h, f, Sold, Snew);
+    collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, Sold, Snew);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)

@@ -96,9 +96,17 @@ __device__ __forceinline__ void scatter_f(const KParams<T>& kp, S* __restrict__ 
 
 // one node: moments, linear source, Case 1 auxiliary source, matrix collision
 // (Eq. evolution12 with the linear equilibrium of Eq. feq-phi, deviation form)
-template <class T, int M>
+// CONS (FP32 storage): the rest populations take the remainder of each
+// species' post-collision mass in FP64 (as in the fluid model's collision).
+template <class T, int M, bool CONS = false>
 __device__ __forceinline__ void collide_cde(const KParams<T>& kp, T f[M][5], const T u[2], const T prevd[M],
                                             const T Sold[M], T phid[M], T Snew[M]) {
+    double mass_in[M];
+    if constexpr (CONS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            mass_in[a] = (((double)f[a][0] + (double)f[a][1]) + ((double)f[a][2] + (double)f[a][3])) + (double)f[a][4];
+    }
     T phi[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -161,6 +169,13 @@ __device__ __forceinline__ void collide_cde(const KParams<T>& kp, T f[M][5], con
             f[a][i] = f[a][i] - coll + wsrc[a][i] + T(3) * wi * cg;
         }
     }
+    if constexpr (CONS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const double moving = ((double)f[a][1] + (double)f[a][2]) + ((double)f[a][3] + (double)f[a][4]);
+            f[a][0] = T((mass_in[a] + (double)src[a]) - moving);
+        }
+    }
 }
 
 template <class S, int M, bool ODD, bool NT>
@@ -186,7 +201,7 @@ __global__ __launch_bounds__(256) void k_cde_step(KParams<typename St<S>::T> kp,
         Sold[a] = T(0);
         if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
-    collide_cde<T, M>(kp, f, u, prevd, Sold, phid, Snew);
+    collide_cde<T, M, std::is_same_v<S, float>>(kp, f, u, prevd, Sold, phid, Snew);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {

@@ -463,10 +463,18 @@ __device__ __forceinline__ T lam_excess(const KParams<T>& kp, const T phi[M], in
 }
 
 // ---- the node update ------------------------------------------------------
-template <class T, int M, int MODEL, int COLL>
+// CONS (FP32 storage): the scalar rest populations take the remainder of the
+// species' post-collision mass in FP64, see below.
+template <class T, int M, int MODEL, int COLL, bool CONS = false>
 __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5], const T Sold[M], T Snew[M]) {
     Macro<T, M> mc;
     macro<T, M>(kp, h, f, mc);
+    double mass_in[M];  // exact sums of the stored (FP32) input populations
+    if constexpr (CONS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            mass_in[a] = (((double)f[a][0] + (double)f[a][1]) + ((double)f[a][2] + (double)f[a][3])) + (double)f[a][4];
+    }
 
     // relaxation matrix, Eq. omega-D with lambda = I: omega = (3 D + I/2)^-1
     T om[M][M];
@@ -568,6 +576,20 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
 #pragma unroll
             for (int b = 0; b < M; ++b) acc -= om[a][b] * neq[b];
             f[a][i] = acc;
+        }
+    }
+    // In exact arithmetic the collision changes the mass of species a by its
+    // source only, sum_i f*_a,i = sum_i f_a,i + src_a.  Evaluated in FP32 its
+    // rounding errors are deterministic functions of smooth fields and add up
+    // coherently over nodes and steps (a slow systematic drift of the mass).
+    // With FP32 storage the rest population takes the remainder computed in
+    // FP64 from the stored inputs and the other four outputs, which are exact
+    // in FP64, so that the only error left is the final rounding of f*_0.
+    if constexpr (CONS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const double moving = ((double)f[a][1] + (double)f[a][2]) + ((double)f[a][3] + (double)f[a][4]);
+            f[a][0] = T((mass_in[a] + (double)src[a]) - moving);
         }
     }
 

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
         Sold[a] = T(0);
         if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
-    collide<T, M, MODEL, COLL>(kp, h, f, Sold, Snew);
+    collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, Sold, Snew);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_step2(KParams<typename St<S>::T> kp, co
             So[a] = T(0);
             if (kp.src_mask >> a & 1) So[a] = sold_src[(long long)(k++) * N + n];
         }
-        collide<T, M, MODEL, COLL>(kp, h, f, So, Sn);
+        collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, So, Sn);
 #pragma unroll
         for (int i = 0; i < 9; ++i) buf1[i * N1 + r] = h[i];
 #pragma unroll
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_step2(KParams<typename St<S>::T> kp, co
         lds_pull<T, M, NQ>(kp, buf1, G::RX, N1, lx, ly, ex1, h, f);
 #pragma unroll
         for (int a = 0; a < M; ++a) So[a] = sb[a * N1 + ly * G::RX + lx];
-        collide<T, M, MODEL, COLL>(kp, h, f, So, Sn);
+        collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, So, Sn);
 #pragma unroll
         for (int i = 0; i < 9; ++i) buf2[i * N2 + r] = h[i];
 #pragma unroll
