@@ -44,7 +44,15 @@ constexpr int kMaxC = 128;
 constexpr int kFeat = 15;
 constexpr int kSplit = 64;      // split-K factor of the weight gradient
 constexpr int kRed = 256;       // blocks of the first pass of small reductions
-constexpr int LDSK = 40;        // LDS row pitch in bf16 of the convolution tiles (32 + 8 pad, 16-byte aligned)
+constexpr int LDSK = 32;        // LDS row pitch in bf16 of the convolution tiles (32 channels, no pad)
+
+// Offset (bf16) of the 16-byte segment seg (8 channels) of row `row` in a
+// convolution tile: the segment index is XOR-swizzled with ((row >> 1) ^
+// (row >> 3)) & 3, so that the segment stores of two adjacent rows and the
+// MFMA operand reads (16 rows, one segment) spread over distinct LDS banks.
+__device__ __forceinline__ int tile_off(int row, int seg) {
+    return row * LDSK + (((seg ^ (row >> 1) ^ (row >> 3)) & 3) << 3);
+}
 
 // ---- features ------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_features(const float* __restrict__ params, const int* __restrict__ idx,
@@ -105,15 +113,15 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const 
         for (int c0 = 0; c0 < Cin; c0 += 32) {
             uint4 va = make_uint4(0u, 0u, 0u, 0u);
             if (in) va = *reinterpret_cast<const uint4*>(X + src + c0 + 8 * sq);
-            *reinterpret_cast<uint4*>(&As[sj * LDSK + 8 * sq]) = va;
-            *reinterpret_cast<uint4*>(&Bs[sj * LDSK + 8 * sq]) =
+            *reinterpret_cast<uint4*>(&As[tile_off(sj, sq)]) = va;
+            *reinterpret_cast<uint4*>(&Bs[tile_off(sj, sq)]) =
                 *reinterpret_cast<const uint4*>(Wk + wsrc + c0 + 8 * sq);
             __syncthreads();
-            const int r = lane & 15, kq = (lane >> 4) * 8;
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSK + kq]);
-            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSK + kq]);
-            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + r) * LDSK + kq]);
-            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + 16 + r) * LDSK + kq]);
+            const int r = lane & 15;
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[tile_off(wr + r, lane >> 4)]);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[tile_off(wr + 16 + r, lane >> 4)]);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[tile_off(wc + r, lane >> 4)]);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[tile_off(wc + 16 + r, lane >> 4)]);
             acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
@@ -180,17 +188,17 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
             uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = make_uint4(0u, 0u, 0u, 0u);
             if (ina) va = *reinterpret_cast<const uint4*>(X + srca + c0 + 8 * sq);
             if (inb) vb = *reinterpret_cast<const uint4*>(X + srcb + c0 + 8 * sq);
-            *reinterpret_cast<uint4*>(&As[sj * LDSK + 8 * sq]) = va;
-            *reinterpret_cast<uint4*>(&As[(sj + 64) * LDSK + 8 * sq]) = vb;
-            *reinterpret_cast<uint4*>(&Bs[sj * LDSK + 8 * sq]) =
+            *reinterpret_cast<uint4*>(&As[tile_off(sj, sq)]) = va;
+            *reinterpret_cast<uint4*>(&As[tile_off(sj + 64, sq)]) = vb;
+            *reinterpret_cast<uint4*>(&Bs[tile_off(sj, sq)]) =
                 *reinterpret_cast<const uint4*>(Wk + wsrc + c0 + 8 * sq);
             __syncthreads();
-            const int r = lane & 15, kq = (lane >> 4) * 8;
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSK + kq]);
-            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSK + kq]);
+            const int r = lane & 15;
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[tile_off(wr + r, lane >> 4)]);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[tile_off(wr + 16 + r, lane >> 4)]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[(16 * j + r) * LDSK + kq]);
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[tile_off(16 * j + r, lane >> 4)]);
                 acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][j], 0, 0, 0);
                 acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][j], 0, 0, 0);
             }
@@ -268,20 +276,27 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, cons
         const bf16* a1 = reinterpret_cast<const bf16*>(&va[1]);
         const bf16* b0 = reinterpret_cast<const bf16*>(&vb[0]);
         const bf16* b1 = reinterpret_cast<const bf16*>(&vb[1]);
+        // row 8 cg + e, pixel pair pp: its 8-pixel group pp / 4 is XOR-swizzled
+        // with the row's cg (rows 8 apart would otherwise share LDS banks)
+        const int col = ((((pp >> 2) ^ cg) & 7) << 3) | ((pp & 3) << 1);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            *reinterpret_cast<uint32_t*>(&As[(8 * cg + e) * LDSW + 2 * pp]) = pack_bf16x2(a0[e], a1[e]);
-            *reinterpret_cast<uint32_t*>(&Bs[(8 * cg + e) * LDSW + 2 * pp]) = pack_bf16x2(b0[e], b1[e]);
+            *reinterpret_cast<uint32_t*>(&As[(8 * cg + e) * LDSW + col]) = pack_bf16x2(a0[e], a1[e]);
+            *reinterpret_cast<uint32_t*>(&Bs[(8 * cg + e) * LDSW + col]) = pack_bf16x2(b0[e], b1[e]);
         }
         __syncthreads();
         if (c + 1 < c_end) load(c + 1);
         const int r = lane & 15, kq = (lane >> 4) * 8;
+        // the 8-pixel group (kk + kq) / 8 of row R sits at group ((kk + kq) / 8) ^ ((R / 8) & 7)
+        auto at = [&](const bf16* base, int R, int k) -> bf16x8 {
+            return *reinterpret_cast<const bf16x8*>(&base[R * LDSW + ((((k >> 3) ^ (R >> 3)) & 7) << 3)]);
+        };
 #pragma unroll
         for (int kk = 0; kk < 64; kk += 32) {
-            const bf16x8 x0 = *reinterpret_cast<const bf16x8*>(&As[(wr + r) * LDSW + kk + kq]);
-            const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(&As[(wr + 16 + r) * LDSW + kk + kq]);
-            const bf16x8 y0 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + r) * LDSW + kk + kq]);
-            const bf16x8 y1 = *reinterpret_cast<const bf16x8*>(&Bs[(wc + 16 + r) * LDSW + kk + kq]);
+            const bf16x8 x0 = at(As, wr + r, kk + kq);
+            const bf16x8 x1 = at(As, wr + 16 + r, kk + kq);
+            const bf16x8 y0 = at(Bs, wc + r, kk + kq);
+            const bf16x8 y1 = at(Bs, wc + 16 + r, kk + kq);
             acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y0, acc[1][0], 0, 0, 0);
