@@ -235,7 +235,26 @@ def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000, n_plain=4):
         plain_s.append(secs)
         plain_err.append(SS.rel_l2(fw[i], f))
     per_warm = (warm["seconds"] + t_pred) / n_cases
+    # time to steady: a batch's wall time is set by its slowest cavity, and
+    # cavities that never become steady (oscillating flows, e.g. Nc near -1)
+    # run to the step cap either way.  Time the warm and the cold path again
+    # on the cavities that became steady in either run above, with a higher
+    # cap, so that both times measure the approach to a steady state.
+    steady = [i for i in range(n_cases) if warm["status"][i] == 1 or cold["status"][i] == 1]
+    sub = [cases[i] for i in steady]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred_s = SS.predict(net, params[steady])
+    t_pred_s = time.perf_counter() - t0
+    warm_s, _ = SS.solve_path(sub, pred_s, max_steps=2 * max_steps, label="warm", log=quiet)
+    cold_s, _ = SS.solve_path(sub, None, max_steps=2 * max_steps, label="cold", log=quiet)
+    to_steady = {"cavities": len(steady), "max_steps_per_phase": 2 * max_steps,
+                 "steady_warm": sum(1 for v in warm_s["status"] if v == 1),
+                 "steady_cold": sum(1 for v in cold_s["status"] if v == 1),
+                 "wall_s_warm": round(warm_s["seconds"] + t_pred_s, 2), "wall_s_cold": round(cold_s["seconds"], 2),
+                 "speedup": round(cold_s["seconds"] / (warm_s["seconds"] + t_pred_s), 3)}
     return {"cases": n_cases, "L": 128, "converged_both": len(ok), "tol": 1e-8,
+            "time_to_steady": to_steady,
             "plain_fp64_s_per_case": round(float(np.mean(plain_s)), 3) if plain_s else None,
             "warm_batched_s_per_case": round(per_warm, 3),
             "speedup_vs_plain": round(float(np.mean(plain_s)) / per_warm, 2) if plain_s else None,
