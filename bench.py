@@ -253,6 +253,10 @@ def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000, n_plain=4):
                  "steady_cold": sum(1 for v in cold_s["status"] if v == 1),
                  "wall_s_warm": round(warm_s["seconds"] + t_pred_s, 2), "wall_s_cold": round(cold_s["seconds"], 2),
                  "speedup": round(cold_s["seconds"] / (warm_s["seconds"] + t_pred_s), 3)}
+    if plain_s:
+        per = (warm_s["seconds"] + t_pred_s) / len(steady)
+        to_steady["warm_s_per_cavity"] = round(per, 3)
+        to_steady["speedup_vs_plain"] = round(float(np.mean(plain_s)) / per, 2)
     return {"cases": n_cases, "L": 128, "converged_both": len(ok), "tol": 1e-8,
             "time_to_steady": to_steady,
             "plain_fp64_s_per_case": round(float(np.mean(plain_s)), 3) if plain_s else None,

@@ -72,8 +72,11 @@ enum { LB_MODEL_LINEAR = 0,      /* D constant, S = K phi, F = F0 + sum_a Fphi[a
                                     lb_wall_flux and lb_copy_state are not available. */
 /* population storage in device memory */
 enum { LB_STORE_F64 = 0,         /* raw populations, FP64 arithmetic */
-       LB_STORE_F32 = 1,         /* deviations f - W_i phi_ref, h - rho0 delta_i0 in FP32, FP32 arithmetic */
-       LB_STORE_F16 = 2 };       /* the same deviations times fp16_scale in binary16, FP32 arithmetic */
+       LB_STORE_F32 = 1,         /* deviations f - W_i phi_ref, h - rho0 delta_i0 in FP32, FP32 arithmetic;
+                                    each species' rest population takes the FP64 remainder of its
+                                    post-collision mass (no systematic drift of the scalar totals) */
+       LB_STORE_F16 = 2 };       /* the same deviations times fp16_scale in binary16, stochastically
+                                    rounded (reproducible counter-based dither), FP32 arithmetic */
 /* fluid collision */
 enum { LB_COLL_BGK = 0, LB_COLL_MRT = 1 };
 /* chemotaxis cut-off r(c) */

@@ -21,7 +21,9 @@
  * the message of the last failure on the calling thread.  Fields are
  * host arrays in FP64, x fastest: phi [m][nz][ny][nx], u [3][nz][ny][nx],
  * p [nz][ny][nx].  Storage LB_STORE_F64, or LB_STORE_F32 holding deviations
- * from W_i phi_ref (scalars) and rho0 (rest fluid population).
+ * from W_i phi_ref (scalars) and rho0 (rest fluid population), with each
+ * species' rest population set to the FP64 remainder of its post-collision
+ * mass.  Grids need nx ny nz < 2^31 and (nx + 64)(19 + 7m) < 2^31.
  */
 #ifndef LB3_H
 #define LB3_H

@@ -246,6 +246,26 @@ def main():
                      "status_warm": warm["status"], "status_cold": cold["status"]},
     }
     save()
+    # time to steady: batch wall times are set by the slowest cavity, and
+    # cavities that never become steady run to the step cap either way; time
+    # both paths again on the cavities that became steady in either run
+    steady = [i for i in range(len(cases)) if warm["status"][i] == 1 or cold["status"][i] == 1]
+    log(f"time to steady: {len(steady)} cavities")
+    _sync()
+    t0 = time.perf_counter()
+    pred_s = predict(net, tparams[steady])
+    t_pred_s = time.perf_counter() - t0
+    sub = [cases[i] for i in steady]
+    warm_s, _ = solve_path(sub, pred_s, tol32=args.tol32, max_steps=3_000_000, label="warm (steady set)", log=log)
+    cold_s, _ = solve_path(sub, None, tol32=args.tol32, max_steps=3_000_000, label="cold (steady set)", log=log)
+    summary["time_to_steady"] = {
+        "cavities": len(steady), "max_steps_per_phase": 3_000_000,
+        "steady_warm": int(sum(1 for v in warm_s["status"] if v == 1)),
+        "steady_cold": int(sum(1 for v in cold_s["status"] if v == 1)),
+        "warm_seconds": warm_s["seconds"] + t_pred_s, "cold_seconds": cold_s["seconds"],
+        "speedup_warm_vs_cold": cold_s["seconds"] / (warm_s["seconds"] + t_pred_s),
+    }
+    save()
     log("plain FP64 reference on a subset")
     plain = []
     for i in ok[: args.plain]:
@@ -263,8 +283,12 @@ def main():
             "speedup": per_case_plain / (summary["batched"]["warm_seconds"] / len(cases)),
             "warm_relL2_vs_plain_max": max(p["warm_relL2"] for p in plain),
         }
+        tts = summary["time_to_steady"]
+        tts["warm_seconds_per_cavity"] = tts["warm_seconds"] / tts["cavities"]
+        tts["speedup_vs_plain"] = per_case_plain / tts["warm_seconds_per_cavity"]
     save()
-    log(json.dumps({k: summary[k] for k in ("dataset", "training", "batched") if k in summary}, indent=1))
+    log(json.dumps({k: summary[k] for k in ("dataset", "training", "batched", "time_to_steady") if k in summary},
+                   indent=1))
 
 
 if __name__ == "__main__":
