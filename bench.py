@@ -97,7 +97,21 @@ def kernel_time(step_fn, stream, launches):
     return e0.elapsed_time(e1) / 1e3 / launches
 
 
-def cpu_baseline(wl, phi0, u0, p0, budget_s=15.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, phi0, u0, p0, budget_s=15.0, single_s=5.0):
+    """The oracle on the host cores: all threads on a ~15 s sample, then one
+    thread on a ~5 s sample of the same run (the per-node updates are
+    independent, so the thread count does not change results)."""
     from oracle import oracle as O
 
     o = O.Oracle(wl, phi0, u0, p0)
@@ -110,8 +124,24 @@ def cpu_baseline(wl, phi0, u0, p0, budget_s=15.0):
     o.step(steps)
     el = time.perf_counter() - t0
     lu = wl["nx"] * wl["ny"] * steps
-    return {"value": round(lu / el / 1e6, 2), "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
-            "sample": f"{wl['name']}, FP64 oracle, {steps} steps from the same initial state ({el:.1f} s)"}
+    cores = O.threads()
+    O.set_threads(1)
+    try:
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(2)
+        dt1 = max(time.perf_counter() - t0, 1e-6) / 2
+        s1 = max(2, int(single_s / dt1))
+        t0 = time.perf_counter()
+        o.step(s1)
+        el1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(cores)
+    return {"value": round(lu / el / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{wl['name']}, FP64 oracle, {steps} steps from the same initial state ({el:.1f} s)",
+            "single_thread_MLUPS": round(wl["nx"] * wl["ny"] * s1 / el1 / 1e6, 2),
+            "single_thread_sample": f"{s1} further steps on one thread ({el1:.1f} s)",
+            "cpu_model": cpu_model()}
 
 
 def traffic_record():

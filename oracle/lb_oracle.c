@@ -671,6 +671,16 @@ int orc_threads(void) {
 #endif
 }
 
+/* sets the number of threads of the parallel step loop (n > 0); results do
+   not depend on it: every node's update is independent of the others */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 size_t orc_cfg_size(void) { return sizeof(orc_cfg); }
 
 /* the chemotaxis cut-off r(c) of the record (for pin tests) */

@@ -251,3 +251,7 @@ def cutoff(wl: dict, c: float) -> float:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
