@@ -147,3 +147,40 @@ def test_copy_cavity_rejects_mismatched_parameters():
     b = lb.Batch(cases[:2])
     with pytest.raises(lb.LBError):
         lb.lbb_copy_cavity(b.handle, 0, a.handle, 1)
+
+
+def test_full_sweep_sampled_cavities(oracle_mod):
+    """The 256-cavity sweep at its full size (8.0 M nodes, sides 64..256), as
+    benchmarked: FP32 after autotuning, every sampled cavity bitwise equal to
+    a single-domain FP32 run; and FP64 on the same batch, the smallest, the
+    largest and a middle cavity against the oracle after 300 steps (both
+    parities visited) at 1e-11."""
+    pds = W.sweep_params(256, seed=4)
+    cases = [W.ddc_case(pd) for pd in pds]
+    sizes = [c[0]["nx"] * c[0]["ny"] for c in cases]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), len(cases) // 2})
+
+    b32 = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
+    b32.autotune(4)
+    b32.step(301 - b32.time(0)[0])
+    for i in pick:
+        s = lb.Solver(*cases[i], storage="f32", phi_ref=[0.5, 0.5])
+        s.step(301)
+        phi_b, u_b, _ = b32.moments(i)
+        phi_s, u_s, _ = s.moments()
+        assert np.array_equal(phi_b, phi_s) and np.array_equal(u_b, u_s), f"cavity {i}"
+        s.close()
+    b32.close()
+
+    b64 = lb.Batch(cases, storage="f64")
+    b64.step(300)
+    for i in pick:
+        wl, phi0, u0, p0 = cases[i]
+        o = oracle_mod.Oracle(wl, phi0, u0, p0)
+        o.step(300)
+        phi, u, _ = b64.moments(i)
+        po, uo, _ = o.moments()
+        e = max(max(np.abs(phi[a] - po[a]).max() / np.abs(po[a]).max() for a in range(2)),
+                max(np.abs(u[d] - uo[d]).max() / np.abs(uo[d]).max() for d in range(2)))
+        print(f"sweep cavity {i} ({wl['nx']}x{wl['ny']}): FP64 vs oracle {e:.2e}", flush=True)
+        assert e <= 1e-11
