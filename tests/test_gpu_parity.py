@@ -233,3 +233,15 @@ def test_tile_shapes_identical(tile):
     fa, ha = a.populations()
     fb, hb = b.populations()
     assert np.array_equal(fa, fb) and np.array_equal(ha, hb)
+
+
+def test_taylor_green_4096_full_grid(oracle_mod):
+    """The 4096^2 grid of the bandwidth measurement (FP64 state 2.55 GB, so
+    element offsets past 2^31 bytes; 256 x 1 tiles and the even-step cache
+    hint), 11 steps (both AA parities, ending on an odd step) against the
+    oracle: moments at 1e-11."""
+    wl, phi0, u0, p0 = W.taylor_green_blobs(n=4096, steps=0)
+    o, g = run_pair(oracle_mod, wl, phi0, u0, p0, 11)
+    e = moment_errors(o, g)
+    print(f"taylor_green 4096x4096 11 steps: moments {e:.2e}", flush=True)
+    assert e <= TOL64
