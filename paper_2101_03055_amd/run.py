@@ -1,0 +1,148 @@
+"""Run a named workload configuration on the GPU.
+
+    python -m paper_2101_03055_amd.run CONFIG [--storage f64|f32|f16] [--steps N] [--steady]
+                                       [--out fields.npz]
+
+CONFIG is a file name under ``configs/`` (without ``.json``) or a path.  A
+transient run advances the configured number of steps (or ``--steps``) and
+reports the step rate, the per-species masses and the fields; a steady run
+(``--steady``, or a configuration whose run section sets ``tol``) iterates to
+the configured residual.  With reduced-precision storage a steady run first
+iterates in that storage to ``tol32`` (1e-5 unless the configuration sets
+it; FP32/FP16 storage cannot resolve residuals near 1e-8), then copies the
+state to FP64 storage and finishes there.  A sweep configuration runs as one
+batch (reduced-precision phase, then FP64).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import lb, workloads as W
+
+
+def _sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def _transient(case, storage, phi_ref, steps):
+    wl = case[0]
+    s = lb.Solver(*case, storage=storage, phi_ref=phi_ref)
+    s.step(min(steps, 64))  # first launches and graph build outside the timed part
+    _sync()
+    t0 = time.perf_counter()
+    s.step(steps - min(steps, 64))
+    _sync()
+    secs = time.perf_counter() - t0
+    timed = steps - min(steps, 64)
+    mass, _ = s.mass()
+    phi, u, p = s.moments()
+    out = {"steps": s.t, "seconds": secs,
+           "MLUPS": wl["nx"] * wl["ny"] * timed / secs / 1e6 if timed and secs > 0 else None,
+           "mass": mass.tolist()}
+    s.close()
+    return out, (phi, u, p)
+
+
+def _steady(case, storage, phi_ref, tol, tol32, check_every, max_steps):
+    _sync()
+    t0 = time.perf_counter()
+    out = {}
+    if storage == "f64":
+        s = lb.Solver(*case, storage="f64")
+        steps, res, st = s.solve_steady(tol, check_every, max_steps)
+        out.update(steps=steps, status=int(st), residual=res.tolist())
+    else:
+        r = lb.Solver(*case, storage=storage, phi_ref=phi_ref)
+        n_r, res_r, st_r = r.solve_steady(tol32, check_every, max_steps)
+        s = lb.Solver(*case, storage="f64")
+        if st_r != lb.LB_ENONFINITE:
+            lb.lb_copy_state(s.handle, r.handle)
+        r.close()
+        steps, res, st = s.solve_steady(tol, check_every, max_steps)
+        out.update(steps_reduced=n_r, status_reduced=int(st_r), steps_fp64=steps, status=int(st),
+                   residual=res.tolist())
+    _sync()
+    out["seconds"] = time.perf_counter() - t0
+    mass, _ = s.mass()
+    out["mass"] = mass.tolist()
+    fields = s.moments()
+    s.close()
+    return out, fields
+
+
+def _sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps):
+    from .surrogate_study import run_batch
+
+    quiet = lambda s: None
+    _sync()
+    t0 = time.perf_counter()
+    b = lb.Batch(cases, storage=storage, phi_ref=phi_ref)
+    tile = b.autotune(10)[:2]
+    if storage != "f64":
+        s_r, st_r, _ = run_batch(b, tol32, check_every, max_steps, window=50000, log=quiet)
+        b64 = lb.Batch(cases, storage="f64")
+        for i in range(len(cases)):
+            if st_r[i] != lb.LBB_DIVERGED:
+                lb.lbb_copy_cavity(b64.handle, i, b.handle, i)
+        b.close()
+        b = b64
+    s64, st64, _ = run_batch(b, tol, check_every, max_steps, window=50000, log=quiet)
+    _sync()
+    secs = time.perf_counter() - t0
+    st64 = np.asarray(st64)
+    out = {"cavities": len(cases), "tile": list(tile), "seconds": secs,
+           "converged": int((st64 == lb.LBB_CONVERGED).sum()), "diverged": int((st64 == lb.LBB_DIVERGED).sum()),
+           "steps_fp64_median": float(np.median(s64))}
+    b.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("config")
+    ap.add_argument("--storage", choices=["f64", "f32", "f16"], default=None)
+    ap.add_argument("--steps", type=int, default=None, help="transient run of this many steps")
+    ap.add_argument("--steady", action="store_true", help="iterate to the configured residual")
+    ap.add_argument("--max-steps", type=int, default=None)
+    ap.add_argument("--out", default=None, help="write phi, u, p to this .npz (single domains)")
+    args = ap.parse_args(argv)
+
+    cfg, cases = W.load_config(args.config)
+    run = cfg.get("run", {})
+    storage = args.storage or (run.get("storage") or ["f64"])[0]
+    phi_ref = run.get("phi_ref")
+    tol, tol32 = run.get("tol", 1e-8), run.get("tol32", 1e-5)
+    check_every = run.get("check_every", 1000)
+    max_steps = args.max_steps or run.get("max_steps", 5_000_000)
+    if cfg["workload"] == "sweep_case":
+        raise SystemExit("the surrogate configuration runs through `python -m paper_2101_03055_amd.surrogate_study`")
+    rec = {"config": os.path.basename(args.config).removesuffix(".json"), "storage": storage}
+    fields = None
+    if cfg["workload"] == "sweep":
+        rec.update(_sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps))
+    elif args.steady or (args.steps is None and "tol" in run):
+        out, fields = _steady(cases[0], storage, phi_ref, tol, tol32, check_every, max_steps)
+        rec.update(out)
+    else:
+        steps = args.steps if args.steps is not None else run.get("steps", 1000)
+        steps = steps[0] if isinstance(steps, list) else steps
+        out, fields = _transient(cases[0], storage, phi_ref, int(steps))
+        rec.update(out)
+    if args.out and fields is not None:
+        phi, u, p = fields
+        np.savez(args.out, phi=phi, u=u, p=p)
+        rec["out"] = args.out
+    print(json.dumps(rec), flush=True)
+    return rec
+
+
+if __name__ == "__main__":
+    sys.exit(0 if main() else 1)

@@ -1,0 +1,64 @@
+"""The configuration runner (python -m paper_2101_03055_amd.run).
+
+CPU: every named configuration loads; the surrogate configuration is sent
+to its own study driver before anything touches a GPU.  GPU: a transient
+run through the runner equals a direct Solver run bitwise, and a steady run
+in FP32 storage (FP32 phase, FP64 finish) converges to 1e-8 within 1e-6 of
+the all-FP64 solution.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2101_03055_amd import lb, run, workloads as W
+
+CONFIGS = sorted(f[:-5] for f in os.listdir(W.CONFIG_DIR) if f.endswith(".json"))
+
+
+def test_configs_have_runner_sections():
+    assert "taylor_green_blobs_64" in CONFIGS and "ddc_sweep_256_cavities" in CONFIGS
+    for name in CONFIGS:
+        with open(os.path.join(W.CONFIG_DIR, name + ".json")) as fh:
+            cfg = json.load(fh)
+        assert "workload" in cfg and "run" in cfg, name
+
+
+def test_surrogate_config_goes_to_its_study():
+    with pytest.raises(SystemExit):
+        run.main(["surrogate_ddc128"])
+
+
+@pytest.mark.gpu
+def test_transient_run_equals_direct_solver(tmp_path):
+    out = str(tmp_path / "tg.npz")
+    rec = run.main(["taylor_green_blobs_64", "--out", out])
+    assert rec["steps"] == 1000 and rec["MLUPS"] > 0
+    cfg, cases = W.load_config("taylor_green_blobs_64")
+    s = lb.Solver(*cases[0])
+    s.step(1000)
+    phi, u, p = s.moments()
+    d = np.load(out)
+    assert np.array_equal(d["phi"], phi) and np.array_equal(d["u"], u) and np.array_equal(d["p"], p)
+
+
+@pytest.mark.gpu
+def test_steady_run_in_fp32_storage(tmp_path):
+    path = str(tmp_path / "ddc64.json")
+    with open(path, "w") as fh:
+        json.dump({"workload": "ddc", "kwargs": {"L": 64, "Ra": 1e4, "Pr": 0.71, "Le": 2.0, "Nc": 1.0, "Sr": 0.1,
+                                                 "Df": 0.1, "A": 1.0, "u_lat": 0.1},
+                   "run": {"storage": ["f32"], "phi_ref": [0.5, 0.5], "tol": 1e-8, "check_every": 1000,
+                           "max_steps": 2000000}}, fh)
+    out = str(tmp_path / "ddc64.npz")
+    rec = run.main([path, "--steady", "--out", out])
+    assert rec["status"] == lb.LB_OK and max(rec["residual"]) <= 1e-8
+    _, cases = W.load_config(path)
+    ref = lb.Solver(*cases[0], storage="f64")
+    _, _, st = ref.solve_steady(1e-8, 1000, 2000000)
+    assert st == lb.LB_OK
+    phi_r, u_r, _ = ref.moments()
+    d = np.load(out)
+    assert np.linalg.norm(d["phi"] - phi_r) / np.linalg.norm(phi_r) < 1e-6
+    assert np.linalg.norm(d["u"] - u_r) / np.linalg.norm(u_r) < 1e-6
