@@ -173,6 +173,21 @@ def hbm_sweep(W, lb, torch):
                                      "bytes_per_lu": bb}
         del sb
         torch.cuda.empty_cache()
+    # the MRT fluid collision (Lallemand-Luo basis) on the same grid: same bytes, more arithmetic
+    for storage in ("f64", "f32"):
+        n = 4096
+        wlb, pb, ub, ppb = W.taylor_green_blobs(n=n, steps=0)
+        wlb = dict(wlb, collision="mrt")
+        sb = lb.Solver(wlb, pb, ub, ppb, storage=storage, phi_ref=[1.0, 1.0])
+        sb.step(20)
+        kt = kernel_time(sb.step, sb.stream, 100)
+        bb = bytes_per_lu(2, storage, 0)
+        ach = bb * n * n / kt / 1e9
+        out[f"mrt_{storage}_{n}x{n}"] = {"MLUPS": round(n * n / kt / 1e6, 1), "achieved_GBs": round(ach, 1),
+                                         "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2),
+                                         "bytes_per_lu": bb}
+        del sb
+        torch.cuda.empty_cache()
     return out
 
 
