@@ -2,9 +2,9 @@
 
 CPU: every named configuration loads; the surrogate configuration is sent
 to its own study driver before anything touches a GPU.  GPU: a transient
-run through the runner equals a direct Solver run bitwise, and a steady run
-in FP32 storage (FP32 phase, FP64 finish) converges to 1e-8 within 1e-6 of
-the all-FP64 solution.
+run through the runner equals a direct Solver run bitwise, and steady runs
+in FP32 and FP16 storage (reduced-precision phase, FP64 finish) converge to
+1e-8 within 1e-6 of the all-FP64 solution.
 """
 import json
 import os
@@ -44,15 +44,17 @@ def test_transient_run_equals_direct_solver(tmp_path):
 
 
 @pytest.mark.gpu
-def test_steady_run_in_fp32_storage(tmp_path):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_steady_run_in_reduced_storage(tmp_path, storage):
     path = str(tmp_path / "ddc64.json")
     with open(path, "w") as fh:
         json.dump({"workload": "ddc", "kwargs": {"L": 64, "Ra": 1e4, "Pr": 0.71, "Le": 2.0, "Nc": 1.0, "Sr": 0.1,
                                                  "Df": 0.1, "A": 1.0, "u_lat": 0.1},
-                   "run": {"storage": ["f32"], "phi_ref": [0.5, 0.5], "tol": 1e-8, "check_every": 1000,
+                   "run": {"storage": [storage], "phi_ref": [0.5, 0.5], "tol": 1e-8, "check_every": 1000,
                            "max_steps": 2000000}}, fh)
     out = str(tmp_path / "ddc64.npz")
     rec = run.main([path, "--steady", "--out", out])
+    print(f"\n{storage}: {rec}", flush=True)
     assert rec["status"] == lb.LB_OK and max(rec["residual"]) <= 1e-8
     _, cases = W.load_config(path)
     ref = lb.Solver(*cases[0], storage="f64")
