@@ -375,7 +375,7 @@ def main():
                          "sweep / batch: only the 4096^2 or the batched-cavity leg (for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the design notes describe how the domain would be sharded).", file=sys.stderr)
         sys.exit(2)
 
