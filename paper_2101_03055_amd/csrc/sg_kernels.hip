@@ -154,20 +154,37 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const 
 // or half a longer one) x 64 output channels: each wavefront computes 32
 // pixels x 64 channels, so every K step issues 8 MFMAs per 6 LDS operand reads
 // (4 per 4 in k_conv).  Needs W % 128 == 0.
+// 16 zero bytes: the source of the LDS DMA loads of pixels outside the image
+__device__ const uint4 kZero16 = {0u, 0u, 0u, 0u};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// wait until at most N vector-memory operations of this wave are outstanding
+// (LDS DMA loads count there until their data is in LDS); other counters untouched
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+constexpr int kStages = 3;                          // LDS ring depth of k_conv128
+constexpr int kStageElems = (128 + 64) * LDSK;      // bf16 per stage: A tile, then B tile
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
                                                  const float* __restrict__ bias, const float* __restrict__ Zprev,
                                                  float* __restrict__ Zout, bf16* __restrict__ Yout, int H, int W,
                                                  int Cin, int Cout, int act) {
-    __shared__ __attribute__((aligned(16))) bf16 As[128 * LDSK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSK];
+    // kStages LDS stages (A: 128 pixels x 32 channels, B: 64 output channels x
+    // 32 channels), filled by LDS DMA (global_load_lds): kStages - 1 K steps
+    // are in flight while the matrix cores work on one, with no staging registers
+    __shared__ __attribute__((aligned(16))) bf16 Sbuf[kStages * kStageElems];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_per_row = W >> 7;
     const int img_row = blockIdx.x / tiles_per_row;  // b * H + y
     const int x0 = (blockIdx.x % tiles_per_row) << 7;
     const int y = img_row % H;
     const int n0 = blockIdx.y << 6;
-    const int sj = tid >> 2, sq = tid & 3;  // rows sj and sj + 64 of A, row sj of B; 8 channels each
     const int wr = wave << 5;
     floatx4 acc[2][4];
 #pragma unroll
@@ -175,35 +192,81 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int tap = 0; tap < 9; ++tap) {
+    // A DMA load writes 64 lanes x 16 bytes = 16 tile rows at the wave's base;
+    // lane l fills row 16 c + l / 4, LDS segment l % 4, from global segment
+    // (l % 4) ^ swz(row), which is where tile_off() looks for it
+    const int rsub = lane >> 2, pseg = lane & 3;
+    const int nc = Cin >> 5, nsteps = 9 * nc;
+    auto issue = [&](int st, bf16* As, bf16* Bs) {
+        const int tap = st / nc, c0 = (st - tap * nc) << 5;
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         const int yy = y + dy;
         const bool rowin = (yy >= 0) & (yy < H);
-        const int xa = x0 + sj + dx, xb = x0 + sj + 64 + dx;
-        const bool ina = rowin & (xa >= 0) & (xa < W), inb = rowin & (xb >= 0) & (xb < W);
-        const long long srca = ((long long)(img_row + dy) * W + xa) * Cin;
-        const long long srcb = ((long long)(img_row + dy) * W + xb) * Cin;
-        const long long wsrc = ((long long)(n0 + sj) * 9 + tap) * Cin;
-        for (int c0 = 0; c0 < Cin; c0 += 32) {
-            uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = make_uint4(0u, 0u, 0u, 0u);
-            if (ina) va = *reinterpret_cast<const uint4*>(X + srca + c0 + 8 * sq);
-            if (inb) vb = *reinterpret_cast<const uint4*>(X + srcb + c0 + 8 * sq);
-            *reinterpret_cast<uint4*>(&As[tile_off(sj, sq)]) = va;
-            *reinterpret_cast<uint4*>(&As[tile_off(sj + 64, sq)]) = vb;
-            *reinterpret_cast<uint4*>(&Bs[tile_off(sj, sq)]) =
-                *reinterpret_cast<const uint4*>(Wk + wsrc + c0 + 8 * sq);
-            __syncthreads();
-            const int r = lane & 15;
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[tile_off(wr + r, lane >> 4)]);
-            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[tile_off(wr + 16 + r, lane >> 4)]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[tile_off(16 * j + r, lane >> 4)]);
-                acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[0][j], 0, 0, 0);
-                acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[1][j], 0, 0, 0);
-            }
-            __syncthreads();
+        for (int q = 0; q < 2; ++q) {
+            const int row = 16 * (wave + 4 * q) + rsub;  // pixel x0 + row
+            const int seg = (pseg ^ (row >> 1) ^ (row >> 3)) & 3;
+            const int xx = x0 + row + dx;
+            const bool in = rowin & (xx >= 0) & (xx < W);
+            const void* src = in ? (const void*)(X + ((long long)(img_row + dy) * W + xx) * Cin + c0 + 8 * seg)
+                                 : (const void*)&kZero16;
+            __builtin_amdgcn_global_load_lds(src, (lds_void*)(As + (16 * (wave + 4 * q)) * LDSK), 16, 0, 0);
         }
+        {
+            const int row = 16 * wave + rsub;  // output channel n0 + row
+            const int seg = (pseg ^ (row >> 1) ^ (row >> 3)) & 3;
+            __builtin_amdgcn_global_load_lds((const void*)(Wk + ((long long)(n0 + row) * 9 + tap) * Cin + c0 + 8 * seg),
+                                             (lds_void*)(Bs + (16 * wave) * LDSK), 16, 0, 0);
+        }
+    };
+    auto lds_addr = [](const bf16* p) { return (uint32_t)(uintptr_t)p; };
+    // inflight: loads issued after this stage's (3 per stage and thread)
+    auto compute = [&](const bf16* As, const bf16* Bs, int inflight) {
+        // this wave's loads of this stage have landed, later stages may still be in flight ...
+        switch (inflight) {
+            case 9: wait_vm<9>(); break;
+            case 6: wait_vm<6>(); break;
+            case 3: wait_vm<3>(); break;
+            default: wait_vm<0>(); break;
+        }
+        __builtin_amdgcn_s_barrier();  // ... and every other wave's
+        const int r = lane & 15, sg = lane >> 4;
+        // The six operand reads are written as one asm block that waits for
+        // them itself: as plain loads, the compiler cannot tell them from the
+        // LDS DMA writes still in flight to the other stages and waits for
+        // all vector-memory operations first (vmcnt(0)), which serialises the
+        // pipeline.
+        bf16x8 a0, a1, b0, b1, b2, b3;
+        asm volatile(
+            "ds_read_b128 %0, %6\n\t"
+            "ds_read_b128 %1, %7\n\t"
+            "ds_read_b128 %2, %8\n\t"
+            "ds_read_b128 %3, %9\n\t"
+            "ds_read_b128 %4, %10\n\t"
+            "ds_read_b128 %5, %11\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(a0), "=&v"(a1), "=&v"(b0), "=&v"(b1), "=&v"(b2), "=&v"(b3)
+            : "v"(lds_addr(&As[tile_off(wr + r, sg)])), "v"(lds_addr(&As[tile_off(wr + 16 + r, sg)])),
+              "v"(lds_addr(&Bs[tile_off(r, sg)])), "v"(lds_addr(&Bs[tile_off(16 + r, sg)])),
+              "v"(lds_addr(&Bs[tile_off(32 + r, sg)])), "v"(lds_addr(&Bs[tile_off(48 + r, sg)]))
+            : "memory");
+        const bf16x8 bj[4] = {b0, b1, b2, b3};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bj[j], acc[0][j], 0, 0, 0);
+            acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bj[j], acc[1][j], 0, 0, 0);
+        }
+        __builtin_amdgcn_s_barrier();  // every wave is done reading this stage before it is refilled
+    };
+    auto stage_a = [&](int st) { return Sbuf + (st % kStages) * kStageElems; };
+    auto stage_b = [&](int st) { return Sbuf + (st % kStages) * kStageElems + 128 * LDSK; };
+#pragma unroll
+    for (int k = 0; k < kStages - 1; ++k)
+        if (k < nsteps) issue(k, stage_a(k), stage_b(k));
+    for (int st = 0; st < nsteps; ++st) {
+        if (st + kStages - 1 < nsteps) issue(st + kStages - 1, stage_a(st + kStages - 1), stage_b(st + kStages - 1));
+        const int later = min(kStages - 1, nsteps - 1 - st);  // stages issued after this one
+        compute(stage_a(st), stage_b(st), 3 * later);
     }
     const long long pbase = (long long)img_row * W + x0;
 #pragma unroll
