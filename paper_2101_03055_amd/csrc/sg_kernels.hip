@@ -42,7 +42,7 @@ constexpr int kCinPad[kLayers] = {32, 64, 128, 64, 64, 64};
 constexpr int kCoutPad[kLayers] = {64, 128, 64, 64, 64, 64};
 constexpr int kMaxC = 128;
 constexpr int kFeat = 15;
-constexpr int kSplit = 64;      // split-K factor of the weight gradient
+constexpr int kSplit = 128;     // split-K factor of the weight gradient
 constexpr int kRed = 256;       // blocks of the first pass of small reductions
 constexpr int LDSK = 32;        // LDS row pitch in bf16 of the convolution tiles (32 channels, no pad)
 
@@ -304,48 +304,62 @@ __device__ __forceinline__ uint32_t pack_bf16x2(bf16 lo, bf16 hi) {
 
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, const bf16* __restrict__ X,
                                                float* __restrict__ part, int H, int W, int P, int Ci, int Co) {
+    // one workgroup: the three taps dx = -1, 0, +1 of one dy share the
+    // transposed dZ tile (A), each with its own shifted input tile (B)
     __shared__ __attribute__((aligned(16))) bf16 As[64 * LDSW];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[64 * LDSW];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[3][64 * LDSW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x << 6, n0 = blockIdx.y << 6;
-    const int tap = blockIdx.z % 9, s = blockIdx.z / 9;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int dy = (int)(blockIdx.z % 3) - 1, s = blockIdx.z / 3;
     const int chunks = P >> 6;
     const int c_begin = (int)((long long)s * chunks / kSplit), c_end = (int)((long long)(s + 1) * chunks / kSplit);
     const int pp = tid >> 3, cg = tid & 7;  // pixel pair (0..31), 8-channel group (0..7)
     const int wr = (wave >> 1) << 5, wc = (wave & 1) << 5;
     const bool bcol = n0 + 8 * cg < Ci;
-    floatx4 acc[2][2];
+    floatx4 acc[3][2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int t = 0; t < 3; ++t)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    uint4 va[2], vb[2];
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[t][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    uint4 va[2], vb[3][2];
     auto load = [&](int c) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const long long p = ((long long)c << 6) + 2 * pp + q;
             va[q] = *reinterpret_cast<const uint4*>(dZ + p * Co + m0 + 8 * cg);
             const int img_row = (int)(p / W), xi = (int)(p % W), yi = img_row % H;
-            const int yy = yi + dy, xx = xi + dx;
-            vb[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (bcol && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                vb[q] = *reinterpret_cast<const uint4*>(X + ((long long)(img_row + dy) * W + xx) * Ci + n0 + 8 * cg);
+            const int yy = yi + dy;
+            const bool rowin = bcol && yy >= 0 && yy < H;
+            const bf16* xrow = X + (long long)(img_row + dy) * W * Ci + n0 + 8 * cg;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int xx = xi + t - 1;
+                vb[t][q] = make_uint4(0u, 0u, 0u, 0u);
+                if (rowin && xx >= 0 && xx < W) vb[t][q] = *reinterpret_cast<const uint4*>(xrow + (long long)xx * Ci);
+            }
         }
     };
     if (c_begin < c_end) load(c_begin);
     for (int c = c_begin; c < c_end; ++c) {
-        const bf16* a0 = reinterpret_cast<const bf16*>(&va[0]);
-        const bf16* a1 = reinterpret_cast<const bf16*>(&va[1]);
-        const bf16* b0 = reinterpret_cast<const bf16*>(&vb[0]);
-        const bf16* b1 = reinterpret_cast<const bf16*>(&vb[1]);
         // row 8 cg + e, pixel pair pp: its 8-pixel group pp / 4 is XOR-swizzled
         // with the row's cg (rows 8 apart would otherwise share LDS banks)
         const int col = ((((pp >> 2) ^ cg) & 7) << 3) | ((pp & 3) << 1);
+        {
+            const bf16* a0 = reinterpret_cast<const bf16*>(&va[0]);
+            const bf16* a1 = reinterpret_cast<const bf16*>(&va[1]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            *reinterpret_cast<uint32_t*>(&As[(8 * cg + e) * LDSW + col]) = pack_bf16x2(a0[e], a1[e]);
-            *reinterpret_cast<uint32_t*>(&Bs[(8 * cg + e) * LDSW + col]) = pack_bf16x2(b0[e], b1[e]);
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<uint32_t*>(&As[(8 * cg + e) * LDSW + col]) = pack_bf16x2(a0[e], a1[e]);
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const bf16* b0 = reinterpret_cast<const bf16*>(&vb[t][0]);
+            const bf16* b1 = reinterpret_cast<const bf16*>(&vb[t][1]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<uint32_t*>(&Bs[t][(8 * cg + e) * LDSW + col]) = pack_bf16x2(b0[e], b1[e]);
         }
         __syncthreads();
         if (c + 1 < c_end) load(c + 1);
@@ -358,26 +372,33 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, cons
         for (int kk = 0; kk < 64; kk += 32) {
             const bf16x8 x0 = at(As, wr + r, kk + kq);
             const bf16x8 x1 = at(As, wr + 16 + r, kk + kq);
-            const bf16x8 y0 = at(Bs, wc + r, kk + kq);
-            const bf16x8 y1 = at(Bs, wc + 16 + r, kk + kq);
-            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y1, acc[1][1], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const bf16x8 y0 = at(Bs[t], wc + r, kk + kq);
+                const bf16x8 y1 = at(Bs[t], wc + 16 + r, kk + kq);
+                acc[t][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y0, acc[t][0][0], 0, 0, 0);
+                acc[t][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, y1, acc[t][0][1], 0, 0, 0);
+                acc[t][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y0, acc[t][1][0], 0, 0, 0);
+                acc[t][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, y1, acc[t][1][1], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
-    float* dst = part + ((long long)s * 9 + tap) * Co * Ci;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int t = 0; t < 3; ++t) {
+        const int tap = 3 * (dy + 1) + t;
+        float* dst = part + ((long long)s * 9 + tap) * Co * Ci;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int co = m0 + wr + 16 * i + 4 * (lane >> 4) + e;
-                const int ci = n0 + wc + 16 * j + (lane & 15);
-                if (ci < Ci) dst[(long long)co * Ci + ci] = acc[i][j][e];
-            }
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = m0 + wr + 16 * i + 4 * (lane >> 4) + e;
+                    const int ci = n0 + wc + 16 * j + (lane & 15);
+                    if (ci < Ci) dst[(long long)co * Ci + ci] = acc[t][i][j][e];
+                }
+    }
 }
 
 // dW[co][tap][ci] (packed) = sum_s part[s][tap][co][ci], fixed order
@@ -724,7 +745,7 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
     for (int l = L; l >= 0; --l) {
         const int Ci = kCinPad[l], Co = kCoutPad[l];
         const bf16* xin = l == 0 ? ptr<bf16>(h, h->pl.x0_off) : ptr<bf16>(h, h->pl.y_off[l - 1]);
-        hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 9u * kSplit), dim3(256), 0,
+        hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 3u * kSplit), dim3(256), 0,
                            h->s, dz, xin, ptr<float>(h, h->pl.part_off), H, W, (int)P, Ci, Co);
         SGCHK(hipGetLastError());
         const long long n = 9ll * Co * Ci;
