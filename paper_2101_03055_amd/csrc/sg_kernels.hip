@@ -402,17 +402,33 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, cons
 }
 
 // dW[co][tap][ci] (packed) = sum_s part[s][tap][co][ci], fixed order
+static_assert(kSplit % 4 == 0, "k_wgrad_reduce splits the partials in four");
+
+// dW = sum over the kSplit partials, in a fixed order: a workgroup covers 64
+// outputs, its wave g sums partials [g kSplit / 4, (g + 1) kSplit / 4) of them,
+// then the four wave sums are added in wave order
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int Ci, int Co,
                                                       float* __restrict__ dW) {
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float red[3][64];
+    const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const long long k = ((long long)blockIdx.x << 6) + j;
     const long long n = 9ll * Co * Ci;
-    if (k >= n) return;
-    const int tap = (int)(k / ((long long)Co * Ci));
-    const long long rem = k % ((long long)Co * Ci);
-    const int co = (int)(rem / Ci), ci = (int)(rem % Ci);
+    const bool live = k < n;
     float s = 0.f;
-    for (int q = 0; q < kSplit; ++q) s += part[(long long)q * n + k];
-    dW[((long long)co * 9 + tap) * Ci + ci] = s;
+    if (live) {
+        const float* src = part + (long long)g * (kSplit / 4) * n + k;
+#pragma unroll 8
+        for (int q = 0; q < kSplit / 4; ++q) s += src[(long long)q * n];
+    }
+    if (g > 0) red[g - 1][j] = s;
+    __syncthreads();
+    if (g == 0 && live) {
+        s = ((s + red[0][j]) + red[1][j]) + red[2][j];
+        const int tap = (int)(k / ((long long)Co * Ci));
+        const long long rem = k % ((long long)Co * Ci);
+        const int co = (int)(rem / Ci), ci = (int)(rem % Ci);
+        dW[((long long)co * 9 + tap) * Ci + ci] = s;
+    }
 }
 
 // bias gradient, two passes: part[block][co] over contiguous pixel ranges
@@ -749,7 +765,7 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
                            h->s, dz, xin, ptr<float>(h, h->pl.part_off), H, W, (int)P, Ci, Co);
         SGCHK(hipGetLastError());
         const long long n = 9ll * Co * Ci;
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s,
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s,
                            ptr<float>(h, h->pl.part_off), Ci, Co, grads + h->pl.woff[l]);
         SGCHK(hipGetLastError());
         hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
