@@ -459,43 +459,58 @@ __global__ __launch_bounds__(256) void k_bgrad_part(const bf16* __restrict__ dZ,
         part[(long long)blockIdx.x * kMaxC + threadIdx.x] = t;
     }
 }
-__global__ __launch_bounds__(128) void k_bgrad_final(const float* __restrict__ part, int nb, int Co,
+
+// db[co] = sum over the nb first-pass partials, in a fixed order: thread
+// (co, g) sums the g-th eighth of them, then the eight sums are added in g order
+__global__ __launch_bounds__(8 * kMaxC) void k_bgrad_final(const float* __restrict__ part, int nb, int Co,
                                                      float* __restrict__ db) {
-    const int co = threadIdx.x;
-    if (co >= Co) return;
-    // sequential order over the blocks; loads issued 16 at a time
+    __shared__ float red[8][kMaxC];
+    const int co = (int)threadIdx.x % kMaxC, g = (int)threadIdx.x / kMaxC;
+    const int b0 = g * nb / 8, b1 = (g + 1) * nb / 8;
     float s = 0.f;
-    for (int b = 0; b < nb; b += 16) {
-        float v[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = b + k < nb ? part[(long long)(b + k) * kMaxC + co] : 0.f;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) s += v[k];
+    if (co < Co) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) s += part[(long long)b * kMaxC + co];
     }
-    db[co] = s;
+    red[g][co] = s;
+    __syncthreads();
+    if (g == 0 && co < Co) {
+        float t = red[0][co];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) t += red[k][co];
+        db[co] = t;
+    }
 }
 
 // MSE over the SG_OUTPUTS real channels: dZ = 2 (z - t) / count (bf16, zero on
 // padded channels); per-block partial sums of (z - t)^2 in FP64
+static_assert(SG_OUTPUTS <= 8, "k_mse keeps the real output channels in the first 8-channel group");
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Z, const float* __restrict__ fields,
                                              const int* __restrict__ idx, int nb, int H, int W, int Co,
                                              bf16* __restrict__ dZ, double* __restrict__ part) {
     __shared__ double red[256];
     const long long P = (long long)nb * H * W;
     const double inv = 2.0 / (double)(P * SG_OUTPUTS);
+    const long long HW = (long long)H * W;
+    const int groups = Co >> 3;  // a thread writes 8 channels of one pixel (one 16-byte store)
     double acc = 0.0;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(p / ((long long)H * W));
-        const long long pix = p % ((long long)H * W);
-        for (int c = 0; c < Co; ++c) {
-            float g = 0.f;
-            if (c < SG_OUTPUTS) {
-                const float d = Z[p * Co + c] - fields[((long long)idx[b] * SG_OUTPUTS + c) * H * W + pix];
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < P * groups;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long p = e / groups;
+        const int cg = (int)(e - p * groups);
+        uint4 pk = make_uint4(0u, 0u, 0u, 0u);
+        if (cg == 0) {  // the real channels 0 .. SG_OUTPUTS - 1
+            bf16* g = reinterpret_cast<bf16*>(&pk);
+            const int b = (int)(p / HW);
+            const long long pix = p - b * HW;
+#pragma unroll
+            for (int c = 0; c < SG_OUTPUTS; ++c) {
+                const float d = Z[p * Co + c] - fields[((long long)idx[b] * SG_OUTPUTS + c) * HW + pix];
                 acc += (double)d * d;
-                g = (float)(inv * d);
+                g[c] = bf16((float)(inv * d));
             }
-            dZ[p * Co + c] = bf16(g);
         }
+        *reinterpret_cast<uint4*>(dZ + p * Co + 8 * cg) = pk;
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -770,7 +785,7 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
         SGCHK(hipGetLastError());
         hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
         SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(128), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co,
+        hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co,
                            grads + h->pl.boff[l]);
         SGCHK(hipGetLastError());
         if (l > 0) {
