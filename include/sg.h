@@ -86,6 +86,32 @@ lb_status sg_layer_output(sg_handle* h, int32_t layer, float* host_out);
  * pass, host [batch][H][W][cin_pad]. */
 lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out);
 
+/* One 3x3 convolution of layer l, run by the same kernels and launch shapes as
+ * the training pass, on caller-owned device tensors of nb <= batch samples
+ * (channels-last, padded channel counts of sg_layer_info; bf16 arrays are
+ * raw bfloat16 words).  Uses the handle's current bfloat16 weights.
+ *   mode 0 (forward): z = b_l + sum_{tap, ci} w_l[co][tap][ci] x[p + off(tap)][ci]
+ *     with x = d_in [nb][H][W][cin_pad]; d_z [nb][H][W][cout_pad] FP32 receives z
+ *     (may be NULL), d_out [nb][H][W][cout_pad] bf16 receives bf16(SiLU(z)) for
+ *     hidden layers and bf16(z) for the last; d_zprev is ignored.
+ *   mode 1 (data gradient, l >= 1): with g = d_in [nb][H][W][cout_pad] (dL/dz of
+ *     layer l), d_out [nb][H][W][cin_pad] bf16 receives
+ *     bf16(SiLU'(zprev) sum_{tap, co} w_l[co][tap][ci] g[p - off(tap)][co]),
+ *     the gradient with respect to the pre-activation of layer l - 1;
+ *     d_zprev [nb][H][W][cin_pad] FP32 is that pre-activation; d_z is ignored.
+ * Asynchronous on the handle's stream. */
+lb_status sg_conv(sg_handle* h, int32_t layer, int32_t mode, int32_t nb, const void* d_in, const float* d_zprev,
+                  float* d_z, void* d_out);
+
+/* Weight and bias gradients of layer l for nb <= batch samples, by the
+ * kernels of the training pass: d_dw [cout_pad][9][cin_pad] FP32 receives
+ * sum_p g[p][co] x[p + off(tap)][ci] and d_db [cout_pad] FP32 sum_p g[p][co],
+ * with g = d_g [nb][H][W][cout_pad] and x = d_x [nb][H][W][cin_pad] bf16
+ * device tensors.  Both sums run in a fixed order (bitwise reproducible).
+ * Uses the handle's reduction scratch.  Asynchronous on the handle's stream. */
+lb_status sg_weight_grad(sg_handle* h, int32_t layer, int32_t nb, const void* d_g, const void* d_x, float* d_dw,
+                         float* d_db);
+
 /* Separable [1 2 1]/4 x [1 2 1]/4 filter of `planes` device planes of
  * height x width (edge values replicated), d_in -> d_out (not in place),
  * asynchronous on hip_stream.  Applied to predictions before a warm start: it

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const 
                 const float v = acc[i][j][e];
                 if constexpr (MODE == 0) {
                     const float z = v + bias[n];
-                    Zout[o] = z;
+                    if (Zout) Zout[o] = z;
                     Yout[o] = bf16(act ? silu(z) : z);
                 } else {
                     Yout[o] = bf16(v * silu_grad(Zprev[o]));
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
                 const float v = acc[i][j][e];
                 if constexpr (MODE == 0) {
                     const float z = v + bias[n];
-                    Zout[o] = z;
+                    if (Zout) Zout[o] = z;
                     Yout[o] = bf16(act ? silu(z) : z);
                 } else {
                     Yout[o] = bf16(v * silu_grad(Zprev[o]));
@@ -712,6 +712,7 @@ struct sg_handle {
     hipStream_t s;
     long long t;  // Adam step counter
     int nb_last;  // samples in the last forward pass
+    bool z_valid; // the last forward pass stored every layer's pre-activation
 };
 
 namespace {
@@ -729,8 +730,56 @@ lb_status pack_weights(sg_handle* h) {
     return LB_OK;
 }
 
-// forward pass of nb samples listed in the device index array
-lb_status forward(sg_handle* h, const float* d_params, int nb) {
+// one convolution of layer l over P pixels: mode 0 forward (x -> z, y), mode 1
+// data gradient (g = dL/dz_l, zprev = z_{l-1} -> y = dL/dz_{l-1})
+lb_status launch_conv(sg_handle* h, int l, int mode, long long P, const bf16* x, const float* zprev, float* z,
+                      bf16* y) {
+    const int H = h->c.height, W = h->c.width;
+    const int Ci = mode == 0 ? kCinPad[l] : kCoutPad[l];   // K channels (per tap)
+    const int Co = mode == 0 ? kCoutPad[l] : kCinPad[l];   // output channels
+    const bf16* wk = ptr<bf16>(h, mode == 0 ? h->pl.wk_off[l] : h->pl.wt_off[l]);
+    const float* bias = mode == 0 ? ptr<float>(h, h->pl.w_off) + h->pl.boff[l] : nullptr;
+    const int act = mode == 0 && l + 1 < kLayers ? 1 : 0;
+    if (W % 128 == 0) {
+        const dim3 grid((unsigned)(P / 128), (unsigned)(Co / 64));
+        if (mode == 0)
+            hipLaunchKernelGGL(k_conv128<0>, grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, W, Ci, Co, act);
+        else
+            hipLaunchKernelGGL(k_conv128<1>, grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, W, Ci, Co, act);
+    } else {
+        const dim3 grid((unsigned)(P / 64), (unsigned)(Co / 64));
+        if (mode == 0)
+            hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, W, Ci, Co, act);
+        else
+            hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, W, Ci, Co, act);
+    }
+    SGCHK(hipGetLastError());
+    return LB_OK;
+}
+
+// weight and bias gradients of layer l over P pixels (split-K partials in the
+// workspace, then fixed-order reductions)
+lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const bf16* xin, float* dw, float* db) {
+    const int H = h->c.height, W = h->c.width;
+    const int Ci = kCinPad[l], Co = kCoutPad[l];
+    hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 3u * kSplit), dim3(256), 0, h->s,
+                       dz, xin, ptr<float>(h, h->pl.part_off), H, W, (int)P, Ci, Co);
+    SGCHK(hipGetLastError());
+    const long long n = 9ll * Co * Ci;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s,
+                       ptr<float>(h, h->pl.part_off), Ci, Co, dw);
+    SGCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
+    SGCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co, db);
+    SGCHK(hipGetLastError());
+    return LB_OK;
+}
+
+// forward pass of nb samples listed in the device index array; keep_z = false
+// (prediction) skips the FP32 pre-activation store of the hidden layers, which
+// only the backward pass reads
+lb_status forward(sg_handle* h, const float* d_params, int nb, bool keep_z = true) {
     const int H = h->c.height, W = h->c.width;
     const long long P = (long long)nb * H * W;
     hipLaunchKernelGGL(k_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, h->s, d_params,
@@ -738,20 +787,13 @@ lb_status forward(sg_handle* h, const float* d_params, int nb) {
     SGCHK(hipGetLastError());
     const bf16* x = ptr<bf16>(h, h->pl.x0_off);
     for (int l = 0; l < kLayers; ++l) {
-        if (W % 128 == 0)
-            hipLaunchKernelGGL(k_conv128<0>, dim3((unsigned)(P / 128), (unsigned)(kCoutPad[l] / 64)), dim3(256), 0,
-                               h->s, x, ptr<bf16>(h, h->pl.wk_off[l]), ptr<float>(h, h->pl.w_off) + h->pl.boff[l],
-                               (const float*)nullptr, ptr<float>(h, h->pl.z_off[l]), ptr<bf16>(h, h->pl.y_off[l]), H,
-                               W, kCinPad[l], kCoutPad[l], l + 1 < kLayers ? 1 : 0);
-        else
-            hipLaunchKernelGGL(k_conv<0>, dim3((unsigned)(P / 64), (unsigned)(kCoutPad[l] / 64)), dim3(256), 0, h->s,
-                               x, ptr<bf16>(h, h->pl.wk_off[l]), ptr<float>(h, h->pl.w_off) + h->pl.boff[l],
-                               (const float*)nullptr, ptr<float>(h, h->pl.z_off[l]), ptr<bf16>(h, h->pl.y_off[l]), H,
-                               W, kCinPad[l], kCoutPad[l], l + 1 < kLayers ? 1 : 0);
-        SGCHK(hipGetLastError());
+        float* z = keep_z || l + 1 == kLayers ? ptr<float>(h, h->pl.z_off[l]) : nullptr;
+        lb_status st = launch_conv(h, l, 0, P, x, nullptr, z, ptr<bf16>(h, h->pl.y_off[l]));
+        if (st != LB_OK) return st;
         x = ptr<bf16>(h, h->pl.y_off[l]);
     }
     h->nb_last = nb;
+    h->z_valid = keep_z;
     return LB_OK;
 }
 
@@ -774,31 +816,13 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
     SGCHK(hipGetLastError());
     float* grads = ptr<float>(h, h->pl.g_off);
     for (int l = L; l >= 0; --l) {
-        const int Ci = kCinPad[l], Co = kCoutPad[l];
         const bf16* xin = l == 0 ? ptr<bf16>(h, h->pl.x0_off) : ptr<bf16>(h, h->pl.y_off[l - 1]);
-        hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 3u * kSplit), dim3(256), 0,
-                           h->s, dz, xin, ptr<float>(h, h->pl.part_off), H, W, (int)P, Ci, Co);
-        SGCHK(hipGetLastError());
-        const long long n = 9ll * Co * Ci;
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s,
-                           ptr<float>(h, h->pl.part_off), Ci, Co, grads + h->pl.woff[l]);
-        SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
-        SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co,
-                           grads + h->pl.boff[l]);
-        SGCHK(hipGetLastError());
+        lb_status st = launch_wgrad(h, l, P, dz, xin, grads + h->pl.woff[l], grads + h->pl.boff[l]);
+        if (st != LB_OK) return st;
         if (l > 0) {
             bf16* dzn = ptr<bf16>(h, h->pl.dz_off[(L - l + 1) & 1]);
-            if (W % 128 == 0)
-                hipLaunchKernelGGL(k_conv128<1>, dim3((unsigned)(P / 128), (unsigned)(Ci / 64)), dim3(256), 0, h->s,
-                                   dz, ptr<bf16>(h, h->pl.wt_off[l]), (const float*)nullptr,
-                                   ptr<float>(h, h->pl.z_off[l - 1]), (float*)nullptr, dzn, H, W, Co, Ci, 0);
-            else
-                hipLaunchKernelGGL(k_conv<1>, dim3((unsigned)(P / 64), (unsigned)(Ci / 64)), dim3(256), 0, h->s, dz,
-                                   ptr<bf16>(h, h->pl.wt_off[l]), (const float*)nullptr,
-                                   ptr<float>(h, h->pl.z_off[l - 1]), (float*)nullptr, dzn, H, W, Co, Ci, 0);
-            SGCHK(hipGetLastError());
+            st = launch_conv(h, l, 1, P, dz, ptr<float>(h, h->pl.z_off[l - 1]), nullptr, dzn);
+            if (st != LB_OK) return st;
             dz = dzn;
         }
     }
@@ -879,6 +903,7 @@ lb_status sg_create(const sg_config* cfg, void* dev_workspace, size_t workspace_
     h->s = static_cast<hipStream_t>(hip_stream);
     h->t = 0;
     h->nb_last = 0;
+    h->z_valid = false;
     *out = h;
     return LB_OK;
 }
@@ -961,7 +986,7 @@ lb_status sg_predict(sg_handle* h, const float* d_params, int32_t n, float* d_ou
         const int nb = std::min(h->c.batch, n - s0);
         for (int b = 0; b < nb; ++b) idx[b] = s0 + b;
         lb_status st = set_indices(h, idx.data(), nb);
-        if (st == LB_OK) st = forward(h, d_params, nb);
+        if (st == LB_OK) st = forward(h, d_params, nb, false);
         if (st != LB_OK) return st;
         const long long P = (long long)nb * H * W;
         hipLaunchKernelGGL(k_unpack_out, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, h->s,
@@ -975,6 +1000,8 @@ lb_status sg_predict(sg_handle* h, const float* d_params, int32_t n, float* d_ou
 
 lb_status sg_layer_output(sg_handle* h, int32_t layer, float* host_out) {
     if (!h || !host_out || layer < 0 || layer >= kLayers) return sgfail(LB_EINVAL, "bad argument");
+    if (!h->z_valid && layer + 1 < kLayers)
+        return sgfail(LB_ESTATE, "the last forward pass (a prediction) kept only the output layer's pre-activation");
     const size_t n = (size_t)h->nb_last * h->c.height * h->c.width * kCoutPad[layer];
     SGCHK(hipMemcpyAsync(host_out, ptr<float>(h, h->pl.z_off[layer]), 4 * n, hipMemcpyDeviceToHost, h->s));
     SGCHK(hipStreamSynchronize(h->s));
@@ -993,6 +1020,26 @@ lb_status sg_layer_input(sg_handle* h, int32_t layer, float* host_out) {
         std::memcpy(&host_out[k], &bits, 4);
     }
     return LB_OK;
+}
+
+lb_status sg_conv(sg_handle* h, int32_t layer, int32_t mode, int32_t nb, const void* d_in, const float* d_zprev,
+                  float* d_z, void* d_out) {
+    if (!h || layer < 0 || layer >= kLayers || (mode != 0 && mode != 1)) return sgfail(LB_EINVAL, "bad argument");
+    if (nb < 1 || nb > h->c.batch) return sgfail(LB_EINVAL, "nb must lie in 1..batch");
+    if (!d_in || !d_out) return sgfail(LB_EINVAL, "d_in and d_out are required");
+    if (mode == 1 && (layer == 0 || !d_zprev)) return sgfail(LB_EINVAL, "the data gradient needs layer >= 1 and d_zprev");
+    const long long P = (long long)nb * h->c.height * h->c.width;
+    return launch_conv(h, layer, mode, P, static_cast<const bf16*>(d_in), mode == 1 ? d_zprev : nullptr,
+                       mode == 0 ? d_z : nullptr, static_cast<bf16*>(d_out));
+}
+
+lb_status sg_weight_grad(sg_handle* h, int32_t layer, int32_t nb, const void* d_g, const void* d_x, float* d_dw,
+                         float* d_db) {
+    if (!h || layer < 0 || layer >= kLayers) return sgfail(LB_EINVAL, "bad argument");
+    if (nb < 1 || nb > h->c.batch) return sgfail(LB_EINVAL, "nb must lie in 1..batch");
+    if (!d_g || !d_x || !d_dw || !d_db) return sgfail(LB_EINVAL, "NULL device array");
+    const long long P = (long long)nb * h->c.height * h->c.width;
+    return launch_wgrad(h, layer, P, static_cast<const bf16*>(d_g), static_cast<const bf16*>(d_x), d_dw, d_db);
 }
 
 lb_status sg_smooth(const float* d_in, float* d_out, int32_t planes, int32_t height, int32_t width,

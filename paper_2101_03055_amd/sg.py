@@ -38,6 +38,8 @@ def lib():
             "sg_predict": [vp, vp, i32, vp],
             "sg_layer_output": [vp, i32, vp],
             "sg_layer_input": [vp, i32, vp],
+            "sg_conv": [vp, i32, i32, i32, vp, vp, vp, vp],
+            "sg_weight_grad": [vp, i32, i32, vp, vp, vp, vp],
             "sg_free": [vp],
             "sg_smooth": [vp, vp, i32, i32, i32, vp],
             "sg_destagger": [vp, i32, i32, i32, vp],
@@ -179,6 +181,17 @@ class Surrogate:
         out = np.empty((self.cfg.batch, self.cfg.height, self.cfg.width, ci), dtype=np.float32)
         _check(lib().sg_layer_input(self.handle, l, out.ctypes.data))
         return out
+
+    def conv(self, layer: int, mode: int, nb: int, d_in, d_out, d_z=None, d_zprev=None):
+        """One convolution of the training pass on CUDA tensors (sg_conv): bf16
+        tensors d_in/d_out, float32 d_z (forward) or d_zprev (data gradient)."""
+        ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+        _check(lib().sg_conv(self.handle, layer, mode, nb, ptr(d_in), ptr(d_zprev), ptr(d_z), ptr(d_out)))
+
+    def weight_grad(self, layer: int, nb: int, d_g, d_x, d_dw, d_db):
+        """Weight and bias gradients of one layer on CUDA tensors (sg_weight_grad)."""
+        _check(lib().sg_weight_grad(self.handle, layer, nb, C.c_void_p(d_g.data_ptr()), C.c_void_p(d_x.data_ptr()),
+                                    C.c_void_p(d_dw.data_ptr()), C.c_void_p(d_db.data_ptr())))
 
     def close(self):
         if getattr(self, "handle", None) is not None:
