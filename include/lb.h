@@ -170,6 +170,21 @@ lb_status lb_moments_device(lb_handle* h, double* d_phi, double* d_u, double* d_
  * Synchronises the stream. */
 lb_status lb_residual(lb_handle* h, double* res);
 
+/* lb_residual for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * the same kernels, result and error behaviour, but the reduction's partial
+ * records and result record live in a library-held device array of fixed size
+ * (128.5 KiB: 1024 partial records of 16 doubles plus 64 doubles) instead of
+ * the handle's workspace.  Allocates nothing; grids of any size fit (the first
+ * pass uses at most 1024 workgroups), a larger request would return LB_EINVAL.
+ * Each GPU holds one copy of the array until the process ends, shared by every
+ * call on that GPU and keeping the last call's contents (every value a call
+ * reads it first writes).  Calls through this entry point on one GPU are
+ * serialised by a host lock held until the call's stream has finished with the
+ * array; work that wrote the array concurrently (another process has its own
+ * copy) would race.  Synchronises the stream. */
+lb_status lb_residual_noalloc(lb_handle* h, double* res);
+
 /* Steady solve: repeats { lb_step(check_every); lb_residual } until every
  * residual component is below tol (criterion of Sec. 3.1.1, absolute values),
  * or max_steps steps have been taken, or a field turns non-finite.

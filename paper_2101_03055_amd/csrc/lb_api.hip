@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -366,6 +367,7 @@ struct lb_handle {
     int64_t t;           // steps taken
     int parity;          // 0: canonical layout (own slots); 1: layout left by an even step
     int has_snapshot;
+    int device;          // device current at lb_init (the workspace's)
     Launch lc;
     // cached graph of kGraphSteps single-step launches (FP32/FP64, one step
     // per launch); rebuilt when the tile shape changes
@@ -443,6 +445,46 @@ lb_status lb_workspace_bytes(const lb_params* params, size_t* bytes) {
     return LB_OK;
 }
 
+// ---- library-held reduction scratch (lb_residual_noalloc) -------------------
+// Partial records of the first reduction pass (at most kRedBlocks of kRedWidth
+// doubles) and the result record, for callers that cannot allocate.  Each GPU
+// holds its own copy; host code reaches it only through the device address
+// that hipGetSymbolAddress returns for that GPU (the array's name is a host
+// stand-in there).
+constexpr size_t kScratchDoubles = (size_t)kRedBlocks * kRedWidth + 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                    // guards the table
+double* g_scratch[kMaxDevices] = {};        // device address of `scratch` per device
+std::mutex g_scratch_use[kMaxDevices];      // one lb_residual_noalloc at a time per device
+}  // namespace
+
+// Looks up the device address of `scratch` on `dev` once (with dev current).
+static hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[dev] = static_cast<double*>(ptr);
+    return hipSuccess;
+}
+
+static double* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
+
 lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace_bytes, void* hip_stream,
                   const double* phi0, const double* u0, const double* p0, lb_handle** out) {
     if (!out) return fail(LB_EINVAL, "out is NULL");
@@ -472,6 +514,14 @@ lb_status lb_init(const lb_params* params, void* dev_workspace, size_t workspace
     h->parity = 0;
     h->has_snapshot = 0;
     h->lc = default_launch(h->p);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(LB_EDEVICE, "lb_init: hipGetDevice failed");
+    }
+    if (scratch_setup(h->device) != hipSuccess) {
+        delete h;
+        return fail(LB_EDEVICE, "lb_init: device address of the reduction scratch array not available");
+    }
 
     double* stage = (double*)at(h->ws, L.stage_off);
     hipError_t e = hipMemcpyAsync(stage, phi0, m * N * 8, hipMemcpyHostToDevice, h->stream);
@@ -596,6 +646,35 @@ lb_status lb_residual(lb_handle* h, double* res) {
     double out[64];
     HIPCHK(hipMemcpyAsync(out, at(h->ws, h->L.res_off), sizeof(double) * (3 * Q + 1), hipMemcpyDeviceToHost,
                           h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int q = 0; q < Q; ++q) res[q] = mode == 0 ? out[2 * Q + 1 + q] : HUGE_VAL;
+    h->has_snapshot = 1;
+    if (out[2 * Q] != 0.0) return fail(LB_ENONFINITE, "non-finite values at %.0f nodes", out[2 * Q]);
+    return LB_OK;
+}
+
+lb_status lb_residual_noalloc(lb_handle* h, double* res) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!res) return fail(LB_EINVAL, "res is NULL");
+    const int Q = h->p.m + 2;
+    const size_t need = (size_t)reduce_blocks(h->L.N) * kRedWidth + (size_t)(3 * Q + 1);
+    if (need > kScratchDoubles)
+        return fail(LB_EINVAL, "lb_residual_noalloc: %zu doubles of scratch needed, the array holds %zu", need,
+                    kScratchDoubles);
+    double* sp = scratch_ptr(h->device);
+    if (!sp) return fail(LB_EDEVICE, "lb_residual_noalloc: no scratch address for device %d", h->device);
+    double* part = sp;
+    double* rec = sp + (size_t)kRedBlocks * kRedWidth;
+    // the array is shared by every call on this device: hold it until this
+    // call's stream has finished reading it
+    std::lock_guard<std::mutex> use(g_scratch_use[h->device]);
+    const int mode = h->has_snapshot ? 0 : 1;
+    hipError_t e = h->p.model == LB_MODEL_CDE
+                       ? launch_cde_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, mode, h->stream, part, rec)
+                       : launch_reduce(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, mode, h->stream, part, rec);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_residual_noalloc: %s", hipGetErrorString(e));
+    double out[64];
+    HIPCHK(hipMemcpyAsync(out, rec, sizeof(double) * (3 * Q + 1), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     for (int q = 0; q < Q; ++q) res[q] = mode == 0 ? out[2 * Q + 1 + q] : HUGE_VAL;
     h->has_snapshot = 1;

@@ -423,10 +423,10 @@ hipError_t launch_cde_export(const lb_params& p, const Layout& L, void* ws, cons
 }
 
 hipError_t launch_cde_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                             const KParams<float>& kf, bool odd, int mode, hipStream_t s) {
+                             const KParams<float>& kf, bool odd, int mode, hipStream_t s, double* part, double* res) {
     const int nb = reduce_blocks(L.N);
-    double* part = (double*)at(ws, L.part_off);
-    double* res = (double*)at(ws, L.res_off);
+    if (!part) part = (double*)at(ws, L.part_off);
+    if (!res) res = (double*)at(ws, L.res_off);
     hipError_t e = dispatch_cde(p, [&]<class S, int M>() -> hipError_t {
         using T = typename St<S>::T;
         const S* pop = (const S*)at(ws, L.pop_off);

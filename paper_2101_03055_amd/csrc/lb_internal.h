@@ -83,8 +83,11 @@ hipError_t launch_cde_moments(const lb_params& p, const Layout& L, void* ws, con
 hipError_t launch_cde_export(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                              const KParams<float>& kf, bool odd, int plane_begin, int plane_count, double* out,
                              hipStream_t s);
+// part / res: partial records (reduce_blocks(L.N) x kRedWidth doubles) and the
+// result record; nullptr selects the workspace's own (L.part_off, L.res_off)
 hipError_t launch_cde_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                             const KParams<float>& kf, bool odd, int mode, hipStream_t s);
+                             const KParams<float>& kf, bool odd, int mode, hipStream_t s, double* part = nullptr,
+                             double* res = nullptr);
 hipError_t launch_wall_flux(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                             const KParams<float>& kf, bool odd, int side, double* out, hipStream_t s);
 hipError_t launch_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
@@ -101,9 +104,11 @@ hipError_t launch_import(const lb_params& p, const Layout& L, void* ws, const KP
 // converts the previous-step source planes between storage modes
 hipError_t launch_copy_sold(const lb_params& ps, const Layout& Ls, void* wss, const lb_params& pd,
                             const Layout& Ld, void* wsd, hipStream_t s);
-// mode 0: residual (updates the snapshot), mode 1: snapshot only, mode 2: mass
+// mode 0: residual (updates the snapshot), mode 1: snapshot only, mode 2: mass;
+// part / res as for launch_cde_reduce
 hipError_t launch_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                         const KParams<float>& kf, bool odd, int mode, hipStream_t s);
+                         const KParams<float>& kf, bool odd, int mode, hipStream_t s, double* part = nullptr,
+                         double* res = nullptr);
 
 // ---- batched sweep ---------------------------------------------------------
 // Per-cavity record visible to the batched kernels (offsets in bytes from the

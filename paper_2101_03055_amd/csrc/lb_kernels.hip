@@ -707,10 +707,10 @@ int reduce_blocks(size_t N) {
 }
 
 hipError_t launch_reduce(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                         const KParams<float>& kf, bool odd, int mode, hipStream_t s) {
+                         const KParams<float>& kf, bool odd, int mode, hipStream_t s, double* part, double* res) {
     const int nb = reduce_blocks(L.N);
-    double* part = (double*)at(ws, L.part_off);
-    double* res = (double*)at(ws, L.res_off);
+    if (!part) part = (double*)at(ws, L.part_off);
+    if (!res) res = (double*)at(ws, L.res_off);
     return dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
         const S* pop = (const S*)at(ws, L.pop_off);
         double* snap = (double*)at(ws, L.snap_off);

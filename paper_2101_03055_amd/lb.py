@@ -79,6 +79,7 @@ def lib():
             "lb_moments": [vp, vp, vp, vp],
             "lb_moments_device": [vp, vp, vp, vp],
             "lb_residual": [vp, vp],
+            "lb_residual_noalloc": [vp, vp],
             "lb_mass": [vp, vp],
             "lb_populations": [vp, vp, vp],
             "lb_time": [vp, C.POINTER(i64)],
@@ -222,6 +223,16 @@ def lb_residual(h, m: int):
     """Returns (res[m + 2], status); status LB_ENONFINITE is reported, not raised."""
     res = np.empty(m + 2)
     st = lib().lb_residual(h, res.ctypes.data)
+    if st not in (LB_OK, LB_ENONFINITE):
+        _check(st)
+    return res, st
+
+
+def lb_residual_noalloc(h, m: int):
+    """lb_residual through the entry point that allocates nothing (library-held
+    scratch array); returns (res[m + 2], status) like lb_residual."""
+    res = np.empty(m + 2)
+    st = lib().lb_residual_noalloc(h, res.ctypes.data)
     if st not in (LB_OK, LB_ENONFINITE):
         _check(st)
     return res, st
