@@ -1,25 +1,28 @@
 """Throughput of the fused collide-stream step on one MI355X.
 
-Workload (headline): the chemotaxis-fluid plume, 512 x 256 nodes, m = 2
-(bacteria n, oxygen c) on D2Q5 + the D2Q9 fluid, step cut-off r(c), oxygen
-consumption source, buoyancy, free-slip/Dirichlet top, no-slip/no-flux
-bottom, periodic sides; populations stored as FP32 deviations and collided in
-FP32.  One step = one lattice update of every node (the full fused update);
-the FP64 steady-state residual is evaluated every 1000 steps inside the timed
-region, as a steady solve does.  Inputs are resident in HBM before timing.
+Workload (headline): the batched parameter sweep of double-diffusive cavities
+-- 256 cavities with Soret/Dufour cross-diffusion (m = 2: T and C on D2Q5 plus
+the D2Q9 fluid), sides drawn from {64, 96, ..., 256}, Ra log-uniform in
+[1e3, 1e6], Le U[1, 5], Nc U[-2, 2], Sr, Df U[0, 0.5], Pr 0.71 (seed 4): 8.0 M
+nodes, a 608 MB FP32 state, well beyond the 256 MB MALL.  Populations are
+stored as FP32 deviations and collided in FP32; one step = one launch over
+the tile list of every cavity (autotuned tile shape).  Every full window of
+1000 steps inside the timed region ends with the FP64 per-cavity residual of
+a steady sweep.  Inputs are resident in HBM before timing.
 
 Prints one JSON line.  Besides the contract's fields:
-  roofline       algorithmic bytes of the step kernel per launch / its mean
-                 duration (HIP events on the solver's stream, back-to-back
+  roofline       algorithmic bytes of the batched step kernel per launch / its
+                 mean duration (HIP events on the batch's stream, back-to-back
                  launches) against the HBM peak; `traffic` from rocprofv3
                  FETCH_SIZE/WRITE_SIZE (profiles/*.traffic.json) while the kernel
                  sources are unchanged, else null;
-  cpu_baseline   the FP64 CPU oracle on a bounded sample of the same workload;
-  fp64           the same workload with FP64 storage;
-  hbm_sweep      periodic 4096^2 grids (FP64/FP32/FP16 storage): working sets
-                 well beyond the caches, where the HBM fraction is meaningful;
-  batched_sweep  256 double-diffusive cavities of uneven size (64..256) in one
-                 launch per step (FP32, autotuned tile);
+  cpu_baseline   the FP64 CPU oracle on a bounded sample of the same workload
+                 (a stated subset of the cavities);
+  production_run the same batch through lbb_run over 2000 steps: residual
+                 windows of 1000 steps, snapshots included;
+  plume          the chemotaxis-fluid plume, 512 x 256 (FP32 and FP64): a
+                 21 MB state resident in the MALL (cache-resident rates);
+  hbm_sweep      periodic 4096^2 grids (FP64/FP32/FP16 storage, BGK and MRT);
   steady_warm_vs_cold  double-diffusive cavities at 128^2 solved to residual
                  1e-8 (batched FP32 phase + FP64 finish) from rest and from the
                  CNN surrogate's prediction (weights from the surrogate study);
@@ -27,7 +30,7 @@ Prints one JSON line.  Besides the contract's fields:
   cde_sweep      the no-fluid model (prescribed velocity) on 4096^2;
   sweep_3d       the 3-D path (D3Q7 + D3Q19) on a periodic 256^3 box.
 Long runs of 2-D steps are replayed by the library as HIP graphs of 64 launches.
-Modes for profiling: --mode pmc | copy | sweep | batch | surrogate | cde | 3d.
+Modes for profiling: --mode pmc | copy | sweep | batch | plume | surrogate | cde | 3d.
 """
 from __future__ import annotations
 
@@ -44,7 +47,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS (fluid+m scalars) & HBM GB/s vs peak; wall time to steady: warm vs cold"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_chemotaxis_plume_512x256_f32.traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bstep_ddc_sweep_256_cavities_f32.traffic.json")
+PLUME_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_chemotaxis_plume_512x256_f32.traffic.json")
 WEIGHTS = os.path.join(ROOT, "paper_2101_03055_amd", "data", "surrogate_ddc128.npz")
 
 
@@ -144,12 +148,12 @@ def cpu_baseline(wl, phi0, u0, p0, budget_s=15.0, single_s=5.0):
             "cpu_model": cpu_model()}
 
 
-def traffic_record():
+def traffic_record(path=TRAFFIC_FILE):
     """Counter-measured bytes per launch, if they describe the current kernel sources."""
     try:
         from paper_2101_03055_amd import profsum
 
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
         if rec.get("source_hash") == profsum.source_hash():
             return rec
@@ -238,18 +242,85 @@ def sweep_3d(W, torch, n=256):
     return out
 
 
-def batched_sweep(W, lb, torch):
+def sweep_cases(W):
+    """The 256 cavities of the batched sweep (seed 4) and their node count."""
     pds = W.sweep_params(256, seed=4)
     cases = [W.ddc_case(pd) for pd in pds]
-    nodes = sum(c[0]["nx"] * c[0]["ny"] for c in cases)
+    return cases, sum(c[0]["nx"] * c[0]["ny"] for c in cases)
+
+
+def time_batch(b, steps, window=1000):
+    """Wall time of exactly `steps` batched steps on the batch's stream; every
+    full window of `window` steps runs through lbb_run (the steady sweep's
+    loop: snapshot, steps, FP64 per-cavity residual), a shorter remainder as
+    plain steps.  Returns (seconds, residual evaluations)."""
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    done = n_res = 0
+    e0.record(b.stream)
+    while done < steps:
+        k = min(window, steps - done)
+        if k == window:
+            b.run(tol=1e-300, check_every=window, max_steps=window)  # never converges: all cavities keep running
+            n_res += 1
+        else:
+            b.step(k)
+        done += k
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, n_res
+
+
+def batch_headline(W, lb, torch, steps, warmup):
+    """The batched sweep: autotune, warm up, time `steps` steps, then the
+    step kernel's mean launch duration and a 2000-step production run."""
+    cases, nodes = sweep_cases(W)
     b = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
     tx, ty, us = b.autotune(10)
-    kt = kernel_time(b.step, b.stream, 200)
-    bb = bytes_per_lu(2, "f32", 0)
-    ach = bb * nodes / kt / 1e9
-    return {"cavities": len(cases), "nodes": nodes, "state_MB": round(nodes * 19 * 4 / 1e6, 1),
-            "tile": [tx, ty], "MLUPS": round(nodes / kt / 1e6, 1), "achieved_GBs": round(ach, 1),
-            "frac": round(ach / HBM_PEAK_GBS, 4), "mean_launch_us": round(kt * 1e6, 2)}
+    b.step(warmup + (warmup & 1))
+    el, n_res = time_batch(b, steps)
+    kt = kernel_time(b.step, b.stream, 256)
+    el_prod, n_prod = time_batch(b, 2000)
+    st = [b.time(i)[1] for i in range(b.count)]
+    return b, {"cases": cases, "nodes": nodes, "tile": [tx, ty], "autotune_us": round(us, 2),
+               "elapsed": el, "residual_evals": n_res, "kernel_s": kt,
+               "production_run": {"steps": 2000, "residual_windows": n_prod, "seconds": round(el_prod, 4),
+                                  "MLUPS": round(nodes * 2000 / el_prod / 1e6, 1),
+                                  "note": "lbb_run windows of 1000 steps: snapshot + steps + FP64 residual of "
+                                          "every cavity"},
+               "diverged": sum(1 for v in st if v == 2)}
+
+
+def cpu_baseline_sweep(W, cases, stride=16, budget_s=15.0):
+    """The FP64 oracle on every `stride`-th cavity of the sweep (all host
+    threads), the same number of steps on each, sized to ~budget_s seconds."""
+    from oracle import oracle as O
+
+    sub = cases[::stride]
+    nodes = sum(c[0]["nx"] * c[0]["ny"] for c in sub)
+    probe = O.Oracle(*sub[0])
+    probe.step(3)
+    t0 = time.perf_counter()
+    probe.step(10)
+    rate = sub[0][0]["nx"] * sub[0][0]["ny"] * 10 / max(time.perf_counter() - t0, 1e-6)
+    del probe
+    steps = max(2, int(budget_s * rate / nodes))
+    el = 0.0
+    for c in sub:
+        o = O.Oracle(*c)
+        t0 = time.perf_counter()
+        o.step(steps)
+        el += time.perf_counter() - t0
+        del o
+    sizes = sorted({c[0]["nx"] for c in sub})
+    return {"value": round(nodes * steps / el / 1e6, 2), "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "sample": f"ddc_sweep_256_cavities: cavities 0, {stride}, ..., {stride * (len(sub) - 1)} "
+                      f"({len(sub)} of 256, sides {sizes[0]}..{sizes[-1]}, {nodes} nodes), {steps} steps each "
+                      f"from rest, FP64 oracle ({el:.1f} s)",
+            "cpu_model": cpu_model()}
 
 
 def steady_warm_vs_cold(W, torch, n_cases=16, max_steps=600_000, n_plain=4):
@@ -365,14 +436,15 @@ def surrogate_bench(torch, epochs=4, samples=64):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "surrogate", "cde", "3d"], default="bench",
-                    help="pmc: only the timed workload's step kernel (for counter runs); "
+    ap.add_argument("--mode", choices=["bench", "pmc", "copy", "sweep", "batch", "plume", "surrogate", "cde", "3d"],
+                    default="bench",
+                    help="pmc: only the plume's step kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy to calibrate the byte counters; "
-                         "sweep / batch: only the 4096^2 or the batched-cavity leg (for profiles)")
+                         "batch / plume / sweep / surrogate / cde / 3d: one leg only (for profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -405,56 +477,88 @@ def main():
         print(json.dumps({"sweep_3d": sweep_3d(W, torch)}), flush=True)
         return
     if args.mode == "batch":
-        print(json.dumps({"batched_sweep": batched_sweep(W, lb, torch)}), flush=True)
+        cases, nodes = sweep_cases(W)
+        b = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
+        tx, ty, _ = b.autotune(10)  # 7 tile shapes x (2 + 10) steps
+        kt = kernel_time(b.step, b.stream, 256)
+        print(json.dumps({"launches": 7 * 12 + 256, "timed_launches": 256, "tile": [tx, ty],
+                          "mean_launch_us": round(kt * 1e6, 2),
+                          "bytes_per_launch": bytes_per_lu(2, "f32", 0) * nodes}), flush=True)
         return
-    wl, phi0, u0, p0 = W.chemotaxis_plume()
-    N = wl["nx"] * wl["ny"]
-    bpl = bytes_per_lu(2, "f32", 1)
+    if args.mode == "plume":
+        print(json.dumps({"plume": plume(W, lb, torch, 4000, 200)}), flush=True)
+        return
     if args.mode == "pmc":
+        wl, phi0, u0, p0 = W.chemotaxis_plume()
         solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
         solver.step(200)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_steps": 200, "bytes_per_launch": bpl * N}), flush=True)
+        print(json.dumps({"pmc_steps": 200, "bytes_per_launch": bytes_per_lu(2, "f32", 1) * wl["nx"] * wl["ny"]}),
+              flush=True)
         return
 
-    solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
-    el, n_res = time_steps(solver, args.steps, args.warmup)
-    mlups = N * args.steps / el / 1e6
-    kt = kernel_time(solver.step, solver.stream, 1000)
-    achieved = bpl * N / kt / 1e9
+    b, r = batch_headline(W, lb, torch, args.steps, args.warmup)
+    nodes = r["nodes"]
+    bpl = bytes_per_lu(2, "f32", 0)
+    kt = r["kernel_s"]
+    achieved = bpl * nodes / kt / 1e9
     tr = traffic_record()
+    el = r["elapsed"]
     out = {
-        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "metric": METRIC, "value": round(nodes * args.steps / el / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded PCG64 noise on n0; the paper's plume parameters)",
-        "config": {"workload": wl["name"], "nx": wl["nx"], "ny": wl["ny"], "m": 2,
-                   "storage": "f32 deviations from phi_ref = (1, 1) and rho0", "collision": "bgk",
-                   "residual_every": 1000, "residual_evals_timed": n_res},
+        "data": "synthetic (seeded sweep law; cavities start from rest as in Sec. 3.2)",
+        "config": {"workload": "ddc_sweep_256_cavities", "cavities": 256, "sides": "64..256 step 32",
+                   "nodes": nodes, "state_MB": round(nodes * 19 * 4 / 1e6, 1), "m": 2,
+                   "storage": "f32 deviations from phi_ref = (0.5, 0.5) and rho0", "collision": "bgk",
+                   "tile": r["tile"], "residual_every": 1000, "residual_evals_timed": r["residual_evals"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(tr["traffic_bytes_per_launch"]) if tr else None,
-                     "kernel": "k_step (even/odd AA-pattern launches alternate)",
-                     "bytes_per_launch": bpl * N, "mean_launch_us": round(kt * 1e6, 3),
-                     "note": "21 MB working set: resident in the 256 MB MALL; hbm_sweep gives the HBM-bound case"},
+                     "kernel": "k_bstep (even/odd AA-pattern launches alternate)",
+                     "bytes_per_launch": bpl * nodes, "bytes_per_node": bpl, "mean_launch_us": round(kt * 1e6, 3)},
+        "production_run": r["production_run"],
+        "diverged_cavities": r["diverged"],
     }
+    cases = r["cases"]
+    b.close()
+    del b
+    torch.cuda.empty_cache()
     if not args.no_extra:
-        s64 = lb.Solver(wl, phi0, u0, p0, storage="f64")
-        el64, _ = time_steps(s64, 2000, 100)
-        kt64 = kernel_time(s64.step, s64.stream, 500)
-        out["fp64"] = {"value": round(N * 2000 / el64 / 1e6, 1), "unit": "MLUPS", "mean_launch_us": round(kt64 * 1e6, 3),
-                       "achieved_GBs": round(bytes_per_lu(2, "f64", 1) * N / kt64 / 1e9, 1)}
-        del s64
+        out["plume"] = plume(W, lb, torch, 4000, 200)
         out["hbm_sweep"] = hbm_sweep(W, lb, torch)
-        out["batched_sweep"] = batched_sweep(W, lb, torch)
         out["cde_sweep"] = cde_sweep(W, lb, torch)
         torch.cuda.empty_cache()
         out["sweep_3d"] = sweep_3d(W, torch)
         out["steady_warm_vs_cold"] = steady_warm_vs_cold(W, torch)
         out["surrogate"] = surrogate_bench(torch)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, phi0, u0, p0)
+        out["cpu_baseline"] = cpu_baseline_sweep(W, cases)
     print(json.dumps(out), flush=True)
+
+
+def plume(W, lb, torch, steps, warmup):
+    """The chemotaxis-fluid plume 512 x 256 (FP32 and FP64): its 21 MB state
+    stays in the MALL, so its rates are cache-resident, not HBM-bound."""
+    wl, phi0, u0, p0 = W.chemotaxis_plume()
+    N = wl["nx"] * wl["ny"]
+    bpl = bytes_per_lu(2, "f32", 1)
+    solver = lb.Solver(wl, phi0, u0, p0, storage="f32", phi_ref=[1.0, 1.0])
+    el, n_res = time_steps(solver, steps, warmup)
+    kt = kernel_time(solver.step, solver.stream, 1024)
+    tr = traffic_record(PLUME_TRAFFIC_FILE)
+    out = {"workload": wl["name"], "nx": wl["nx"], "ny": wl["ny"], "steps": steps, "residual_evals": n_res,
+           "MLUPS": round(N * steps / el / 1e6, 1), "mean_launch_us": round(kt * 1e6, 3),
+           "bytes_per_launch": bpl * N, "effective_GBs": round(bpl * N / kt / 1e9, 1),
+           "traffic": round(tr["traffic_bytes_per_launch"]) if tr else None,
+           "bound": "cache-resident (21 MB state in the 256 MB MALL)"}
+    s64 = lb.Solver(wl, phi0, u0, p0, storage="f64")
+    el64, _ = time_steps(s64, 2000, 100)
+    kt64 = kernel_time(s64.step, s64.stream, 512)
+    out["fp64"] = {"MLUPS": round(N * 2000 / el64 / 1e6, 1), "mean_launch_us": round(kt64 * 1e6, 3),
+                   "effective_GBs": round(bytes_per_lu(2, "f64", 1) * N / kt64 / 1e9, 1)}
+    return out
 
 
 if __name__ == "__main__":
