@@ -32,8 +32,15 @@
  *     F_0 being the rest component of Eq. force (its second, expanded form
  *     and Eq. sum-p drop the factor W_0 and disagree in sign).  varphi != 0
  *     needs BGK (the correction uses the single fluid rate).
- *   - gamma = 0 and the first-order backward difference for d/dt S (text
- *     after Eq. source); S_old at t = 0 is S(phi0).
+ *   - D-bar of Eq. evolution12, delta d/dt + gamma c_i . grad on the discrete
+ *     source S_i = W_i S (Eq. source): d/dt S by the first-order backward
+ *     difference (text after Eq. source), S_old at t = 0 being S(phi0); gamma
+ *     is diagonal (gamma[a]; 0 in the paper's runs).  The paper gives no
+ *     discretisation of c_i . grad S_i: it is taken as W_i c_i . grad S with
+ *     grad S by central differences of the previous step's source field
+ *     S(x +- e_d, t - dt), the field the step already keeps; across a wall
+ *     the node's own value stands in for the missing neighbour (periodic
+ *     sides wrap).
  *   - Initial populations: scalar equilibrium of (phi0, u0); fluid equilibrium
  *     of (p0, u0 - F(phi0)/2), so that Eq. sum-u gives u0 at t = 0.
  *   - Half-way walls; anti-bounce-back f_opp = -f*_i + 2 W_i phi_w for
@@ -86,6 +93,7 @@ typedef struct orc_cfg {
     double wall[4 * ORC_MAXM];          /* Dirichlet values [side][alpha] */
     double lam[ORC_MAXM * ORC_MAXM];    /* lambda of Eq. feq-phi, row-major (identity in Sec. 3) */
     double varphi;                      /* varphi of Eq. force (0 in Sec. 3) */
+    double gamma[ORC_MAXM];             /* diagonal of gamma in D-bar of Eq. evolution12 (0 in Sec. 3) */
 } orc_cfg;
 
 /* ---- lattices (Sec. 2, D2Q5 and D2Q9 tables) ---------------------------- */
@@ -397,7 +405,7 @@ static void node_moments(const orc_cfg *cfg, const double *f /*[m][5]*/, const d
 
 /* ---- collision of one node ----------------------------------------------- */
 static int collide_node(const orc_cfg *cfg, const double Minv[9][9], const double *f,
-                        const double *h, const double *Sold, double *fs, double *hs,
+                        const double *h, const double *Sold, const double *gradS, double *fs, double *hs,
                         double *Snew) {
     int m = cfg->m;
     node_macro mc;
@@ -449,14 +457,19 @@ static int collide_node(const orc_cfg *cfg, const double Minv[9][9], const doubl
     orc_source_pop(m, S, Si);
     orc_source_pop(m, Sold, Si_old);
 
-    /* Eq. evolution12 with gamma = 0: (dt^2/2) Dbar S_i = (dt/2)(S_i(t) - S_i(t - dt)) */
+    /* Eq. evolution12: (dt^2/2) Dbar_{ab} S_{i,b} with Dbar = delta d/dt + gamma c_i . grad:
+     * d/dt S_i = (S_i(t) - S_i(t - dt))/dt and, gamma being diagonal,
+     * gamma_a c_i . grad S_{i,a} = gamma_a W_i c_i . grad S_a (S_i = W_i S, Eq. source) */
     for (int a = 0; a < m; ++a)
         for (int i = 0; i < 5; ++i) {
             double coll = 0.0;
             for (int b = 0; b < m; ++b) coll += omega[a * m + b] * (f[b * 5 + i] - feq[b * 5 + i]);
             double dS = (cfg->mutation == 3) ? 0.0 : (Si[a * 5 + i] - Si_old[a * 5 + i]);
+            double cgrad = e5[i][0] * gradS[a * 2] + e5[i][1] * gradS[a * 2 + 1];
+            double gam = (cfg->mutation == 15) ? -cfg->gamma[a] : cfg->gamma[a];
+            double dbar = dS / dt + gam * W5x(i, cgrad);
             fs[a * 5 + i] = f[a * 5 + i] - coll + dt * Si[a * 5 + i] + dt * Gi[a * 5 + i]
-                            + (dt * dt / 2.0) * dS / dt;
+                            + (dt * dt / 2.0) * dbar;
         }
     for (int a = 0; a < m; ++a) Snew[a] = S[a];
 
@@ -586,19 +599,37 @@ int orc_step(const orc_cfg *cfg, double *f, double *h, double *Sold, int64_t nst
     if (!orc_mrt_basis(M, Minvf)) { free(f2); free(h2); return 0; }
     for (int r = 0; r < 9; ++r)
         for (int c = 0; c < 9; ++c) Minv[r][c] = Minvf[r * 9 + c];
+    /* the previous step's source field S(x, t - dt), read at the neighbours
+     * by the gamma term (Sold itself is overwritten node by node) */
+    double *Sprev = (double *)malloc(sizeof(double) * N * m);
+    if (!Sprev) { free(f2); free(h2); return 0; }
     int ok = 1;
     for (int64_t s = 0; s < nsteps && ok; ++s) {
+        memcpy(Sprev, Sold, sizeof(double) * N * m);
 #pragma omp parallel for schedule(static) reduction(&& : ok)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 size_t n = nidx(cfg, x, y);
                 double fl[ORC_MAXM * 5], hl[9], so[ORC_MAXM], fs[ORC_MAXM * 5], hs[9], sn[ORC_MAXM];
+                double gs[ORC_MAXM * 2];
                 for (int a = 0; a < m; ++a) {
                     for (int i = 0; i < 5; ++i) fl[a * 5 + i] = f[(a * 5 + i) * N + n];
                     so[a] = Sold[a * N + n];
+                    /* central differences; a wall side takes the node's own value */
+                    for (int d = 0; d < 2; ++d) {
+                        int len = d == 0 ? nx : ny, c = d == 0 ? x : y;
+                        int wall_lo = d == 0 ? cfg->scalar_bc[0][a] != 0 : cfg->scalar_bc[2][a] != 0;
+                        int wall_hi = d == 0 ? cfg->scalar_bc[1][a] != 0 : cfg->scalar_bc[3][a] != 0;
+                        int cp = c + 1, cm = c - 1;
+                        if (cp >= len) cp = wall_hi ? c : 0;
+                        if (cm < 0) cm = wall_lo ? c : len - 1;
+                        size_t np_ = d == 0 ? nidx(cfg, cp, y) : nidx(cfg, x, cp);
+                        size_t nm_ = d == 0 ? nidx(cfg, cm, y) : nidx(cfg, x, cm);
+                        gs[a * 2 + d] = (Sprev[a * N + np_] - Sprev[a * N + nm_]) / 2.0;
+                    }
                 }
                 for (int i = 0; i < 9; ++i) hl[i] = h[i * N + n];
-                if (!collide_node(cfg, Minv, fl, hl, so, fs, hs, sn)) ok = 0;
+                if (!collide_node(cfg, Minv, fl, hl, so, gs, fs, hs, sn)) ok = 0;
                 for (int a = 0; a < m; ++a) Sold[a * N + n] = sn[a];
                 /* fluid streaming (Case 1: the per-node values stay in place) */
                 if (cfg->model == 2) {
@@ -637,6 +668,7 @@ int orc_step(const orc_cfg *cfg, double *f, double *h, double *Sold, int64_t nst
         memcpy(f, f2, sizeof(double) * N * 5 * m);
         memcpy(h, h2, sizeof(double) * N * 9);
     }
+    free(Sprev);
     free(f2);
     free(h2);
     return ok;

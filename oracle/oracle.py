@@ -49,6 +49,7 @@ class OrcCfg(C.Structure):
         ("wall", C.c_double * (4 * MAXM)),
         ("lam", C.c_double * (MAXM * MAXM)),
         ("varphi", C.c_double),
+        ("gamma", C.c_double * MAXM),
     ]
 
 
@@ -145,6 +146,9 @@ def make_cfg(wl: dict, mutation: int = 0) -> OrcCfg:
         for b in range(m):
             c.lam[a * m + b] = lam[a, b]
     c.varphi = wl.get("varphi", 0.0)
+    gam = wl.get("gamma_s", [0.0] * m)
+    for a in range(m):
+        c.gamma[a] = gam[a]
     return c
 
 

@@ -223,6 +223,74 @@ def test_uniform_reaction_ab2(oracle_mod):
     assert _ab2_err(oracle_mod) < 1e-13
 
 
+def test_uniform_reaction_ab2_with_gamma(oracle_mod):
+    """gamma != 0 in D-bar (Eq. evolution12) acts on grad S only: on uniform
+    fields the AB2 recurrence is unchanged."""
+    import copy
+
+    k, y0, N = 0.01, 2.0, 200
+    ys = {}
+    for gam in (0.0, 1.5):
+        wl = W._base(4, 4, 1, 0.8, [[0.1]], K=[[-k]], gamma_s=[gam])
+        o = oracle_mod.Oracle(wl, np.full((1, 4, 4), y0), np.zeros((2, 4, 4)))
+        o.step(N)
+        ys[gam] = copy.deepcopy(o.f)
+    assert np.array_equal(ys[0.0], ys[1.5])
+
+
+def _gamma_step_err(O, mutation=0):
+    """One step from a non-uniform equilibrium: the populations of a run with
+    gamma != 0 minus those of the same run with gamma = 0 are exactly the
+    gamma part of (dt^2/2) D-bar S_i (Eq. evolution12), (1/2) gamma_a W_i
+    c_i . grad S_a(x) with S = K phi0 (S_old at t = 0 is S(phi0)) and grad S by
+    central differences (the node's own value across a wall), streamed to
+    x + c_i -- or, for a link leaving through a wall, reflected into the
+    opposite direction at x (no-flux walls: sign +, Dirichlet: sign -)."""
+    nx, ny, m = 16, 12, 2
+    X, Y = W.cell_centres(nx, ny)
+    phi0 = np.stack([1.0 + 0.2 * np.cos(2 * np.pi * X / nx) + 0.1 * np.sin(np.pi * Y / ny) ** 2,
+                     2.0 + 0.3 * np.sin(2 * np.pi * X / nx + 0.4) * np.cos(np.pi * Y / ny)])
+    K = np.array([[-0.02, 0.01], [0.005, -0.03]])
+    gam = np.array([0.7, 1.3])
+    sbc = [["periodic"] * 2, ["periodic"] * 2, ["noflux", "dirichlet"], ["dirichlet", "noflux"]]
+    fbc = ["periodic", "periodic", "noslip", "noslip"]
+    out = {}
+    for g in (gam, np.zeros(2)):
+        wl = W._base(nx, ny, m, 0.8, [[0.05, 0.01], [0.02, 0.08]], K=K.tolist(), gamma_s=g.tolist(),
+                     fluid_bc=fbc, scalar_bc=sbc, wall=[[0, 0], [0, 0], [1.0, 2.0], [1.5, 0.5]])
+        o = O.Oracle(wl, phi0, np.zeros((2, ny, nx)), mutation=mutation)
+        o.step(1)
+        out[g[0]] = np.array(o.f).reshape(m, 5, ny, nx)
+    diff = out[gam[0]] - out[0.0]
+    S = np.einsum("ab,byx->ayx", K, phi0)
+    e5 = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1)]
+    opp = [0, 3, 4, 1, 2]
+    want = np.zeros_like(diff)
+    for a in range(m):
+        wall_lo = sbc[2][a] != "periodic"
+        Sp = np.vstack([S[a][1:], S[a][-1:]])     # y + 1, own value at the top wall
+        Sm = np.vstack([S[a][:1], S[a][:-1]])     # y - 1, own value at the bottom wall
+        assert wall_lo
+        gx = (np.roll(S[a], -1, axis=1) - np.roll(S[a], 1, axis=1)) / 2
+        gy = (Sp - Sm) / 2
+        for i in range(1, 5):
+            term = 0.5 * gam[a] * (1.0 / 6.0) * (e5[i][0] * gx + e5[i][1] * gy)
+            for y in range(ny):
+                for x in range(nx):
+                    ty = y + e5[i][1]
+                    if 0 <= ty < ny:
+                        want[a, i, ty, (x + e5[i][0]) % nx] += term[y, x]
+                    else:
+                        side = 2 if ty < 0 else 3
+                        sgn = 1.0 if sbc[side][a] == "noflux" else -1.0
+                        want[a, opp[i], y, x] += sgn * term[y, x]
+    return np.abs(diff - want).max()
+
+
+def test_gamma_term_one_step_closed_form(oracle_mod):
+    assert _gamma_step_err(oracle_mod) < 1e-15
+
+
 def _centroid_err(O, mutation=0):
     """Uniform force F, periodic, u0 = 0: the fluid velocity is u(t) = F t
     exactly.  With the auxiliary source G (Eq. Gi) each species' first moment
@@ -386,6 +454,39 @@ def _pulse_lam_err(O, n, sigma, steps, mutation=0):
     return np.abs(phi - exact).max() / np.abs(exact - 1).max()
 
 
+def _pulse_decay_err(O, n, sigma, steps, k, gamma):
+    """Gaussian pulses under a non-symmetric D with the uniform decay S = -k phi
+    and gamma in D-bar: phi = e^{-k t} (1 + pulses of the closed form)."""
+    D = np.array([[0.1, 0.03], [0.02, 0.05]])
+    lam, P = np.linalg.eig(D)
+    wl = W._base(n, n, 2, 0.8, D, K=(-k * np.eye(2)).tolist(), gamma_s=[gamma, gamma])
+    X, Y = W.cell_centres(n, n)
+    amps = [0.5, 0.3]
+    psi0 = np.stack([_gauss(X, Y, n / 2, n / 2, sigma ** 2, n, amps[k_]) for k_ in range(2)])
+    o = O.Oracle(wl, np.einsum("ak,kyx->ayx", P, psi0) + 1.0, np.zeros((2, n, n)))
+    o.step(steps)
+    phi, _, _ = o.moments()
+    psit = np.stack([_gauss(X, Y, n / 2, n / 2, sigma ** 2 + 2 * lam[k_] * steps, n,
+                            amps[k_] * sigma ** 2 / (sigma ** 2 + 2 * lam[k_] * steps)) for k_ in range(2)])
+    exact = np.exp(-k * steps) * (np.einsum("ak,kyx->ayx", P, psit) + 1.0)
+    return np.abs(phi - exact).max() / np.abs(exact).max()
+
+
+def test_gaussian_pulse_with_decay_and_gamma_second_order(oracle_mod):
+    """With gamma != 0 the scheme still converges at second order in
+    diffusive scaling (dt ~ dx^2, so k per step scales by 1/4): with M_1S = 0
+    gamma drops out of Eq. order2; the gamma term's first moment,
+    (dt^2/2) gamma cs^2 grad S, changes the second-order error constant
+    (measured 9.7e-4 with gamma = 1 against 6.2e-4 with gamma = 0 at n = 64),
+    not the order."""
+    e1 = _pulse_decay_err(oracle_mod, 64, 4.0, 200, 2e-3, 1.0)
+    e2 = _pulse_decay_err(oracle_mod, 128, 8.0, 800, 5e-4, 1.0)
+    f1 = _pulse_decay_err(oracle_mod, 64, 4.0, 200, 2e-3, 0.0)
+    f2 = _pulse_decay_err(oracle_mod, 128, 8.0, 800, 5e-4, 0.0)
+    assert 3.5 < e1 / e2 < 4.5 and 3.5 < f1 / f2 < 4.5
+    assert e1 < 2e-3 and f1 < 2e-3
+
+
 def test_gaussian_pulse_with_lambda_second_order(oracle_mod):
     e1 = _pulse_lam_err(oracle_mod, 64, 4.0, 200)
     e2 = _pulse_lam_err(oracle_mod, 128, 8.0, 800)
@@ -544,6 +645,49 @@ def test_chemotaxis_steady_closed_form(oracle_mod):
 
 
 @pytest.mark.slow
+def test_chemotaxis_steady_closed_form_at_the_papers_step(oracle_mod):
+    """Sec. 3.1.1 at the paper's own spacing and step: dx = 0.02 (50 rows),
+    dt = 2.5e-7 (dt/dx^2 = 6.25e-4).  Started from the closed form itself
+    (n scaled to the mass pi/40 of the paper's uniform initial state: the
+    discrete steady state is fixed by that mass) and run until the relative
+    change over 20000 steps is below 2e-8 (~1.5 M steps; the slowest mode
+    decays by e in ~4e5 steps, so the remaining drift is < 1e-6 of the error
+    measured).  Expected: relative L1 5.3e-5 (n) and 1.7e-5 (c), the O(dt F)
+    error of G in hydrostatic balance (reading 3), measured 5.34e-5 / 1.68e-5
+    when run on to a change below 1e-10."""
+    with open(os.path.join(GOLDEN, "cf_steady.json")) as fh:
+        g = json.load(fh)
+    dx, dt = g["dx"], g["dt"]
+    ny = int(round(1.0 / dx))
+    alpha, beta, delta = g["alpha"], g["beta"], g["delta"]
+    A = math.pi / 20.0
+    y = (np.arange(ny) + 0.5) / ny
+    ns = delta * A * A / beta * alpha / 2 / np.cos(alpha * A * y / 2) ** 2
+    cs = 1 - 2 / alpha * np.log(np.cos(alpha * A * y / 2) / np.cos(alpha * A / 2))
+    wl, phi0, u0, p0 = W.chemotaxis_steady(ny=ny, nx=1, ratio=dt / dx ** 2, alpha=alpha, beta=beta, delta=delta,
+                                           gamma=g["gamma"], Sc=g["Sc"])
+    phi0[0] = (ns * (math.pi / 40) / ns.mean())[:, None]
+    phi0[1] = cs[:, None]
+    threads = oracle_mod.threads()
+    oracle_mod.set_threads(1)     # 50 nodes: one thread is fastest
+    try:
+        o = oracle_mod.Oracle(wl, phi0, u0, p0)
+        prev = None
+        for _ in range(200):
+            o.step(20000)
+            phi, u, _ = o.moments()
+            if prev is not None and max(np.abs(phi[a] - prev[a]).sum() / np.abs(phi[a]).sum() for a in range(2)) < 2e-8:
+                break
+            prev = phi.copy()
+    finally:
+        oracle_mod.set_threads(threads)
+    en = np.abs(phi[0, :, 0] - ns).sum() / np.abs(ns).sum()
+    ec = np.abs(phi[1, :, 0] - cs).sum() / np.abs(cs).sum()
+    assert en < 6e-5 and ec < 2e-5
+    assert abs(phi[0].mean() - math.pi / 40) < 1e-14 and np.abs(u).max() < 1e-10
+
+
+@pytest.mark.slow
 def test_chemotaxis_steady_second_order(oracle_mod):
     en1, ec1, _, _ = _cf_steady(oracle_mod, 50, nx=1)
     en2, ec2, _, _ = _cf_steady(oracle_mod, 100, nx=1)
@@ -579,6 +723,7 @@ MUTATIONS = {
     12: "lambda on the wrong side of D in the relaxation matrix",
     13: "varphi pressure correction with the wrong sign",
     14: "varphi term of the discrete force dropped",
+    15: "gamma term of D-bar with the wrong sign",
 }
 
 
@@ -594,6 +739,7 @@ def _battery(O, mutation):
         "pulse": _pulse_err(O, 64, 4.0, 200, mutation) < 7e-3,
         "pulse_lambda": _pulse_lam_err(O, 64, 4.0, 200, mutation) < 7e-3,
         "accel_varphi": _accel_err(O, 1.0, mutation) < 1e-14,
+        "gamma_step": _gamma_step_err(O, mutation) < 1e-15,
     }
 
 
