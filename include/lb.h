@@ -12,7 +12,8 @@
  * matrix relaxation omega_ab = (D/(cs^2 dt) + I/2)^-1 (Eq. omega-D with
  * lambda = I), whose off-diagonal entries carry the cross-diffusion; the
  * auxiliary source G of Eq. Gi cancels the numerical diffusion of convection;
- * the source carries its time-derivative correction (Eq. source, gamma = 0);
+ * the source carries its time-derivative correction (Eq. source; the gamma
+ * part of D-bar is a parameter, 0 by default as in the paper's runs);
  * the fluid is BGK (Eq. evolution3) with the force term of Eq. force
  * (varphi = 0) and the pressure scheme of appendix A, or MRT.
  *
@@ -128,6 +129,12 @@ typedef struct lb_params {
                                     varphi W_i (uF + Fu):(c_i c_i - cs^2 I)/(2 cs^4) and the pressure
                                     dt (1/omega - 1/2) F_0 inside the bracket of appendix A.  BGK only;
                                     not for the no-fluid model */
+    double gamma_s[LB_MAX_M];    /* diagonal of gamma in D-bar = delta d/dt + gamma c_i . grad of
+                                    Eq. evolution12 (0 in Sec. 3): the step adds (1/2) gamma_a W_i c_i .
+                                    grad S_a, grad S_a by central differences of the previous step's
+                                    source field (S(x +- e_d, t - dt); across a wall the node's own
+                                    value).  Non-zero values need the linear or chemotaxis model,
+                                    one step per launch, and no batch */
 } lb_params;
 
 typedef struct lb_handle lb_handle;

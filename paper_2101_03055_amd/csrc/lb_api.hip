@@ -61,6 +61,14 @@ int source_mask(const lb_params& p) {
     return mask;
 }
 
+// gamma of D-bar acts (gamma != 0 for a species that carries a source)
+bool gamma_on(const lb_params& p) {
+    const int mask = source_mask(p);
+    for (int a = 0; a < p.m; ++a)
+        if ((mask >> a & 1) && p.gamma_s[a] != 0.0) return true;
+    return false;
+}
+
 Layout make_layout(const lb_params& p) {
     Layout L{};
     L.N = (size_t)p.nx * (size_t)p.ny;
@@ -89,6 +97,10 @@ Layout make_layout(const lb_params& p) {
     off += 256 * 8;
     L.pop2_off = L.pop_off;
     L.sold2_off = L.sold_off;
+    if (gamma_on(p) && p.fused_steps != 2) {
+        L.sold2_off = off;
+        off += round_up(L.nsrc * L.N * arith_bytes(p.storage), 256);
+    }
     if (p.fused_steps == 2) {
         off = round_up(off, 4096);
         L.pop2_off = off;
@@ -256,6 +268,10 @@ lb_status validate(const lb_params* p) {
     if (p->varphi != 0.0 && p->collision != LB_COLL_BGK)
         return fail(LB_EINVAL, "varphi != 0 needs BGK (its pressure correction uses the single fluid rate)");
     if (p->varphi != 0.0 && p->model == LB_MODEL_CDE) return fail(LB_EINVAL, "no-fluid model: varphi must be 0");
+    for (int a = 0; a < p->m; ++a)
+        if (!std::isfinite(p->gamma_s[a])) return fail(LB_EINVAL, "gamma_s[%d] not finite", a);
+    if (gamma_on(*p) && (p->model == LB_MODEL_CDE || p->fused_steps == 2))
+        return fail(LB_EINVAL, "gamma != 0 needs the linear or chemotaxis model and one step per launch");
     double lamm[LB_MAX_M * LB_MAX_M];
     const bool lam_on = lambda_matrix(*p, lamm);
     if (lam_on && p->model == LB_MODEL_CHEMOTAXIS)
@@ -352,6 +368,8 @@ void fill_kparams(const lb_params& p, const Layout& L, KParams<T>& k) {
     k.inv_scale_h = T(p.storage == LB_STORE_F16 ? 1.0 / p.fp16_scale_h : 1.0);
     k.varphi = T(p.varphi);
     k.vp_p = T((p.tau_f - 0.5) * (4.0 / 3.0) * p.varphi);
+    k.gam_on = gamma_on(p) ? 1 : 0;
+    for (int a = 0; a < m; ++a) k.gam12[a] = T(k.gam_on ? p.gamma_s[a] / 12.0 : 0.0);
 }
 
 }  // namespace
@@ -374,6 +392,7 @@ struct lb_handle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     Launch glc{0, 0};
+    size_t gsold = 0;    // source buffer the graph's first launch reads (gamma != 0 alternates two)
     ~lb_handle() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -575,11 +594,13 @@ lb_status lb_step(lb_handle* h, int64_t n) {
         if (h->parity) {
             hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, true, h->lc, h->t, h->stream);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+            if (h->kd.gam_on) std::swap(h->L.sold_off, h->L.sold2_off);
             h->t += 1;
             h->parity = 0;
             n -= 1;
         }
-        if (!h->gexec || h->glc.tile_x != h->lc.tile_x || h->glc.tile_y != h->lc.tile_y) {
+        if (!h->gexec || h->glc.tile_x != h->lc.tile_x || h->glc.tile_y != h->lc.tile_y ||
+            h->gsold != h->L.sold_off) {
             if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
             if (h->graph) (void)hipGraphDestroy(h->graph);
             h->gexec = nullptr;
@@ -588,6 +609,7 @@ lb_status lb_step(lb_handle* h, int64_t n) {
             if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph: %s", hipGetErrorString(e));
             h->glc = h->lc;
+            h->gsold = h->L.sold_off;
         }
         for (; n >= kGraphSteps; n -= kGraphSteps) {
             hipError_t e = hipGraphLaunch(h->gexec, h->stream);
@@ -599,6 +621,8 @@ lb_status lb_step(lb_handle* h, int64_t n) {
         const bool odd = h->parity != 0;
         hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, odd, h->lc, h->t, h->stream);
         if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+        // gamma != 0: the launch wrote the new source field into the second buffer
+        if (h->kd.gam_on) std::swap(h->L.sold_off, h->L.sold2_off);
         h->t += 1;
         h->parity ^= 1;
     }
@@ -1037,6 +1061,7 @@ lb_status lbb_workspace_bytes(const lb_params* params, int32_t count, size_t* by
             return fail(LB_EINVAL, "cavity %d: m, model, storage, collision and r_kind must match cavity 0", c);
         if (params[c].fused_steps == 2) return fail(LB_EINVAL, "cavity %d: the batched sweep takes one step per launch", c);
         if (params[c].model == LB_MODEL_CDE) return fail(LB_EINVAL, "cavity %d: the no-fluid model is not batched", c);
+        if (gamma_on(params[c])) return fail(LB_EINVAL, "cavity %d: gamma != 0 is not batched", c);
     }
     *bytes = batch_plan(params, count, nullptr);
     return LB_OK;

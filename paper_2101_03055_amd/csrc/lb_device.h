@@ -465,8 +465,11 @@ __device__ __forceinline__ T lam_excess(const KParams<T>& kp, const T phi[M], in
 // ---- the node update ------------------------------------------------------
 // CONS (FP32 storage): the scalar rest populations take the remainder of the
 // species' post-collision mass in FP64, see below.
+// gS (may be NULL): gamma_a grad S_a / 6 per species and axis, the term of
+// D-bar (Eq. evolution12) that acts like the auxiliary source.
 template <class T, int M, int MODEL, int COLL, bool CONS = false>
-__device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5], const T Sold[M], T Snew[M]) {
+__device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5], const T Sold[M], T Snew[M],
+                                        const T (*gS)[2] = nullptr) {
     Macro<T, M> mc;
     macro<T, M>(kp, h, f, mc);
     double mass_in[M];  // exact sums of the stored (FP32) input populations
@@ -521,6 +524,15 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
             const T cf = (a == b ? T(1) : T(0)) - T(0.5) * om[a][b];
             g[a][0] += cf * (mc.u[0] * S[b] + mc.phi[b] * mc.F[0]);
             g[a][1] += cf * (mc.u[1] * S[b] + mc.phi[b] * mc.F[1]);
+        }
+    }
+    // gamma of D-bar: (dt^2/2) gamma_a c_i . grad S_{i,a} with S_i = W_i S (Eq. source)
+    // is 3 W_i c_i . (gamma_a grad S_a / 6), the form of G_i above
+    if (gS) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            g[a][0] += gS[a][0];
+            g[a][1] += gS[a][1];
         }
     }
     // source with its time-derivative correction (Eq. source, gamma = 0):

@@ -39,6 +39,9 @@ struct KParams {
     T lamm[LB_MAX_M * LB_MAX_M]; // lambda - I, row-major
     T varphi;             // varphi of Eq. force (0: the force term of Sec. 3)
     T vp_p;               // pressure correction per u.F: (tau_f - 1/2) (4/3) varphi
+    int gam_on;           // gamma != 0 in D-bar (Eq. evolution12) for a species with a source
+    T gam12[LB_MAX_M];    // gamma_a / 12: the auxiliary-source vector gains gamma_a grad S_a / 6,
+                          // with grad S_a = (S(x + e) - S(x - e)) / 2
 };
 
 struct Layout {
@@ -48,7 +51,9 @@ struct Layout {
     size_t npop;          // population planes, 9 + 5m
     size_t nsrc;          // S_old planes
     size_t pop_off, sold_off, snap_off, stage_off, part_off, res_off, total;
-    size_t pop2_off, sold2_off;  // second population / source arrays (two-step launches only)
+    size_t pop2_off, sold2_off;  // second population / source arrays (two-step launches; the source
+                                 // planes also when gamma != 0: the step reads the previous source
+                                 // field at the neighbours while writing the new one)
     size_t naux, aux_off;        // no-fluid model: prescribed u (2 planes) and previous phi - phi_ref (m planes)
 };
 

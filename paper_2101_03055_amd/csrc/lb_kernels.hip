@@ -32,8 +32,8 @@ namespace lbk {
 // ---- kernels ------------------------------------------------------------------
 template <class S, int M, int MODEL, int COLL, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* __restrict__ pop,
-                                              typename St<S>::T* __restrict__ sold, int tile_x, int tile_y,
-                                              int tiles_x, uint32_t salt) {
+                                              const typename St<S>::T* sold, typename St<S>::T* sold_out,
+                                              int tile_x, int tile_y, int tiles_x, uint32_t salt) {
     using T = typename St<S>::T;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = b % tiles_x, by = b / tiles_x;
@@ -51,11 +51,31 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
         Sold[a] = T(0);
         if (kp.src_mask >> a & 1) Sold[a] = load_raw<NT>(&sold[(long long)(k++) * N + n]);
     }
-    collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, Sold, Snew);
+    // gamma of D-bar (Eq. evolution12): central differences of the previous
+    // step's source field (`sold`, not written by this launch when gamma != 0);
+    // across a wall the node's own value stands in for the missing neighbour
+    T gS[M][2];
+    if (kp.gam_on) {
+        k = 0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            gS[a][0] = gS[a][1] = T(0);
+            if (kp.src_mask >> a & 1) {
+                const T* pl = sold + (long long)(k++) * N;
+                const long long xp = x + 1 < kp.nx ? n + 1 : (kp.sbc[1][a] == LB_SBC_PERIODIC ? n + 1 - kp.nx : n);
+                const long long xm = x > 0 ? n - 1 : (kp.sbc[0][a] == LB_SBC_PERIODIC ? n - 1 + kp.nx : n);
+                const long long yp = y + 1 < kp.ny ? n + kp.nx : (kp.sbc[3][a] == LB_SBC_PERIODIC ? n + kp.nx - N : n);
+                const long long ym = y > 0 ? n - kp.nx : (kp.sbc[2][a] == LB_SBC_PERIODIC ? n - kp.nx + N : n);
+                gS[a][0] = kp.gam12[a] * (pl[xp] - pl[xm]);
+                gS[a][1] = kp.gam12[a] * (pl[yp] - pl[ym]);
+            }
+        }
+    }
+    collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, Sold, Snew, kp.gam_on ? gS : nullptr);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)
-        if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold[(long long)(k++) * N + n]);
+        if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold_out[(long long)(k++) * N + n]);
     scatter<S, M, ODD, NT>(kp, pop, x, y, h, f, salt);
 }
 
@@ -543,9 +563,12 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
         S* pop = (S*)at(ws, L.pop_off);
         T* sold = (T*)at(ws, L.sold_off);
         KParams<T> kp = kpar<S>(kd, kf);
+        // with gamma != 0 the new source field goes to the second buffer (the
+        // caller swaps the two after the launch); otherwise in place
+        T* sold_out = kp.gam_on ? (T*)at(ws, L.sold2_off) : sold;
         int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
         uint32_t sl = salt;
-        void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &sl};
+        void* args[] = {&kp, &pop, &sold, &sold_out, &tx, &ty, &tsx, &sl};
         const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
@@ -567,11 +590,14 @@ hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const
     e = dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
         using T = typename St<S>::T;
         S* pop = (S*)at(ws, L.pop_off);
-        T* sold = (T*)at(ws, L.sold_off);
+        // source planes: launch k reads buffer k % 2 and writes the other one
+        // (the same buffer twice unless gamma != 0)
         KParams<T> kp = kpar<S>(kd, kf);
+        T* sbuf[2] = {(T*)at(ws, L.sold_off), (T*)at(ws, kp.gam_on ? L.sold2_off : L.sold_off)};
         int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
         uint32_t salt = 0;
-        void* args[] = {&kp, &pop, &sold, &tx, &ty, &tsx, &salt};
+        void* args[2][8] = {{&kp, &pop, &sbuf[0], &sbuf[1], &tx, &ty, &tsx, &salt},
+                            {&kp, &pop, &sbuf[1], &sbuf[0], &tx, &ty, &tsx, &salt}};
         const bool mrt = p.collision == LB_COLL_MRT;
         void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0));
         void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0));
@@ -582,7 +608,7 @@ hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const
             np.gridDim = grid;
             np.blockDim = block;
             np.sharedMemBytes = 0;
-            np.kernelParams = args;
+            np.kernelParams = args[k & 1];
             np.extra = nullptr;
             hipGraphNode_t node;
             hipError_t ee = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);

@@ -56,6 +56,7 @@ class lb_params(C.Structure):
         ("fp16_scale_h", C.c_double),
         ("lam", C.c_double * (MAXM * MAXM)),
         ("varphi", C.c_double),
+        ("gamma_s", C.c_double * MAXM),
     ]
 
 
@@ -174,6 +175,8 @@ def params_from_workload(wl: dict, storage: str = "f64", phi_ref=None, fp16_scal
             for b in range(m):
                 p.lam[a * m + b] = lam[a, b]
     p.varphi = float(wl.get("varphi", 0.0))
+    for a, g in enumerate(wl.get("gamma_s", [0.0] * m)):
+        p.gamma_s[a] = float(g)
     return p
 
 

@@ -225,3 +225,25 @@ def test_lb3_init_rejects_before_touching_the_device():
                       C.byref(h)) == lb.LB_ENONFINITE
     assert not h.value
     assert L.lb3_free(None) == lb.LB_OK
+
+
+def test_gamma_validation():
+    """gamma of D-bar: finite, not with two steps per launch, the no-fluid
+    model or a batch; a species without a source makes gamma inert (no second
+    source buffer)."""
+    wl, *_ = W.random_case(16, 12, m=2, seed=1, source=True)
+    base = lb.params_from_workload(dict(wl, gamma_s=[0.0, 0.0]))
+    p = lb.params_from_workload(dict(wl, gamma_s=[1.0, -0.5]))
+    assert lb.lb_workspace_bytes(p) > lb.lb_workspace_bytes(base)      # the second source buffer
+    nan = lb.params_from_workload(dict(wl, gamma_s=[float("nan"), 0.0]))
+    fused = lb.params_from_workload(dict(wl, gamma_s=[1.0, 0.0]), fused_steps=2)
+    for bad in (nan, fused):
+        with pytest.raises(lb.LBError) as ei:
+            lb.lb_workspace_bytes(bad)
+        assert ei.value.status == lb.LB_EINVAL
+    with pytest.raises(lb.LBError) as ei:
+        lb.lbb_workspace_bytes([p, p])
+    assert ei.value.status == lb.LB_EINVAL
+    nosrc, *_ = W.random_case(16, 12, m=2, seed=1, source=False)
+    assert lb.lb_workspace_bytes(lb.params_from_workload(dict(nosrc, gamma_s=[1.0, 1.0]))) == \
+        lb.lb_workspace_bytes(lb.params_from_workload(nosrc))

@@ -118,3 +118,84 @@ def test_no_fluid_model_with_lambda(oracle_mod, walls):
     ef = max(np.abs(f[a, i] - o.f[a, i]).max() / np.abs(o.f[a, i]).max() for a in range(2) for i in range(5))
     print(f"no-fluid lambda walls {walls}: f {ef:.2e}", flush=True)
     assert ef <= TOL64
+
+
+# ---- gamma of D-bar (Eq. evolution12) ----------------------------------------
+GAM = [1.7, -0.9, 0.6]
+
+
+def gamma_case(name, m=2, seed=7, model="linear"):
+    fb, sb = BC_CASES[name]
+    if m != 2:
+        sb = [[r[0]] * m for r in sb]
+    wl, phi0, u0, p0 = W.random_case(67, 45, m=m, seed=seed, fluid_bc=fb, scalar_bc=sb, force=True, source=True,
+                                     model=model, amp=0.2)
+    wl["K"] = (np.asarray(wl["K"]) * 20).tolist()   # sources strong enough for the gamma term to matter
+    wl["gamma_s"] = GAM[:m]
+    return wl, phi0, u0, p0
+
+
+@pytest.mark.parametrize("name", sorted(BC_CASES))
+def test_gamma_matches_oracle(oracle_mod, name):
+    """Through single launches of both parities and replayed step graphs (the
+    two source buffers alternate): 1, 2, 37, 130 steps."""
+    wl, phi0, u0, p0 = gamma_case(name)
+    o = oracle_mod.Oracle(wl, phi0, u0, p0)
+    g = lb.Solver(wl, phi0, u0, p0)
+    for n in (1, 2, 37, 130):
+        o.step(n)
+        g.step(n)
+        ef, eh = pop_errors(o, g)
+        print(f"gamma {name} t = {g.t}: f {ef:.2e} h {eh:.2e}", flush=True)
+        assert ef <= TOL64 and eh <= TOL64
+    assert moment_errors(o, g) <= TOL64
+
+
+def test_gamma_three_species_and_chemotaxis(oracle_mod):
+    for case in (gamma_case("cavity_noslip_dirichlet", m=3, seed=9),
+                 gamma_case("channel_freeslip_top", seed=11, model="chemotaxis")):
+        o = oracle_mod.Oracle(*case)
+        g = lb.Solver(*case)
+        o.step(151)
+        g.step(151)
+        ef, eh = pop_errors(o, g)
+        print(f"gamma {case[0]['model']} m = {case[0]['m']}: f {ef:.2e} h {eh:.2e}", flush=True)
+        assert ef <= TOL64 and eh <= TOL64
+
+
+def test_gamma_changes_the_result():
+    wl, phi0, u0, p0 = gamma_case("periodic_y_walls_x")
+    a = lb.Solver(wl, phi0, u0, p0)
+    b = lb.Solver(dict(wl, gamma_s=[0.0, 0.0]), phi0, u0, p0)
+    a.step(100)
+    b.step(100)
+    fa, _ = a.populations()
+    fb, _ = b.populations()
+    assert plane_errors(fa, fb) > 1e-9
+
+
+def test_gamma_save_load_and_fp32(oracle_mod):
+    """Checkpoints at odd and even steps resume bit for bit (the current source
+    buffer alternates); FP32 storage stays within its usual error."""
+    case = gamma_case("cavity_noslip_dirichlet")
+    for k in (41, 64):
+        a = lb.Solver(*case)
+        a.step(k)
+        blob = lb.lb_save(a.handle)
+        a.step(99)
+        fa, ha = a.populations()
+        b = lb.Solver(*case)
+        b.step(3)                     # a different buffer parity before the load
+        lb.lb_load(b.handle, blob)
+        b.step(99)
+        fb, hb = b.populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ha, hb), k
+    o = oracle_mod.Oracle(*case)
+    g = lb.Solver(*case, storage="f32", phi_ref=[1.0, 1.0])
+    o.step(500)
+    g.step(500)
+    phi, u, _ = g.moments()
+    po, uo, _ = o.moments()
+    ephi = max(np.abs(phi[a] - po[a]).max() / np.abs(po[a]).max() for a in range(2))
+    print(f"gamma fp32: phi {ephi:.2e}", flush=True)
+    assert ephi <= 2e-6
