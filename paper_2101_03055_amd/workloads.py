@@ -147,6 +147,25 @@ def chemotaxis_sinusoidal(nx=300, ny=50, dt=2.5e-7, a=3.0, alpha=10.0, beta=10.0
     return wl, phi0, u0, p0
 
 
+def chemotaxis_layer(alpha, beta, delta, nx=100, ny=50, a=1.0, dt=1e-8, gamma=418.0, Sc=7700.0, cstar=0.3):
+    """Parameter-influence case of Sec. 3.1.2 on [-a, a] x [0, 1], dx = 1/ny
+    (nx = 2 a ny): n0 = 1 where y > 0.501 - 0.01 sin((x - 0.5) pi), 0.5 below;
+    c0 = 1, u0 = 0 (cell centres); gamma = 418, Sc = 7700, dt = 1e-8 and the
+    regularised cut-off r(c) with eps = dx.  Deterministic: no random draw.
+    Defaults: dx = 0.02 (the grid the paper states for its chemotaxis runs)
+    and one period of the modulation, x in [-1, 1]."""
+    dx = 1.0 / ny
+    if abs(nx * dx - 2.0 * a) > 1e-9:
+        raise ValueError("nx must equal 2 a ny")
+    X, Y = cell_centres(nx, ny)
+    x, y = -a + X * dx, Y * dx
+    n0 = np.where(y > 0.501 - 0.01 * np.sin((x - 0.5) * math.pi), 1.0, 0.5)
+    wl, phi0, u0, p0 = chemotaxis(nx, ny, dx, dt, alpha, beta, delta, gamma, Sc, n0, r_kind="smooth",
+                                  cstar=cstar, eps=dx)
+    wl["name"] = f"chemotaxis_layer_a{alpha:g}_b{beta:g}_d{delta:g}_{nx}x{ny}"
+    return wl, phi0, u0, p0
+
+
 def chemotaxis_steady(ny=50, nx=4, ratio=0.01, alpha=10.0, beta=10.0, delta=5.0, gamma=1000.0,
                       Sc=500.0):
     """Steady validation case of Sec. 3.1.1: n0 = pi/40, c0 = 1, u0 = 0 on a
