@@ -150,6 +150,48 @@ def test_chemotaxis_plume_full_size(oracle_mod):
     assert moment_errors(o, g) <= TOL64
 
 
+def test_chemotaxis_steady_case_at_the_papers_step(oracle_mod):
+    """Sec. 3.1.1 with the paper's spacing and step (dx = 0.02, 50 rows,
+    dt = 2.5e-7) and initial state (n0 = pi/40, c0 = 1, u0 = 0) on an
+    x-homogeneous periodic strip: FP64 equals the oracle at 1e-11 after 20000
+    steps; run on to a steady state, the
+    fields match the closed form n^s, c^s to the oracle pin's tolerance
+    (relative L1 5.3e-5 / 1.7e-5 expected), the criterion being a relative
+    change of n and c over 20000 steps below 2e-8."""
+    import json, math, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cf_steady.json")) as fh:
+        gd = json.load(fh)
+    dx, dt = gd["dx"], gd["dt"]
+    ny = int(round(1.0 / dx))
+    wl, phi0, u0, p0 = W.chemotaxis_steady(ny=ny, nx=2, ratio=dt / dx ** 2, alpha=gd["alpha"], beta=gd["beta"],
+                                           delta=gd["delta"], gamma=gd["gamma"], Sc=gd["Sc"])
+    o, g = run_pair(oracle_mod, wl, phi0, u0, p0, 20000)
+    ef, eh = pop_errors(o, g)
+    print(f"steady chemotaxis case, 20000 steps: f {ef:.2e} h {eh:.2e}", flush=True)
+    assert ef <= TOL64 and eh <= TOL64
+    # steady criterion on the scalars (the fluid stays at rest: its residual is rounding noise)
+    g.residual()
+    steps = 20000
+    for _ in range(1000):
+        g.step(20000)
+        steps += 20000
+        res, st = g.residual()
+        if max(res[2:]) < 2e-8:
+            break
+    phi, u, _ = g.moments()
+    alpha, beta, delta, A = gd["alpha"], gd["beta"], gd["delta"], math.pi / 20
+    y = (np.arange(ny) + 0.5) / ny
+    ns = delta * A * A / beta * alpha / 2 / np.cos(alpha * A * y / 2) ** 2
+    cs = 1 - 2 / alpha * np.log(np.cos(alpha * A * y / 2) / np.cos(alpha * A / 2))
+    en = np.abs(phi[0, :, 0] - ns).sum() / np.abs(ns).sum()
+    ec = np.abs(phi[1, :, 0] - cs).sum() / np.abs(cs).sum()
+    print(f"steady after {steps} steps (change over 20000 steps {max(res[2:]):.1e}): n {en:.3e} c {ec:.3e}",
+          flush=True)
+    assert st == lb.LB_OK and max(res[2:]) < 2e-8
+    assert en < 6e-5 and ec < 2e-5
+    assert abs(phi[0].mean() - math.pi / 40) < 1e-13 and np.abs(u).max() < 1e-10
+
+
 def test_ddc_cavity_full_size(oracle_mod):
     wl, phi0, u0, p0 = W.ddc_cavity(256)
     o, g = run_pair(oracle_mod, wl, phi0, u0, p0, 1000)
