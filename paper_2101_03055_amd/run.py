@@ -106,7 +106,7 @@ def _steady(case, storage, phi_ref, tol, tol_reduced, check_every, max_steps):
     return out, fields
 
 
-def _sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps):
+def _sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps, keep_fields=False):
     from .surrogate_study import run_batch
 
     quiet = lambda s: None
@@ -114,7 +114,7 @@ def _sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps):
     t0 = time.perf_counter()
     b = lb.Batch(cases, storage=storage, phi_ref=phi_ref)
     tile = b.autotune(10)[:2]
-    if storage != "f64":
+    if storage == "f32":  # FP32 values are exact in FP64: carry the populations over
         s_r, st_r, _ = run_batch(b, tol32, check_every, max_steps, window=50000, log=quiet)
         b64 = lb.Batch(cases, storage="f64")
         for i in range(len(cases)):
@@ -122,6 +122,17 @@ def _sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps):
                 lb.lbb_copy_cavity(b64.handle, i, b.handle, i)
         b.close()
         b = b64
+    elif storage == "f16":  # restart FP64 at equilibrium of each cavity's fields, off the staggered mode
+        s_r, st_r, _ = run_batch(b, tol32, check_every, max_steps, window=50000, log=quiet)
+        restart = []
+        for i, c in enumerate(cases):
+            if st_r[i] == lb.LBB_DIVERGED:
+                restart.append(c)
+            else:
+                phi, u, p = b.moments(i)
+                restart.append((c[0], phi, destagger(c[0], u), p))
+        b.close()
+        b = lb.Batch(restart, storage="f64")
     s64, st64, _ = run_batch(b, tol, check_every, max_steps, window=50000, log=quiet)
     _sync()
     secs = time.perf_counter() - t0
@@ -129,8 +140,9 @@ def _sweep(cases, storage, phi_ref, tol, tol32, check_every, max_steps):
     out = {"cavities": len(cases), "tile": list(tile), "seconds": secs,
            "converged": int((st64 == lb.LBB_CONVERGED).sum()), "diverged": int((st64 == lb.LBB_DIVERGED).sum()),
            "steps_fp64_median": float(np.median(s64))}
+    fields = [b.moments(i) for i in range(len(cases))] if keep_fields else None
     b.close()
-    return out
+    return out, fields
 
 
 def main(argv=None):
@@ -158,7 +170,7 @@ def main(argv=None):
     rec = {"config": os.path.basename(args.config).removesuffix(".json"), "storage": storage}
     fields = None
     if cfg["workload"] == "sweep":
-        rec.update(_sweep(cases, storage, phi_ref, tol, tol_reduced, check_every, max_steps))
+        rec.update(_sweep(cases, storage, phi_ref, tol, tol_reduced, check_every, max_steps)[0])
     elif args.steady or (args.steps is None and "tol" in run):
         out, fields = _steady(cases[0], storage, phi_ref, tol, tol_reduced, check_every, max_steps)
         rec.update(out)
