@@ -169,6 +169,17 @@ __device__ __forceinline__ void wait_vm() {
 
 constexpr int kStages = 3;                          // LDS ring depth of k_conv128
 constexpr int kStageElems = (128 + 64) * LDSK;      // bf16 per stage: A tile, then B tile
+// LDS DMA loads per thread and stage in k_conv128: one load of a wavefront
+// fills 16 tile rows (64 lanes x 16 bytes, 4 lanes per 64-byte row), so the
+// 128-row A tile takes 2 per wavefront and the 64-row B tile 1 (4 wavefronts).
+// compute() waits for all but the loads of the later stages: kLoadsPerStage
+// times the number of stages issued after its own.
+constexpr int kWaves128 = 4, kRowsPerLoad = 16;
+constexpr int kLoadsA = 128 / (kRowsPerLoad * kWaves128), kLoadsB = 64 / (kRowsPerLoad * kWaves128);
+constexpr int kLoadsPerStage = kLoadsA + kLoadsB;
+static_assert(kLoadsA * kRowsPerLoad * kWaves128 == 128 && kLoadsB * kRowsPerLoad * kWaves128 == 64,
+              "the tiles must be whole multiples of the rows one round of loads fills");
+static_assert(kLoadsPerStage * (kStages - 1) < 16, "wait_vm takes counts below 16 here");
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
@@ -203,30 +214,33 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
         const int yy = y + dy;
         const bool rowin = (yy >= 0) & (yy < H);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int row = 16 * (wave + 4 * q) + rsub;  // pixel x0 + row
+        for (int q = 0; q < kLoadsA; ++q) {
+            const int blk = wave + kWaves128 * q;          // 16-row block of the A tile
+            const int row = kRowsPerLoad * blk + rsub;     // pixel x0 + row
             const int seg = (pseg ^ (row >> 1) ^ (row >> 3)) & 3;
             const int xx = x0 + row + dx;
             const bool in = rowin & (xx >= 0) & (xx < W);
             const void* src = in ? (const void*)(X + ((long long)(img_row + dy) * W + xx) * Cin + c0 + 8 * seg)
                                  : (const void*)&kZero16;
-            __builtin_amdgcn_global_load_lds(src, (lds_void*)(As + (16 * (wave + 4 * q)) * LDSK), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(src, (lds_void*)(As + (kRowsPerLoad * blk) * LDSK), 16, 0, 0);
         }
-        {
-            const int row = 16 * wave + rsub;  // output channel n0 + row
+#pragma unroll
+        for (int q = 0; q < kLoadsB; ++q) {
+            const int blk = wave + kWaves128 * q;          // 16-row block of the B tile
+            const int row = kRowsPerLoad * blk + rsub;     // output channel n0 + row
             const int seg = (pseg ^ (row >> 1) ^ (row >> 3)) & 3;
             __builtin_amdgcn_global_load_lds((const void*)(Wk + ((long long)(n0 + row) * 9 + tap) * Cin + c0 + 8 * seg),
-                                             (lds_void*)(Bs + (16 * wave) * LDSK), 16, 0, 0);
+                                             (lds_void*)(Bs + (kRowsPerLoad * blk) * LDSK), 16, 0, 0);
         }
     };
     auto lds_addr = [](const bf16* p) { return (uint32_t)(uintptr_t)p; };
-    // inflight: loads issued after this stage's (3 per stage and thread)
-    auto compute = [&](const bf16* As, const bf16* Bs, int inflight) {
+    // later: stages issued after this one (their kLoadsPerStage loads each may still be in flight)
+    auto compute = [&](const bf16* As, const bf16* Bs, int later) {
         // this wave's loads of this stage have landed, later stages may still be in flight ...
-        switch (inflight) {
-            case 9: wait_vm<9>(); break;
-            case 6: wait_vm<6>(); break;
-            case 3: wait_vm<3>(); break;
+        static_assert(kStages - 1 <= 2, "extend the cases below with the ring depth");
+        switch (later) {
+            case 2: wait_vm<2 * kLoadsPerStage>(); break;
+            case 1: wait_vm<kLoadsPerStage>(); break;
             default: wait_vm<0>(); break;
         }
         __builtin_amdgcn_s_barrier();  // ... and every other wave's
@@ -266,7 +280,7 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
     for (int st = 0; st < nsteps; ++st) {
         if (st + kStages - 1 < nsteps) issue(st + kStages - 1, stage_a(st + kStages - 1), stage_b(st + kStages - 1));
         const int later = min(kStages - 1, nsteps - 1 - st);  // stages issued after this one
-        compute(stage_a(st), stage_b(st), 3 * later);
+        compute(stage_a(st), stage_b(st), later);
     }
     const long long pbase = (long long)img_row * W + x0;
 #pragma unroll
