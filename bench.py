@@ -426,11 +426,70 @@ def surrogate_bench(torch, epochs=4, samples=64):
     torch.cuda.synchronize()
     t_pred = e0.elapsed_time(e1) / 1e3 / 10
     flops_pred = 2.0 * B * H * Wd * sum(macs)
+    layers = surrogate_kernel_rooflines(net, torch, B, H, Wd)
+    bound_step = sum(k["binding_us"] for L in layers for k in L["kernels"].values()) * 1e-6
     return {"batch": B, "grid": [H, Wd], "train_step_ms": round(t_step * 1e3, 3),
             "train_TFLOPs": round(flops_step / t_step / 1e12, 1),
             "train_frac_bf16_peak": round(flops_step / t_step / 2.5e15, 4),
+            "train_binding_roofline_ms": round(bound_step * 1e3, 3),
+            "train_frac_binding_roofline": round(bound_step / t_step, 4),
             "predict_ms_per_batch": round(t_pred * 1e3, 3),
-            "predict_TFLOPs": round(flops_pred / t_pred / 1e12, 1)}
+            "predict_TFLOPs": round(flops_pred / t_pred / 1e12, 1),
+            "kernels": layers,
+            "note": "binding roofline per kernel = max(algorithmic HBM bytes / 8 TB/s, real-channel flops / "
+                    "2.5 PFLOP/s); bytes are the stored (padded) tensors read and written once: forward x in, "
+                    "z (FP32) and y out; data gradient dz and z_prev in, dx out; weight gradient dz and x in, "
+                    "dW out (the split-K partial sums are not counted)"}
+
+
+def surrogate_kernel_rooflines(net, torch, B, H, Wd, reps=10):
+    """Each convolution of the training pass timed alone through sg_conv /
+    sg_weight_grad (HIP events on the surrogate's stream, `reps` back-to-back
+    calls) against its binding roofline."""
+    from paper_2101_03055_amd import sg
+
+    P = B * H * Wd
+    g = torch.Generator(device="cpu").manual_seed(5)
+    out = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(net.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(net.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps  # us
+
+    for l in range(sg.SG_LAYERS):
+        cin, cout, ci, co = sg.layer_info(l)
+        x = (torch.rand((B, H, Wd, ci), generator=g) - 0.5).to(torch.bfloat16).cuda()
+        gz = (torch.rand((B, H, Wd, co), generator=g) - 0.5).to(torch.bfloat16).cuda()
+        z = torch.empty((B, H, Wd, co), dtype=torch.float32, device="cuda")
+        y = torch.empty((B, H, Wd, co), dtype=torch.bfloat16, device="cuda")
+        zp = torch.rand((B, H, Wd, ci), generator=g).cuda()
+        dx = torch.empty((B, H, Wd, ci), dtype=torch.bfloat16, device="cuda")
+        dw = torch.empty((co, 9, ci), dtype=torch.float32, device="cuda")
+        db = torch.empty((co,), dtype=torch.float32, device="cuda")
+        gemm = 2.0 * P * 9 * cin * cout
+        kern = {}
+        kern["forward"] = (timed(lambda: net.conv(l, 0, B, x, y, d_z=z)), gemm, P * (2 * ci + 6 * co))
+        if l > 0:
+            kern["data_gradient"] = (timed(lambda: net.conv(l, 1, B, gz, dx, d_zprev=zp)), gemm, P * (2 * co + 6 * ci))
+        kern["weight_gradient"] = (timed(lambda: net.weight_grad(l, B, gz, x, dw, db)), gemm,
+                                   P * (2 * co + 2 * ci) + 4 * 9 * co * ci)
+        rec = {"layer": l, "channels": [cin, cout], "kernels": {}}
+        for k, (us, fl, by) in kern.items():
+            bind = max(by / 8e12, fl / 2.5e15) * 1e6
+            rec["kernels"][k] = {"us": round(us, 2), "TFLOPs": round(fl / us / 1e6, 1),
+                                 "GBs": round(by / us / 1e3, 1), "binding_us": round(bind, 2),
+                                 "bound": "hbm" if by / 8e12 >= fl / 2.5e15 else "mfma",
+                                 "frac_binding": round(bind / us, 4)}
+        out.append(rec)
+        del x, gz, z, y, zp, dx
+    return out
 
 
 def main():

@@ -17,6 +17,7 @@
 // and D[4 (l / 16) + j][l % 16], j < 4.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -34,6 +35,7 @@ namespace sgk {
 typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
 constexpr int kLayers = SG_LAYERS;
 constexpr int kCin[kLayers] = {15, 64, 128, 64, 64, 64};
@@ -302,6 +304,186 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
                 }
             }
 }
+
+// ---- persistent row-streaming convolution (width 128, K channels 32 or 64) ----
+// One workgroup (4 wavefronts) owns 64 output channels and a run of whole image
+// rows of 128 pixels.  Its weights (all 9 taps) stay in LDS for the whole run;
+// the input rows pass through a ring of 4 LDS slots filled by LDS DMA, the
+// next row loading while the current one is computed, so each input row
+// crosses from L2 once per workgroup and there is one barrier per output row.
+// Wavefront w computes pixels 32 w .. 32 w + 31 x 64 channels on the 32x32x16
+// bf16 MFMA (twice the rate of the 16x16x32 form on gfx950); the outputs leave
+// through per-wavefront LDS staging as whole 16-byte stores.
+constexpr int kRowW = 128;       // image width handled by the row kernel
+constexpr int kRowPx = kRowW + 2;   // an input row with its two halo pixels
+constexpr int kStagePitch = 68;  // floats per pixel row of the epilogue staging (64 + 4: no bank aliasing)
+// 16-byte segment swizzle of LDS rows of CK bf16 (pixels of an input row, or output channels of a
+// weight tap): consecutive rows that would start on the same banks get different segments, so that
+// 16 lanes reading one logical segment of 16 consecutive rows hit 64 distinct banks
+template <int CK> __device__ __forceinline__ int swz(int row) { return (row / (128 / CK)) & (CK / 8 - 1); }
+
+template <int MODE, int CK>
+__global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
+        const float* __restrict__ bias, const float* __restrict__ Zprev, float* __restrict__ Zout,
+        bf16* __restrict__ Yout, int H, int rows_total, int rows_per_wg, int Cout, int act) {
+    constexpr int S = CK / 8;                       // 16-byte segments per pixel / per weight row
+    constexpr int kWts = 9 * 64 * CK;               // bf16 of the workgroup's weights
+    constexpr int kSlot = kRowPx * CK;              // bf16 per ring slot
+    constexpr int kRowPieces = kRowPx * S;          // 16-byte pieces per input row
+    constexpr int kFull = kRowPieces / 256, kRem = kRowPieces - 256 * kFull;
+    static_assert(kRem % 4 == 0 && kRem > 0 && kRem / 4 <= 64, "remainder pieces split over the four wavefronts");
+    constexpr int kRowLoads = kFull + 1;            // DMA instructions per input row and wavefront
+    static_assert(kWts % (256 * 8) == 0, "weight pieces fill whole rounds");
+    __shared__ __attribute__((aligned(16))) bf16 Wts[kWts];
+    __shared__ __attribute__((aligned(16))) bf16 Ring[4 * kSlot];
+    __shared__ __attribute__((aligned(16))) float Stage[4 * 16 * kStagePitch];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n0 = blockIdx.y << 6;
+    const int R0 = blockIdx.x * rows_per_wg;
+    const int R1 = min(R0 + rows_per_wg, rows_total);
+    if (R0 >= R1) return;
+    float* stage = Stage + wave * 16 * kStagePitch;
+
+    // weights of this workgroup's 64 output channels: piece q = (tap 64 + co) S + s, segment
+    // s holding the 8 channels (s ^ (co & (S - 1))) so that the operand reads spread over the banks
+#pragma unroll
+    for (int r = 0; r < kWts / (256 * 8); ++r) {
+        const int q = (r * 4 + wave) * 64 + lane;
+        const int tap = q / (64 * S), co = (q / S) % 64, ps = q % S;
+        const int ls = ps ^ swz<CK>(co);
+        __builtin_amdgcn_global_load_lds((const void*)(Wk + ((long long)(n0 + co) * 9 + tap) * CK + 8 * ls),
+                                         (lds_void*)(Wts + (size_t)(r * 4 + wave) * 64 * 8), 16, 0, 0);
+    }
+    // input row Rg (global row index) into ring slot Rg & 3: piece q = px S + s, pixel px of the
+    // row with halo (image column px - 1), segment s holding the channels (s ^ (px & (S - 1)));
+    // every wavefront issues kRowLoads instructions (the last round spread over all four)
+    auto load_row = [&](int Rg) {
+        bf16* slot = Ring + (size_t)(Rg & 3) * kSlot;
+        const bool rin = Rg >= 0 && Rg < rows_total;
+#pragma unroll
+        for (int r = 0; r < kRowLoads; ++r) {
+            const bool last = r == kFull;
+            const int base = last ? kFull * 256 + wave * (kRem / 4) : (r * 4 + wave) * 64;
+            const bool on = !last || lane < kRem / 4;
+            const int q = base + lane;
+            const int px = q / S, ps = q % S;
+            const int ls = ps ^ swz<CK>(px);
+            const int x = px - 1;
+            const bool in = rin && on && x >= 0 && x < kRowW;
+            const void* src = in ? (const void*)(X + ((long long)Rg * kRowW + x) * CK + 8 * ls) : (const void*)&kZero16;
+            if (on) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)base * 8), 16, 0, 0);
+        }
+    };
+    load_row(R0 - 1);
+    load_row(R0);
+    load_row(R0 + 1);
+    wait_vm<0>();
+    __syncthreads();
+
+    auto lds_addr = [](const void* p) { return (uint32_t)(uintptr_t)p; };
+    const int l32 = lane & 31, kg = lane >> 5;
+    const int swzw = swz<CK>(l32);   // weight-row swizzle (output channels l32 and 32 + l32 alike)
+    for (int R = R0; R < R1; ++R) {
+        const int y = R % H;
+        float zp[2][2][8];
+        if constexpr (MODE == 1) {
+            // pre-activations of this row in the epilogue's piece order (pixel q >> 3, channels 8 (q & 7))
+#pragma unroll
+            for (int g2 = 0; g2 < 2; ++g2)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int q = lane + 64 * i;
+                    const long long o = ((long long)R * kRowW + 32 * wave + 16 * g2 + (q >> 3)) * Cout + n0 + 8 * (q & 7);
+                    const float4 a = *reinterpret_cast<const float4*>(Zprev + o);
+                    const float4 b = *reinterpret_cast<const float4*>(Zprev + o + 4);
+                    zp[g2][i][0] = a.x; zp[g2][i][1] = a.y; zp[g2][i][2] = a.z; zp[g2][i][3] = a.w;
+                    zp[g2][i][4] = b.x; zp[g2][i][5] = b.y; zp[g2][i][6] = b.z; zp[g2][i][7] = b.w;
+                }
+        }
+        // input row R + 1 has landed (this wave's loads are older than the previous
+        // row's stores -- 12 with z, 4 without -- and, for the data gradient, the 8
+        // pre-activation loads just issued), then every wave's
+        if (MODE == 1 || Zout) wait_vm<12>(); else wait_vm<4>();
+        __syncthreads();
+        load_row(R + 2);   // into the slot of row R - 2, which no wave reads any more
+
+        floatx16 acc0, acc1;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = 0.f;
+#pragma unroll
+        for (int dyi = 0; dyi < 3; ++dyi) {
+            const int yy = y + dyi - 1;
+            if (yy < 0 || yy >= H) continue;   // zero padding: the tap row contributes nothing
+            const bf16* slot = Ring + (size_t)((R + dyi - 1) & 3) * kSlot;
+#pragma unroll
+            for (int dxi = 0; dxi < 3; ++dxi) {
+                const int tap = 3 * dyi + dxi;
+                const int pxi = 32 * wave + l32 + dxi;       // pixel (with halo) feeding output pixel 32 w + l32
+                const bf16* arow = slot + (size_t)pxi * CK;
+                const bf16* brow0 = Wts + (size_t)(tap * 64 + l32) * CK;
+                const bf16* brow1 = brow0 + (size_t)32 * CK;
+#pragma unroll
+                for (int h = 0; h < CK / 16; ++h) {
+                    const int ls = 2 * h + kg;
+                    bf16x8 a, b0, b1;
+                    // one asm block waits for its own LDS reads: as plain loads the compiler would
+                    // also wait for the row DMA still in flight to another ring slot
+                    asm volatile("ds_read_b128 %0, %3\n\tds_read_b128 %1, %4\n\tds_read_b128 %2, %5\n\ts_waitcnt lgkmcnt(0)"
+                                 : "=&v"(a), "=&v"(b0), "=&v"(b1)
+                                 : "v"(lds_addr(arow + 8 * (ls ^ swz<CK>(pxi)))),
+                                   "v"(lds_addr(brow0 + 8 * (ls ^ swzw))), "v"(lds_addr(brow1 + 8 * (ls ^ swzw)))
+                                 : "memory");
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+                }
+            }
+        }
+        // epilogue in two halves of 16 pixels through this wave's staging rows:
+        // acc element j of lane l is output pixel 8 (j >> 2) + 4 kg + (j & 3), channel l32 (+32)
+#pragma unroll
+        for (int g2 = 0; g2 < 2; ++g2) {
+#pragma unroll
+            for (int j = 8 * g2; j < 8 * g2 + 8; ++j) {
+                const int m = 8 * ((j >> 2) - 2 * g2) + 4 * kg + (j & 3);
+                float v0 = acc0[j], v1 = acc1[j];
+                if constexpr (MODE == 0) {
+                    v0 += bias[n0 + l32];
+                    v1 += bias[n0 + 32 + l32];
+                }
+                stage[m * kStagePitch + l32] = v0;
+                stage[m * kStagePitch + 32 + l32] = v1;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int q = lane + 64 * i, pl = q >> 3, cg = q & 7;
+                const float4 a = *reinterpret_cast<const float4*>(&stage[pl * kStagePitch + 8 * cg]);
+                const float4 b = *reinterpret_cast<const float4*>(&stage[pl * kStagePitch + 8 * cg + 4]);
+                float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+                const long long o = ((long long)R * kRowW + 32 * wave + 16 * g2 + pl) * Cout + n0 + 8 * cg;
+                bf16x8 yv;
+                if constexpr (MODE == 0) {
+                    if (Zout) {
+                        *reinterpret_cast<float4*>(Zout + o) = a;
+                        *reinterpret_cast<float4*>(Zout + o + 4) = b;
+                    }
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) yv[e] = bf16(act ? silu(v[e]) : v[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) yv[e] = bf16(v[e] * silu_grad(zp[g2][i][e]));
+                }
+                *reinterpret_cast<bf16x8*>(Yout + o) = yv;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
 
 // ---- weight gradient: split-K implicit GEMM -------------------------------
 // part[s][tap][co][ci] = sum over the 64-pixel chunks of split s of dZ[p][co] x[p + off(tap)][ci].
@@ -754,7 +936,24 @@ lb_status launch_conv(sg_handle* h, int l, int mode, long long P, const bf16* x,
     const bf16* wk = ptr<bf16>(h, mode == 0 ? h->pl.wk_off[l] : h->pl.wt_off[l]);
     const float* bias = mode == 0 ? ptr<float>(h, h->pl.w_off) + h->pl.boff[l] : nullptr;
     const int act = mode == 0 && l + 1 < kLayers ? 1 : 0;
-    if (W % 128 == 0) {
+    if (W == kRowW && (Ci == 32 || Ci == 64)) {
+        const int rows_total = (int)(P / W);
+        const int nblk = Co / 64;
+        const int nwg = std::max(1, std::min(rows_total, 256 / nblk));   // one workgroup per CU
+        const int rpw = (rows_total + nwg - 1) / nwg;
+        const dim3 grid((unsigned)nwg, (unsigned)nblk);
+        if (mode == 0) {
+            if (Ci == 32)
+                hipLaunchKernelGGL((k_conv_rows<0, 32>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
+            else
+                hipLaunchKernelGGL((k_conv_rows<0, 64>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
+        } else {
+            if (Ci == 32)
+                hipLaunchKernelGGL((k_conv_rows<1, 32>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
+            else
+                hipLaunchKernelGGL((k_conv_rows<1, 64>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
+        }
+    } else if (W % 128 == 0) {
         const dim3 grid((unsigned)(P / 128), (unsigned)(Co / 64));
         if (mode == 0)
             hipLaunchKernelGGL(k_conv128<0>, grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, W, Ci, Co, act);
