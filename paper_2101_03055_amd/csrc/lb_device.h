@@ -465,8 +465,10 @@ __device__ __forceinline__ T lam_excess(const KParams<T>& kp, const T phi[M], in
 // ---- the node update ------------------------------------------------------
 // CONS (FP32 storage): the scalar rest populations take the remainder of the
 // species' post-collision mass in FP64, see below.
-// gS (may be NULL): gamma_a grad S_a / 6 per species and axis, the term of
-// D-bar (Eq. evolution12) that acts like the auxiliary source.
+// gS (may be NULL; read only when kp.gam_on): gamma_a grad S_a / 6 per species
+// and axis, the term of D-bar (Eq. evolution12) that acts like the auxiliary
+// source.  Callers pass their local array itself, never a pointer chosen at run
+// time: an array whose address is selected at run time lives in scratch memory.
 template <class T, int M, int MODEL, int COLL, bool CONS = false>
 __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5], const T Sold[M], T Snew[M],
                                         const T (*gS)[2] = nullptr) {
@@ -528,7 +530,7 @@ __device__ __forceinline__ void collide(const KParams<T>& kp, T h[9], T f[M][5],
     }
     // gamma of D-bar: (dt^2/2) gamma_a c_i . grad S_{i,a} with S_i = W_i S (Eq. source)
     // is 3 W_i c_i . (gamma_a grad S_a / 6), the form of G_i above
-    if (gS) {
+    if (gS && kp.gam_on) {
 #pragma unroll
         for (int a = 0; a < M; ++a) {
             g[a][0] += gS[a][0];

@@ -55,11 +55,12 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
     // step's source field (`sold`, not written by this launch when gamma != 0);
     // across a wall the node's own value stands in for the missing neighbour
     T gS[M][2];
+#pragma unroll
+    for (int a = 0; a < M; ++a) gS[a][0] = gS[a][1] = T(0);
     if (kp.gam_on) {
         k = 0;
 #pragma unroll
         for (int a = 0; a < M; ++a) {
-            gS[a][0] = gS[a][1] = T(0);
             if (kp.src_mask >> a & 1) {
                 const T* pl = sold + (long long)(k++) * N;
                 const long long xp = x + 1 < kp.nx ? n + 1 : (kp.sbc[1][a] == LB_SBC_PERIODIC ? n + 1 - kp.nx : n);
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
             }
         }
     }
-    collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, Sold, Snew, kp.gam_on ? gS : nullptr);
+    collide<T, M, MODEL, COLL, std::is_same_v<S, float>>(kp, h, f, Sold, Snew, gS);
     k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a)

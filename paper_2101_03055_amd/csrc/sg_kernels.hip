@@ -36,6 +36,8 @@ typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
 
 constexpr int kLayers = SG_LAYERS;
 constexpr int kCin[kLayers] = {15, 64, 128, 64, 64, 64};
@@ -327,6 +329,7 @@ __global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X
         const float* __restrict__ bias, const float* __restrict__ Zprev, float* __restrict__ Zout,
         bf16* __restrict__ Yout, int H, int rows_total, int rows_per_wg, int Cout, int act) {
     constexpr int S = CK / 8;                       // 16-byte segments per pixel / per weight row
+    static_assert(CK == 32 || CK == 64, "the operand read blocks are written for 32 and 64 K channels");
     constexpr int kWts = 9 * 64 * CK;               // bf16 of the workgroup's weights
     constexpr int kSlot = kRowPx * CK;              // bf16 per ring slot
     constexpr int kRowPieces = kRowPx * S;          // 16-byte pieces per input row
@@ -346,8 +349,11 @@ __global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X
 
     // weights of this workgroup's 64 output channels: piece q = (tap 64 + co) S + s, segment
     // s holding the 8 channels (s ^ (co & (S - 1))) so that the operand reads spread over the banks
-#pragma unroll
-    for (int r = 0; r < kWts / (256 * 8); ++r) {
+    // the rounds in an order rotated per workgroup: all workgroups read the same weights, and
+    // all of them starting on the first line would queue on the same L2 channels
+    constexpr int kWRounds = kWts / (256 * 8);
+    for (int rr = 0; rr < kWRounds; ++rr) {
+        const int r = (rr + (int)blockIdx.x) % kWRounds;
         const int q = (r * 4 + wave) * 64 + lane;
         const int tap = q / (64 * S), co = (q / S) % 64, ps = q % S;
         const int ls = ps ^ swz<CK>(co);
@@ -422,19 +428,44 @@ __global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X
                 const bf16* arow = slot + (size_t)pxi * CK;
                 const bf16* brow0 = Wts + (size_t)(tap * 64 + l32) * CK;
                 const bf16* brow1 = brow0 + (size_t)32 * CK;
+                // every operand of the tap in one asm block that waits for its own LDS reads
+                // (as plain loads the compiler would also wait for the row DMA still in flight
+                // to another ring slot); the next tap's reads overlap this tap's MFMAs
+                auto at = [&](const bf16* row, int h, int sw) { return lds_addr(row + 8 * ((2 * h + kg) ^ sw)); };
+                const int swa = swz<CK>(pxi);
+                if constexpr (CK == 64) {
+                    bf16x8 a[4], b0[4], b1[4];
+                    asm volatile(
+                        "ds_read_b128 %0, %12\n\tds_read_b128 %1, %13\n\tds_read_b128 %2, %14\n\tds_read_b128 %3, %15\n\t"
+                        "ds_read_b128 %4, %16\n\tds_read_b128 %5, %17\n\tds_read_b128 %6, %18\n\tds_read_b128 %7, %19\n\t"
+                        "ds_read_b128 %8, %20\n\tds_read_b128 %9, %21\n\tds_read_b128 %10, %22\n\tds_read_b128 %11, %23\n\t"
+                        "s_waitcnt lgkmcnt(0)"
+                        : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3]), "=&v"(b0[0]), "=&v"(b0[1]), "=&v"(b0[2]),
+                          "=&v"(b0[3]), "=&v"(b1[0]), "=&v"(b1[1]), "=&v"(b1[2]), "=&v"(b1[3])
+                        : "v"(at(arow, 0, swa)), "v"(at(arow, 1, swa)), "v"(at(arow, 2, swa)), "v"(at(arow, 3, swa)),
+                          "v"(at(brow0, 0, swzw)), "v"(at(brow0, 1, swzw)), "v"(at(brow0, 2, swzw)), "v"(at(brow0, 3, swzw)),
+                          "v"(at(brow1, 0, swzw)), "v"(at(brow1, 1, swzw)), "v"(at(brow1, 2, swzw)), "v"(at(brow1, 3, swzw))
+                        : "memory");
 #pragma unroll
-                for (int h = 0; h < CK / 16; ++h) {
-                    const int ls = 2 * h + kg;
-                    bf16x8 a, b0, b1;
-                    // one asm block waits for its own LDS reads: as plain loads the compiler would
-                    // also wait for the row DMA still in flight to another ring slot
-                    asm volatile("ds_read_b128 %0, %3\n\tds_read_b128 %1, %4\n\tds_read_b128 %2, %5\n\ts_waitcnt lgkmcnt(0)"
-                                 : "=&v"(a), "=&v"(b0), "=&v"(b1)
-                                 : "v"(lds_addr(arow + 8 * (ls ^ swz<CK>(pxi)))),
-                                   "v"(lds_addr(brow0 + 8 * (ls ^ swzw))), "v"(lds_addr(brow1 + 8 * (ls ^ swzw)))
-                                 : "memory");
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+                    for (int h = 0; h < 4; ++h) {
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b0[h], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b1[h], acc1, 0, 0, 0);
+                    }
+                } else {
+                    bf16x8 a[2], b0[2], b1[2];
+                    asm volatile(
+                        "ds_read_b128 %0, %6\n\tds_read_b128 %1, %7\n\tds_read_b128 %2, %8\n\t"
+                        "ds_read_b128 %3, %9\n\tds_read_b128 %4, %10\n\tds_read_b128 %5, %11\n\t"
+                        "s_waitcnt lgkmcnt(0)"
+                        : "=&v"(a[0]), "=&v"(a[1]), "=&v"(b0[0]), "=&v"(b0[1]), "=&v"(b1[0]), "=&v"(b1[1])
+                        : "v"(at(arow, 0, swa)), "v"(at(arow, 1, swa)), "v"(at(brow0, 0, swzw)), "v"(at(brow0, 1, swzw)),
+                          "v"(at(brow1, 0, swzw)), "v"(at(brow1, 1, swzw))
+                        : "memory");
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b0[h], acc0, 0, 0, 0);
+                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b1[h], acc1, 0, 0, 0);
+                    }
                 }
             }
         }
@@ -597,13 +628,173 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, cons
     }
 }
 
-// dW[co][tap][ci] (packed) = sum_s part[s][tap][co][ci], fixed order
-static_assert(kSplit % 4 == 0, "k_wgrad_reduce splits the partials in four");
+// ---- weight gradient: persistent row streaming (width 128) ----------------
+// part[s][tap][co][ci] for the 64 x CI block (co c0.., ci i0..) = the sum over the
+// image rows of split s of dZ[p][co] x[p + off(tap)][ci]; all nine taps at once.
+// A workgroup streams its run of whole rows through LDS (LDS DMA: dZ rows in two
+// slots, input rows with their halo pixels in a ring of four), one barrier per
+// row.  The reduction runs over pixels, and the channels-last rows become MFMA
+// operands with pixels along K through gfx950's transposing LDS read
+// (ds_read_b64_tr_b16: lane 4a + b of each 16-lane group receives element b of
+// the 8-byte chunks addressed by lanes a, a + 4, a + 8, a + 12).  Lane
+// L = 16 G + a + 4 t addresses the 4 channels 16 (G & 1) + 4 a.. of pixel
+// 8 (G >> 1) + t, so lane l receives channel l & 31 of pixels 8 (l >> 5) + 0..3
+// (+ 4..7 with a second read at pixel + 4): the operand layout of the 32x32x16
+// MFMA (row l & 31, k = 8 (l >> 5) + j).  The dx taps read the same input row at
+// pixel offsets 0, 1, 2 of the halo row.
+// CI = 64: wave w computes co 32 (w & 1).. x ci 32 (w >> 1).. of the nine taps.
+// CI = 32 (the first layer): waves w and w + 2 split the 16-pixel K steps of a
+// row between them and write separate partials (split index 2 s + (w >> 1)).
+// The ci-block-0 workgroups also sum dZ over their rows: bpart[s][co].
+template <int CI>
+__global__ __launch_bounds__(256, 1) void k_wgrad_rows(const bf16* __restrict__ dZ, const bf16* __restrict__ X,
+        float* __restrict__ part, float* __restrict__ bpart, int H, int rows_total, int rows_per_wg, int Ci, int Co) {
+    static_assert(CI == 32 || CI == 64, "input blocks of 32 or 64 channels");
+    constexpr int KH = 64 / CI;                 // waves sharing one (co, ci) quadrant over K
+    constexpr int SX = CI / 8;                  // 16-byte segments per input pixel
+    constexpr int kZSlot = kRowW * 64;          // dZ row: 128 px x 64 co
+    constexpr int kXSlot = kRowPx * CI;         // input row: 130 px (halo) x CI
+    constexpr int kXPieces = kRowPx * SX;
+    constexpr int kXFull = kXPieces / 256, kXRem = kXPieces - 256 * kXFull;
+    static_assert(kXRem % 4 == 0 && kXRem > 0 && kXRem / 4 <= 64, "remainder pieces split over the four wavefronts");
+    __shared__ __attribute__((aligned(16))) bf16 Zr[2 * kZSlot];
+    __shared__ __attribute__((aligned(16))) bf16 Xr[4 * kXSlot];
+    __shared__ float bred[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int s = blockIdx.x, c0 = blockIdx.y << 6, i0 = blockIdx.z * CI;
+    const int R0 = s * rows_per_wg, R1 = min(R0 + rows_per_wg, rows_total);
+    const bool bias = blockIdx.z == 0;
+    // dZ row Rg into slot Rg & 1: piece q = px 8 + ps holds the 8 channels (ps ^ swz<64>(px))
+    auto load_z = [&](int Rg) {
+        bf16* slot = Zr + (size_t)(Rg & 1) * kZSlot;
+        const bool rin = Rg >= 0 && Rg < rows_total;
+#pragma unroll
+        for (int r = 0; r < kZSlot / (256 * 8); ++r) {
+            const int base = (r * 4 + wave) * 64, q = base + lane;
+            const int px = q >> 3, ls = (q & 7) ^ swz<64>(px);
+            const void* src = rin ? (const void*)(dZ + ((long long)Rg * kRowW + px) * Co + c0 + 8 * ls) : (const void*)&kZero16;
+            __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)base * 8), 16, 0, 0);
+        }
+    };
+    // input row Rg into ring slot Rg & 3: piece q = px SX + ps, halo pixel px (image column px - 1)
+    auto load_x = [&](int Rg) {
+        bf16* slot = Xr + (size_t)(Rg & 3) * kXSlot;
+        const bool rin = Rg >= 0 && Rg < rows_total;
+#pragma unroll
+        for (int r = 0; r <= kXFull; ++r) {
+            const bool last = r == kXFull;
+            const int base = last ? kXFull * 256 + wave * (kXRem / 4) : (r * 4 + wave) * 64;
+            const bool on = !last || lane < kXRem / 4;
+            const int q = base + lane;
+            const int px = q / SX, ls = (q % SX) ^ swz<CI>(px);
+            const int x = px - 1;
+            const bool in = rin && on && x >= 0 && x < kRowW;
+            const void* src = in ? (const void*)(X + ((long long)Rg * kRowW + x) * Ci + i0 + 8 * ls) : (const void*)&kZero16;
+            if (on) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)base * 8), 16, 0, 0);
+        }
+    };
+    floatx16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+    float bsum = 0.f;
+    if (R0 < R1) {
+        load_x(R0 - 1);
+        load_x(R0);
+        load_x(R0 + 1);
+        load_z(R0);
+    }
+    const int G = lane >> 4, ta = lane & 3, tt = (lane >> 2) & 3;
+    const int tpx = 8 * (G >> 1) + tt;        // pixel of the addressed chunk within a 16-pixel K step
+    const int tch = 16 * (G & 1) + 4 * ta;    // its first channel within the wave's 32
+    const int cw = 32 * (wave & 1);
+    const int iw = KH == 1 ? 32 * (wave >> 1) : 0;
+    const int kh = KH == 1 ? 0 : wave >> 1;
+    auto lds_addr = [](const bf16* p) { return (uint32_t)(uintptr_t)p; };
+    // byte address of the 8-byte chunk of channels ch.. ch + 3 (ch a multiple of 4) of pixel px
+    auto zchunk = [&](const bf16* base, int px, int ch) {
+        return lds_addr(base + (size_t)px * 64 + 8 * ((ch >> 3) ^ swz<64>(px)) + (ch & 4));
+    };
+    auto xchunk = [&](const bf16* base, int px, int ch) {
+        return lds_addr(base + (size_t)px * CI + 8 * ((ch >> 3) ^ swz<CI>(px)) + (ch & 4));
+    };
+    // two 4-element reads side by side as one 8-element operand (a bit cast of the whole
+    // vector: this compiler reads element 0 for a bit cast of a vector-element lvalue)
+    auto pack = [](v4s lo, v4s hi) {
+        const v8s c = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_bit_cast(bf16x8, c);
+    };
+    for (int R = R0; R < R1; ++R) {
+        const int y = R % H;
+        wait_vm<0>();       // this wave's DMA of rows R (dZ) and R + 1 (input) has landed, then every wave's
+        __syncthreads();
+        if (R + 1 < R1) {   // into the slots of rows R - 2 (input) and R - 1 (dZ), read by no wave any more
+            load_x(R + 2);
+            load_z(R + 1);
+        }
+        const bf16* zrow = Zr + (size_t)(R & 1) * kZSlot;
+        // the transposing reads are asm blocks that wait for their own results: as builtins
+        // the compiler would also wait for the row DMA just issued
+#pragma unroll 1
+        for (int k0 = 16 * kh; k0 < kRowW; k0 += 16 * KH) {
+            v4s za, zb;
+            asm volatile("ds_read_b64_tr_b16 %0, %2\n\tds_read_b64_tr_b16 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                         : "=&v"(za), "=&v"(zb)
+                         : "v"(zchunk(zrow, k0 + tpx, cw + tch)), "v"(zchunk(zrow, k0 + tpx + 4, cw + tch))
+                         : "memory");
+            const bf16x8 A = pack(za, zb);
+#pragma unroll
+            for (int dyi = 0; dyi < 3; ++dyi) {
+                const int yy = y + dyi - 1;
+                if (yy < 0 || yy >= H) continue;   // outside the image the taps read zeros
+                const bf16* xrow = Xr + (size_t)((R + dyi - 1) & 3) * kXSlot;
+                const int px = k0 + tpx;          // halo pixel px + dxi is image pixel px + dx
+                v4s x0a, x0b, x1a, x1b, x2a, x2b;
+                asm volatile("ds_read_b64_tr_b16 %0, %6\n\tds_read_b64_tr_b16 %1, %7\n\t"
+                             "ds_read_b64_tr_b16 %2, %8\n\tds_read_b64_tr_b16 %3, %9\n\t"
+                             "ds_read_b64_tr_b16 %4, %10\n\tds_read_b64_tr_b16 %5, %11\n\ts_waitcnt lgkmcnt(0)"
+                             : "=&v"(x0a), "=&v"(x0b), "=&v"(x1a), "=&v"(x1b), "=&v"(x2a), "=&v"(x2b)
+                             : "v"(xchunk(xrow, px, iw + tch)), "v"(xchunk(xrow, px + 4, iw + tch)),
+                               "v"(xchunk(xrow, px + 1, iw + tch)), "v"(xchunk(xrow, px + 5, iw + tch)),
+                               "v"(xchunk(xrow, px + 2, iw + tch)), "v"(xchunk(xrow, px + 6, iw + tch))
+                             : "memory");
+                acc[3 * dyi + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, pack(x0a, x0b), acc[3 * dyi + 0], 0, 0, 0);
+                acc[3 * dyi + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, pack(x1a, x1b), acc[3 * dyi + 1], 0, 0, 0);
+                acc[3 * dyi + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, pack(x2a, x2b), acc[3 * dyi + 2], 0, 0, 0);
+            }
+        }
+        if (bias) {   // thread (wave, co) sums its 32 pixels in order (plain LDS reads, after the MFMA
+                      // loop: the compiler waits for the DMA in flight before them)
+            const int co = lane, pb = 32 * wave;
+            for (int p = 0; p < 32; ++p) {
+                const int px = pb + p;
+                bsum += float(zrow[(size_t)px * 64 + 8 * ((co >> 3) ^ swz<64>(px)) + (co & 7)]);
+            }
+        }
+    }
+    // this workgroup's partial sums; acc element e of lane l is D[8 (e >> 2) + 4 (l >> 5) + (e & 3)][l & 31]
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        float* dst = part + ((((long long)s * KH + kh) * 9 + tap) * Co + c0 + cw) * Ci + i0 + iw;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int m = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            dst[(long long)m * Ci + (lane & 31)] = acc[tap][e];
+        }
+    }
+    if (bias) {
+        bred[wave][lane] = bsum;
+        __syncthreads();
+        if (tid < 64) bpart[(long long)s * kMaxC + c0 + tid] = ((bred[0][tid] + bred[1][tid]) + bred[2][tid]) + bred[3][tid];
+    }
+}
 
-// dW = sum over the kSplit partials, in a fixed order: a workgroup covers 64
-// outputs, its wave g sums partials [g kSplit / 4, (g + 1) kSplit / 4) of them,
-// then the four wave sums are added in wave order
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int Ci, int Co,
+// dW[co][tap][ci] (packed) = sum_s part[s][tap][co][ci], fixed order
+// dW = sum over the ns partials, in a fixed order: a workgroup covers 64
+// outputs, its wave g sums partials [g ns / 4, (g + 1) ns / 4) of them, then
+// the four wave sums are added in wave order
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int ns, int Ci, int Co,
                                                       float* __restrict__ dW) {
     __shared__ float red[3][64];
     const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -612,9 +803,10 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     const bool live = k < n;
     float s = 0.f;
     if (live) {
-        const float* src = part + (long long)g * (kSplit / 4) * n + k;
+        const int q0 = g * ns / 4, q1 = (g + 1) * ns / 4;
+        const float* src = part + k;
 #pragma unroll 8
-        for (int q = 0; q < kSplit / 4; ++q) s += src[(long long)q * n];
+        for (int q = q0; q < q1; ++q) s += src[(long long)q * n];
     }
     if (g > 0) red[g - 1][j] = s;
     __syncthreads();
@@ -975,16 +1167,38 @@ lb_status launch_conv(sg_handle* h, int l, int mode, long long P, const bf16* x,
 lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const bf16* xin, float* dw, float* db) {
     const int H = h->c.height, W = h->c.width;
     const int Ci = kCinPad[l], Co = kCoutPad[l];
-    hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 3u * kSplit), dim3(256), 0, h->s,
-                       dz, xin, ptr<float>(h, h->pl.part_off), H, W, (int)P, Ci, Co);
-    SGCHK(hipGetLastError());
     const long long n = 9ll * Co * Ci;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s,
-                       ptr<float>(h, h->pl.part_off), Ci, Co, dw);
+    float* part = ptr<float>(h, h->pl.part_off);
+    float* bpart = ptr<float>(h, h->pl.bpart_off);
+    if (W == kRowW && (Ci == 32 || Ci % 64 == 0)) {
+        // one workgroup per CU over the (co, ci) blocks, each with a run of whole rows
+        const int rows_total = (int)(P / W);
+        const int cib = Ci == 32 ? 1 : Ci / 64, blocks = (Co / 64) * cib;
+        int nwg = std::max(1, std::min(rows_total, 256 / blocks));
+        const int rpw = (rows_total + nwg - 1) / nwg;
+        nwg = (rows_total + rpw - 1) / rpw;   // no workgroup without rows
+        const int ns = Ci == 32 ? 2 * nwg : nwg;
+        if ((long long)ns * n > (long long)kSplit * 9 * kMaxC * kMaxC || nwg > kRed) return LB_ENOMEM;
+        const dim3 grid((unsigned)nwg, (unsigned)(Co / 64), (unsigned)cib);
+        if (Ci == 32)
+            hipLaunchKernelGGL(k_wgrad_rows<32>, grid, dim3(256), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
+        else
+            hipLaunchKernelGGL(k_wgrad_rows<64>, grid, dim3(256), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
+        SGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s, part, ns, Ci, Co, dw);
+        SGCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, bpart, nwg, Co, db);
+        SGCHK(hipGetLastError());
+        return LB_OK;
+    }
+    hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 3u * kSplit), dim3(256), 0, h->s,
+                       dz, xin, part, H, W, (int)P, Ci, Co);
     SGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, ptr<float>(h, h->pl.bpart_off));
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s, part, kSplit, Ci, Co, dw);
     SGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, ptr<float>(h, h->pl.bpart_off), kRed, Co, db);
+    hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, bpart);
+    SGCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, bpart, kRed, Co, db);
     SGCHK(hipGetLastError());
     return LB_OK;
 }

@@ -4,9 +4,11 @@ the FP64 oracle (oracle/surrogate_oracle.py).
 Layer tests call one convolution or one weight gradient through the C ABI
 (sg_conv, sg_weight_grad) on seeded random inputs: bfloat16 operands made on
 the host, the same values handed to the oracle, so neither side sees the
-other's intermediates.  The 128-pixel workgroup tile (W % 128 == 0) is the one
-taken at 128 x 128; the weight gradient's split-K slices hold 2, 4 and 32
-chunks of 64 pixels at 1 x 128^2, 2 x 128^2 and the benchmarked 16 x 128^2.
+other's intermediates.  At width 128 (the training grids) the convolutions and
+the weight gradient stream whole image rows per workgroup (runs of 1 to 8 rows
+over the shapes below, 8 at the benchmarked 16 x 128^2); other widths that are
+multiples of 128 take the 128-pixel workgroup tile and the split-K weight
+gradient.
 
 Tolerances:
 * forward pre-activation z: FP32 accumulation of K = 9 cin_pad <= 1152 bf16
@@ -103,10 +105,11 @@ def test_data_gradient_convolutions_match_oracle(B, H, W):
         check_bf16_output(to_np(dout), want, f"layer {l} data gradient ({B}x{H}x{W})")
 
 
-@pytest.mark.parametrize("B", [1, 2])
-def test_weight_gradients_match_oracle_multichunk(B):
-    # 128^2 pixels per sample: 256 chunks of 64 pixels per sample over 128 splits
-    H = W = 128
+@pytest.mark.parametrize("B, H, W", [(1, 128, 128), (2, 128, 128), (1, 5, 128), (3, 37, 128), (1, 64, 256)])
+def test_weight_gradients_match_oracle_multichunk(B, H, W):
+    # width 128: the row-streaming kernel, runs of 1 (B = 1, 2 at 128^2, and 5 rows) or
+    # 1-2 rows (3 x 37 = 111 rows over the workgroups, 37 not a multiple of anything);
+    # width 256: the split-K kernel with 128 slices of 2 chunks of 64 pixels
     net, _, layers = make_net(B, H, W, seed=5)
     rng = np.random.default_rng(6)
     for l in range(len(layers)):
