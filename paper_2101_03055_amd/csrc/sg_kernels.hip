@@ -631,10 +631,14 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, cons
 // ---- weight gradient: persistent row streaming (width 128) ----------------
 // part[s][tap][co][ci] for the 64 x CI block (co c0.., ci i0..) = the sum over the
 // image rows of split s of dZ[p][co] x[p + off(tap)][ci]; all nine taps at once.
-// A workgroup streams its run of whole rows through LDS (LDS DMA: dZ rows in two
-// slots, input rows with their halo pixels in a ring of four), one barrier per
-// row.  The reduction runs over pixels, and the channels-last rows become MFMA
-// operands with pixels along K through gfx950's transposing LDS read
+// A workgroup streams its run of whole rows through LDS rings (dZ rows in three
+// slots, input rows with their halo pixels in five), two rows ahead, one barrier
+// per row.  One wavefront only moves the rows in (LDS DMA) and eight compute:
+// the computing wavefronts never have DMA of their own in flight, so their LDS
+// reads are plain loads that the compiler schedules against the MFMAs (it
+// waits for all DMA in flight before any LDS read of a wavefront that issued
+// some).  The reduction runs over pixels, and the channels-last rows become
+// MFMA operands with pixels along K through gfx950's transposing LDS read
 // (ds_read_b64_tr_b16: lane 4a + b of each 16-lane group receives element b of
 // the 8-byte chunks addressed by lanes a, a + 4, a + 8, a + 12).  Lane
 // L = 16 G + a + 4 t addresses the 4 channels 16 (G & 1) + 4 a.. of pixel
@@ -642,82 +646,114 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ dZ, cons
 // (+ 4..7 with a second read at pixel + 4): the operand layout of the 32x32x16
 // MFMA (row l & 31, k = 8 (l >> 5) + j).  The dx taps read the same input row at
 // pixel offsets 0, 1, 2 of the halo row.
-// CI = 64: wave w computes co 32 (w & 1).. x ci 32 (w >> 1).. of the nine taps.
-// CI = 32 (the first layer): waves w and w + 2 split the 16-pixel K steps of a
-// row between them and write separate partials (split index 2 s + (w >> 1)).
-// The ci-block-0 workgroups also sum dZ over their rows: bpart[s][co].
+// Computing wavefront w: quadrant q = w & 3, taps 0-4 (w < 4) or 5-8.  CI = 64:
+// quadrant q is co 32 (q & 1).. x ci 32 (q >> 1)..  CI = 32 (the first layer):
+// co 32 (q & 1).. x all 32 ci over every other 16-pixel K step (from 16 (q >> 1)),
+// written as separate partials (split index 2 s + (q >> 1)).
+// The ci-block-0 workgroups also sum dZ over their rows, from the dZ operands
+// of the taps-0-4 wavefronts: bpart[s][co].
+constexpr int kWgWaves = 9;   // 8 computing wavefronts and the one that moves rows in
+
 template <int CI>
-__global__ __launch_bounds__(256, 1) void k_wgrad_rows(const bf16* __restrict__ dZ, const bf16* __restrict__ X,
+__global__ __launch_bounds__(64 * kWgWaves, 1) void k_wgrad_rows(const bf16* __restrict__ dZ, const bf16* __restrict__ X,
         float* __restrict__ part, float* __restrict__ bpart, int H, int rows_total, int rows_per_wg, int Ci, int Co) {
     static_assert(CI == 32 || CI == 64, "input blocks of 32 or 64 channels");
-    constexpr int KH = 64 / CI;                 // waves sharing one (co, ci) quadrant over K
+    constexpr int KH = 64 / CI;                 // K-step phases of one (co, ci) quadrant
     constexpr int SX = CI / 8;                  // 16-byte segments per input pixel
     constexpr int kZSlot = kRowW * 64;          // dZ row: 128 px x 64 co
     constexpr int kXSlot = kRowPx * CI;         // input row: 130 px (halo) x CI
+    constexpr int kZSlots = 3, kXSlots = 5;     // rows R .. R + 2 of dZ, R - 1 .. R + 3 of the input
+    constexpr int kZLoads = kZSlot / (64 * 8);  // DMA instructions per dZ row (64 lanes x 16 bytes each)
     constexpr int kXPieces = kRowPx * SX;
-    constexpr int kXFull = kXPieces / 256, kXRem = kXPieces - 256 * kXFull;
-    static_assert(kXRem % 4 == 0 && kXRem > 0 && kXRem / 4 <= 64, "remainder pieces split over the four wavefronts");
-    __shared__ __attribute__((aligned(16))) bf16 Zr[2 * kZSlot];
-    __shared__ __attribute__((aligned(16))) bf16 Xr[4 * kXSlot];
+    constexpr int kXLoads = (kXPieces + 63) / 64;
+    constexpr int kXTail = kXPieces - 64 * (kXLoads - 1);   // lanes of the last input-row instruction
+    constexpr int kRowLoads = kZLoads + kXLoads;            // per row, all issued by the moving wavefront
+    static_assert(kRowLoads < 64, "wait_vm counts below 64");
+    __shared__ __attribute__((aligned(16))) bf16 Zr[kZSlots * kZSlot];
+    __shared__ __attribute__((aligned(16))) bf16 Xr[kXSlots * kXSlot];
     __shared__ float bred[4][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int s = blockIdx.x, c0 = blockIdx.y << 6, i0 = blockIdx.z * CI;
     const int R0 = s * rows_per_wg, R1 = min(R0 + rows_per_wg, rows_total);
     const bool bias = blockIdx.z == 0;
-    // dZ row Rg into slot Rg & 1: piece q = px 8 + ps holds the 8 channels (ps ^ swz<64>(px))
-    auto load_z = [&](int Rg) {
-        bf16* slot = Zr + (size_t)(Rg & 1) * kZSlot;
-        const bool rin = Rg >= 0 && Rg < rows_total;
+    auto zslot = [&](int Rg) { return Zr + (size_t)((Rg + kZSlots) % kZSlots) * kZSlot; };
+    auto xslot = [&](int Rg) { return Xr + (size_t)((Rg + kXSlots) % kXSlots) * kXSlot; };   // Rg >= -1
+    if (wave == 8) {
+        // dZ row Rg: piece q = px 8 + ps holds the 8 channels (ps ^ swz<64>(px)); input row Rg:
+        // piece q = px SX + ps, halo pixel px (image column px - 1)
+        auto load_z = [&](int Rg) {
+            bf16* slot = zslot(Rg);
+            const bool rin = Rg >= 0 && Rg < rows_total;
 #pragma unroll
-        for (int r = 0; r < kZSlot / (256 * 8); ++r) {
-            const int base = (r * 4 + wave) * 64, q = base + lane;
-            const int px = q >> 3, ls = (q & 7) ^ swz<64>(px);
-            const void* src = rin ? (const void*)(dZ + ((long long)Rg * kRowW + px) * Co + c0 + 8 * ls) : (const void*)&kZero16;
-            __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)base * 8), 16, 0, 0);
+            for (int r = 0; r < kZLoads; ++r) {
+                const int q = r * 64 + lane;
+                const int px = q >> 3, ls = (q & 7) ^ swz<64>(px);
+                const void* src = rin ? (const void*)(dZ + ((long long)Rg * kRowW + px) * Co + c0 + 8 * ls) : (const void*)&kZero16;
+                __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)r * 64 * 8), 16, 0, 0);
+            }
+        };
+        auto load_x = [&](int Rg) {
+            bf16* slot = xslot(Rg);
+            const bool rin = Rg >= 0 && Rg < rows_total;
+#pragma unroll
+            for (int r = 0; r < kXLoads; ++r) {
+                const bool on = r < kXLoads - 1 || lane < kXTail;
+                const int q = r * 64 + lane;
+                const int px = q / SX, ls = (q % SX) ^ swz<CI>(px);
+                const int x = px - 1;
+                const bool in = rin && on && x >= 0 && x < kRowW;
+                const void* src = in ? (const void*)(X + ((long long)Rg * kRowW + x) * Ci + i0 + 8 * ls) : (const void*)&kZero16;
+                if (on) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)r * 64 * 8), 16, 0, 0);
+            }
+        };
+        if (R0 < R1) {
+            load_x(R0 - 1);
+            load_x(R0);
+            load_x(R0 + 1);
+            load_z(R0);
+            if (R0 + 1 < R1) {
+                load_x(R0 + 2);
+                load_z(R0 + 1);
+            }
         }
-    };
-    // input row Rg into ring slot Rg & 3: piece q = px SX + ps, halo pixel px (image column px - 1)
-    auto load_x = [&](int Rg) {
-        bf16* slot = Xr + (size_t)(Rg & 3) * kXSlot;
-        const bool rin = Rg >= 0 && Rg < rows_total;
-#pragma unroll
-        for (int r = 0; r <= kXFull; ++r) {
-            const bool last = r == kXFull;
-            const int base = last ? kXFull * 256 + wave * (kXRem / 4) : (r * 4 + wave) * 64;
-            const bool on = !last || lane < kXRem / 4;
-            const int q = base + lane;
-            const int px = q / SX, ls = (q % SX) ^ swz<CI>(px);
-            const int x = px - 1;
-            const bool in = rin && on && x >= 0 && x < kRowW;
-            const void* src = in ? (const void*)(X + ((long long)Rg * kRowW + x) * Ci + i0 + 8 * ls) : (const void*)&kZero16;
-            if (on) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)base * 8), 16, 0, 0);
+        for (int R = R0; R < R1; ++R) {
+            // rows R + 1 (input) and R (dZ) have landed; the loads of rows R + 2 and R + 1,
+            // issued one row earlier (when R + 1 < R1), may still be in flight
+            if (R + 1 < R1) wait_vm<kRowLoads>(); else wait_vm<0>();
+            __builtin_amdgcn_s_barrier();
+            if (R + 2 < R1) {   // into the slots of rows R - 2 (input) and R - 1 (dZ), which no wave reads any more
+                load_x(R + 3);
+                load_z(R + 2);
+            }
         }
-    };
-    floatx16 acc[9];
+        __syncthreads();    // pairs with the computing wavefronts' barrier before the bias sums
+        return;
+    }
+    const int q = wave & 3, g = wave >> 2;
+    const int cw = 32 * (q & 1);
+    const int iw = KH == 1 ? 32 * (q >> 1) : 0;
+    const int kh = KH == 1 ? 0 : q >> 1;
+    const bool bsums = bias && g == 0 && (KH == 2 || q < 2);
+    constexpr int kSteps = kRowW / (16 * KH);   // this wavefront's 16-pixel K steps per row
+    floatx16 acc[5];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < 5; ++t)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
     float bsum = 0.f;
-    if (R0 < R1) {
-        load_x(R0 - 1);
-        load_x(R0);
-        load_x(R0 + 1);
-        load_z(R0);
-    }
     const int G = lane >> 4, ta = lane & 3, tt = (lane >> 2) & 3;
     const int tpx = 8 * (G >> 1) + tt;        // pixel of the addressed chunk within a 16-pixel K step
     const int tch = 16 * (G & 1) + 4 * ta;    // its first channel within the wave's 32
-    const int cw = 32 * (wave & 1);
-    const int iw = KH == 1 ? 32 * (wave >> 1) : 0;
-    const int kh = KH == 1 ? 0 : wave >> 1;
-    auto lds_addr = [](const bf16* p) { return (uint32_t)(uintptr_t)p; };
-    // byte address of the 8-byte chunk of channels ch.. ch + 3 (ch a multiple of 4) of pixel px
-    auto zchunk = [&](const bf16* base, int px, int ch) {
-        return lds_addr(base + (size_t)px * 64 + 8 * ((ch >> 3) ^ swz<64>(px)) + (ch & 4));
+    typedef __attribute__((address_space(3))) short lshort;
+    typedef __attribute__((address_space(3))) v4s lv4s;
+    // the 8-byte chunk of channels ch.. ch + 3 (ch a multiple of 4) of pixel px, transposed
+    auto ztr = [&](const bf16* base, int px, int ch) {
+        const bf16* p = base + (size_t)px * 64 + 8 * ((ch >> 3) ^ swz<64>(px)) + (ch & 4);
+        return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lv4s*)(lshort*)p);
     };
-    auto xchunk = [&](const bf16* base, int px, int ch) {
-        return lds_addr(base + (size_t)px * CI + 8 * ((ch >> 3) ^ swz<CI>(px)) + (ch & 4));
+    auto xtr = [&](const bf16* base, int px, int ch) {
+        const bf16* p = base + (size_t)px * CI + 8 * ((ch >> 3) ^ swz<CI>(px)) + (ch & 4);
+        return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lv4s*)(lshort*)p);
     };
     // two 4-element reads side by side as one 8-element operand (a bit cast of the whole
     // vector: this compiler reads element 0 for a bit cast of a vector-element lvalue)
@@ -725,68 +761,68 @@ __global__ __launch_bounds__(256, 1) void k_wgrad_rows(const bf16* __restrict__ 
         const v8s c = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
         return __builtin_bit_cast(bf16x8, c);
     };
+    auto xop = [&](const bf16* xr, int px, int dxi) { return pack(xtr(xr, px + dxi, iw + tch), xtr(xr, px + dxi + 4, iw + tch)); };
     for (int R = R0; R < R1; ++R) {
         const int y = R % H;
-        wait_vm<0>();       // this wave's DMA of rows R (dZ) and R + 1 (input) has landed, then every wave's
-        __syncthreads();
-        if (R + 1 < R1) {   // into the slots of rows R - 2 (input) and R - 1 (dZ), read by no wave any more
-            load_x(R + 2);
-            load_z(R + 1);
-        }
-        const bf16* zrow = Zr + (size_t)(R & 1) * kZSlot;
-        // the transposing reads are asm blocks that wait for their own results: as builtins
-        // the compiler would also wait for the row DMA just issued
-#pragma unroll 1
-        for (int k0 = 16 * kh; k0 < kRowW; k0 += 16 * KH) {
-            v4s za, zb;
-            asm volatile("ds_read_b64_tr_b16 %0, %2\n\tds_read_b64_tr_b16 %1, %3\n\ts_waitcnt lgkmcnt(0)"
-                         : "=&v"(za), "=&v"(zb)
-                         : "v"(zchunk(zrow, k0 + tpx, cw + tch)), "v"(zchunk(zrow, k0 + tpx + 4, cw + tch))
-                         : "memory");
-            const bf16x8 A = pack(za, zb);
+        __builtin_amdgcn_s_barrier();   // the moving wavefront has seen rows R + 1 (input) and R (dZ) land
+        const bf16* zrow = zslot(R);
+        const bf16* xr0 = xslot(R - 1);
+        const bf16* xr1 = xslot(R);
+        const bf16* xr2 = xslot(R + 1);
+        const bool up = y > 0, dn = y + 1 < H;   // outside the image the taps read zeros
+        if (g == 0) {
+#pragma unroll 2
+            for (int i = 0; i < kSteps; ++i) {
+                const int px = 16 * (kh + KH * i) + tpx;
+                const bf16x8 A = pack(ztr(zrow, px, cw + tch), ztr(zrow, px + 4, cw + tch));
+                if (bsums) {   // dZ of channel cw + (l & 31) at pixels k0 + 8 (l >> 5) + 0..7
 #pragma unroll
-            for (int dyi = 0; dyi < 3; ++dyi) {
-                const int yy = y + dyi - 1;
-                if (yy < 0 || yy >= H) continue;   // outside the image the taps read zeros
-                const bf16* xrow = Xr + (size_t)((R + dyi - 1) & 3) * kXSlot;
-                const int px = k0 + tpx;          // halo pixel px + dxi is image pixel px + dx
-                v4s x0a, x0b, x1a, x1b, x2a, x2b;
-                asm volatile("ds_read_b64_tr_b16 %0, %6\n\tds_read_b64_tr_b16 %1, %7\n\t"
-                             "ds_read_b64_tr_b16 %2, %8\n\tds_read_b64_tr_b16 %3, %9\n\t"
-                             "ds_read_b64_tr_b16 %4, %10\n\tds_read_b64_tr_b16 %5, %11\n\ts_waitcnt lgkmcnt(0)"
-                             : "=&v"(x0a), "=&v"(x0b), "=&v"(x1a), "=&v"(x1b), "=&v"(x2a), "=&v"(x2b)
-                             : "v"(xchunk(xrow, px, iw + tch)), "v"(xchunk(xrow, px + 4, iw + tch)),
-                               "v"(xchunk(xrow, px + 1, iw + tch)), "v"(xchunk(xrow, px + 5, iw + tch)),
-                               "v"(xchunk(xrow, px + 2, iw + tch)), "v"(xchunk(xrow, px + 6, iw + tch))
-                             : "memory");
-                acc[3 * dyi + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, pack(x0a, x0b), acc[3 * dyi + 0], 0, 0, 0);
-                acc[3 * dyi + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, pack(x1a, x1b), acc[3 * dyi + 1], 0, 0, 0);
-                acc[3 * dyi + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, pack(x2a, x2b), acc[3 * dyi + 2], 0, 0, 0);
+                    for (int j = 0; j < 8; ++j) bsum += float(A[j]);
+                }
+                if (up) {
+                    acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr0, px, 0), acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr0, px, 1), acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr0, px, 2), acc[2], 0, 0, 0);
+                }
+                acc[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr1, px, 0), acc[3], 0, 0, 0);
+                acc[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr1, px, 1), acc[4], 0, 0, 0);
             }
-        }
-        if (bias) {   // thread (wave, co) sums its 32 pixels in order (plain LDS reads, after the MFMA
-                      // loop: the compiler waits for the DMA in flight before them)
-            const int co = lane, pb = 32 * wave;
-            for (int p = 0; p < 32; ++p) {
-                const int px = pb + p;
-                bsum += float(zrow[(size_t)px * 64 + 8 * ((co >> 3) ^ swz<64>(px)) + (co & 7)]);
+        } else {
+#pragma unroll 2
+            for (int i = 0; i < kSteps; ++i) {
+                const int px = 16 * (kh + KH * i) + tpx;
+                const bf16x8 A = pack(ztr(zrow, px, cw + tch), ztr(zrow, px + 4, cw + tch));
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr1, px, 2), acc[0], 0, 0, 0);
+                if (dn) {
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr2, px, 0), acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr2, px, 1), acc[2], 0, 0, 0);
+                    acc[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, xop(xr2, px, 2), acc[3], 0, 0, 0);
+                }
             }
         }
     }
-    // this workgroup's partial sums; acc element e of lane l is D[8 (e >> 2) + 4 (l >> 5) + (e & 3)][l & 31]
+    // this wavefront's partial sums; acc element e of lane l is D[8 (e >> 2) + 4 (l >> 5) + (e & 3)][l & 31]
+    const int t0 = g == 0 ? 0 : 5, nt = g == 0 ? 5 : 4;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        float* dst = part + ((((long long)s * KH + kh) * 9 + tap) * Co + c0 + cw) * Ci + i0 + iw;
+    for (int t = 0; t < 5; ++t) {
+        if (t < nt) {
+            float* dst = part + ((((long long)s * KH + kh) * 9 + t0 + t) * Co + c0 + cw) * Ci + i0 + iw;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int m = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-            dst[(long long)m * Ci + (lane & 31)] = acc[tap][e];
+            for (int e = 0; e < 16; ++e) {
+                const int m = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                dst[(long long)m * Ci + (lane & 31)] = acc[t][e];
+            }
         }
     }
-    if (bias) {
-        bred[wave][lane] = bsum;
-        __syncthreads();
-        if (tid < 64) bpart[(long long)s * kMaxC + c0 + tid] = ((bred[0][tid] + bred[1][tid]) + bred[2][tid]) + bred[3][tid];
+    if (g == 0) bred[q][lane] = bsum;
+    __syncthreads();
+    if (bias && tid < 64) {
+        // channel co: quadrant co >> 5 (and + 2: the other K phase, CI = 32), lanes co & 31 (pixels
+        // 0..7 of each K step) and + 32 (8..15); fixed order
+        const int h = tid >> 5, l = tid & 31;
+        float v = bred[h][l] + bred[h][l + 32];
+        if (KH == 2) v += bred[h + 2][l] + bred[h + 2][l + 32];
+        bpart[(long long)s * kMaxC + c0 + tid] = v;
     }
 }
 
@@ -1181,9 +1217,9 @@ lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const b
         if ((long long)ns * n > (long long)kSplit * 9 * kMaxC * kMaxC || nwg > kRed) return LB_ENOMEM;
         const dim3 grid((unsigned)nwg, (unsigned)(Co / 64), (unsigned)cib);
         if (Ci == 32)
-            hipLaunchKernelGGL(k_wgrad_rows<32>, grid, dim3(256), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
+            hipLaunchKernelGGL(k_wgrad_rows<32>, grid, dim3(64 * kWgWaves), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
         else
-            hipLaunchKernelGGL(k_wgrad_rows<64>, grid, dim3(256), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
+            hipLaunchKernelGGL(k_wgrad_rows<64>, grid, dim3(64 * kWgWaves), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
         SGCHK(hipGetLastError());
         hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s, part, ns, Ci, Co, dw);
         SGCHK(hipGetLastError());
