@@ -98,6 +98,36 @@ def test_ddc_cavity_reproduces_paper_table(Ra):
     assert -cold[1] == pytest.approx(hot[1], rel=5e-3)
 
 
+# Table 2 on the paper's own 300 x 600 grid, Ra = 1e5 .. 1e7 (same parameters):
+# (Ra, collision, lattice velocity scale, steady tolerance, relative bound).  At
+# Ra = 1e5 the solver lands within 1e-4 of the printed values.  At Ra = 1e6 and
+# 1e7 it lands 0.6-0.8 % below them; at Ra = 1e6 that offset is a property of
+# the converged solution, not of this grid or time step (128, 200 and 300 nodes
+# across and lattice velocity scales 0.025-0.2 all give Nu 5.169-5.191, Sh
+# 8.494-8.518, against 5.2338 / 8.5781).  Ra = 1e7 runs the MRT collision
+# (tau_f = 0.557 with BGK it converges too, 0.4 % lower) to the paper's own
+# steady criterion (relative change 1e-7).
+TABLE2_FINE = {1e5: ("bgk", 0.1, 1e-9, 1e-3), 1e6: ("bgk", 0.2, 1e-9, 1e-2), 1e7: ("mrt", 0.2, 1e-7, 1e-2)}
+TABLE2_ALL = {**TABLE2, 1e6: (5.2338, 8.5781), 1e7: (9.4138, 15.496)}
+
+
+@pytest.mark.parametrize("Ra", sorted(TABLE2_FINE))
+def test_ddc_cavity_on_the_papers_grid(Ra):
+    coll, u_lat, tol, rel = TABLE2_FINE[Ra]
+    wl, phi0, u0, p0 = W.ddc(300, Ra=Ra, Pr=1.0, Le=2.0, Nc=-2.0, Sr=0.1, Df=0.1, A=2.0, u_lat=u_lat, collision=coll)
+    s = lb.Solver(wl, phi0, u0, p0)
+    steps, res, st = s.solve_steady(tol=tol, check_every=2000, max_steps=16_000_000)
+    hot = lb.lb_wall_flux(s.handle, 0, 2)
+    cold = lb.lb_wall_flux(s.handle, 1, 2)
+    nu, sh = TABLE2_ALL[Ra]
+    print(f"Ra {Ra:g} (300 x 600, {coll}): steps {steps} Nu {hot[0]:.5f} ({nu}) Sh {hot[1]:.5f} ({sh})", flush=True)
+    assert st == lb.LB_OK, (steps, res)
+    assert hot[0] == pytest.approx(nu, rel=rel)
+    assert hot[1] == pytest.approx(sh, rel=rel)
+    assert -cold[0] == pytest.approx(hot[0], rel=1e-4)
+    assert -cold[1] == pytest.approx(hot[1], rel=1e-4)
+
+
 # Table 3 (aspect ratio A, Ra = 1e5) and Table 4 (S_TC = D_CT, Ra = 1e5, A = 2),
 # Pr = 1, Le = 2, Nc = -2, "Present" columns: (A, S_TC = D_CT) -> (Nu, Sh)
 TABLES34 = {(0.5, 0.1): (2.2893, 4.3113), (1.0, 0.1): (2.8925, 4.9596), (4.0, 0.1): (2.6508, 4.1383),
