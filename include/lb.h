@@ -237,6 +237,22 @@ lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes);
  * is reset.  Synchronises both streams. */
 lb_status lb_copy_state(lb_handle* dst, lb_handle* src);
 
+/* Fluid reference pressure per row (a storage detail; results are unchanged in
+ * exact arithmetic).  With a reference P(y) the stored fluid populations of
+ * row y are h_i minus the rest equilibrium at pressure P(y) (Eq. heq at u = 0:
+ * r_0 = -(5/3) P, r_i = 3 W_i P for i > 0, so sum_i r_i = 0 and no moment but
+ * the pressure changes), and values that stream between rows change reference
+ * on the way.  A flow close to hydrostatic balance (Sec. 3.1: buoyancy balanced
+ * by a vertical pressure gradient) then stores only its departure from that
+ * balance, so FP32 storage rounds a much smaller number.
+ * mode 1: P(y) = the row mean of the current pressure (FP64 sums, fixed order,
+ * then rounded to the storage's arithmetic type), and every stored fluid value
+ * is moved to it; call again to follow a changing balance.  mode 0: back to no
+ * reference.  lb_moments, lb_populations, lb_save/lb_load and lb_copy_state see
+ * and keep the absolute values.  Not for the no-fluid model or fused_steps = 2
+ * (LB_EINVAL).  Synchronises the stream. */
+lb_status lb_fluid_reference(lb_handle* h, int32_t mode);
+
 /* Launch shape of the step kernel: tile_x * tile_y threads per workgroup,
  * tile_x a multiple of 64 (one wavefront per row segment), product <= 1024.
  * (0, 0) restores the default.  Used by the autotuner. */

@@ -43,7 +43,7 @@ lb_status fail(lb_status st, const char* fmt, ...) {
                         __LINE__);                                                                 \
     } while (0)
 
-constexpr uint64_t kMagic = 0x4c42434446303031ull;  // "LBCDF001"
+constexpr uint64_t kMagic = 0x4c42434446303032ull;  // "LBCDF002"
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -95,6 +95,8 @@ Layout make_layout(const lb_params& p) {
     off += round_up((size_t)kRedBlocks * kRedWidth * 8, 256);
     L.res_off = off;
     off += 256 * 8;
+    L.pref_off = off;
+    off += round_up((size_t)p.ny * 8, 256);
     L.pop2_off = L.pop_off;
     L.sold2_off = L.sold_off;
     if (gamma_on(p) && p.fused_steps != 2) {
@@ -393,6 +395,7 @@ struct lb_handle {
     hipGraphExec_t gexec = nullptr;
     Launch glc{0, 0};
     size_t gsold = 0;    // source buffer the graph's first launch reads (gamma != 0 alternates two)
+    int href = 0;        // a fluid reference pressure per row is in use (kd.pref / kf.pref set)
     ~lb_handle() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -433,6 +436,7 @@ struct StateHeader {
     int64_t has_snapshot;
     uint64_t param_hash;
     uint64_t pop_bytes, sold_bytes, snap_bytes;
+    int64_t href;        // the fluid reference pressure (ny values of the arithmetic type) follows the snapshot
 };
 
 uint64_t fnv(const void* data, size_t n) {
@@ -448,6 +452,19 @@ uint64_t fnv(const void* data, size_t n) {
 size_t sold_bytes(const lb_handle* h) { return (h->L.nsrc + h->L.naux) * h->L.N * arith_bytes(h->p.storage); }
 size_t snap_bytes(const lb_handle* h) { return (size_t)(h->p.m + 2) * h->L.N * 8; }
 size_t pop_bytes(const lb_handle* h) { return h->L.npop * h->L.plane * h->L.elem; }
+size_t pref_bytes(const lb_handle* h) { return (size_t)h->p.ny * arith_bytes(h->p.storage); }
+
+// point the kernels' parameter blocks at the reference array (on) or at none;
+// the cached step graph holds the parameter blocks by value and is rebuilt
+void set_pref(lb_handle* h, bool on) {
+    h->kd.pref = on ? (const double*)at(h->ws, h->L.pref_off) : nullptr;
+    h->kf.pref = on ? (const float*)at(h->ws, h->L.pref_off) : nullptr;
+    h->href = on ? 1 : 0;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
 }  // namespace
 
 extern "C" {
@@ -807,6 +824,37 @@ lb_status lb_populations(lb_handle* h, double* f, double* hpop) {
     return LB_OK;
 }
 
+lb_status lb_fluid_reference(lb_handle* h, int32_t mode) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (mode != 0 && mode != 1) return fail(LB_EINVAL, "mode must be 0 (none) or 1 (row means of the pressure)");
+    if (h->p.model == LB_MODEL_CDE) return fail(LB_EINVAL, "lb_fluid_reference: the no-fluid model has no fluid");
+    if (h->p.fused_steps == 2) return fail(LB_EINVAL, "lb_fluid_reference: not with two steps per launch");
+    if (mode == 0 && !h->href) return LB_OK;
+    const size_t ny = (size_t)h->p.ny;
+    double* rows = (double*)at(h->ws, h->L.stage_off);   // row means (FP64), then the new reference
+    void* pnew = rows + ny;                               // in the arithmetic type
+    hipError_t e = hipSuccess;
+    if (mode == 1) {
+        e = launch_row_pressure(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, rows, h->stream);
+        if (e == hipSuccess) {
+            if (h->p.storage == LB_STORE_F64)
+                e = hipMemcpyAsync(pnew, rows, ny * 8, hipMemcpyDeviceToDevice, h->stream);
+            else
+                e = launch_to_float(rows, (float*)pnew, (long long)ny, h->stream);
+        }
+    } else {
+        e = hipMemsetAsync(pnew, 0, ny * arith_bytes(h->p.storage), h->stream);
+    }
+    if (e == hipSuccess) e = launch_reref(h->p, h->L, h->ws, h->kd, h->kf, pnew, h->stream);
+    if (e == hipSuccess && mode == 1)
+        e = hipMemcpyAsync(at(h->ws, h->L.pref_off), pnew, ny * arith_bytes(h->p.storage), hipMemcpyDeviceToDevice,
+                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(LB_EDEVICE, "lb_fluid_reference: %s", hipGetErrorString(e));
+    set_pref(h, mode == 1);
+    return LB_OK;
+}
+
 lb_status lb_time(lb_handle* h, int64_t* t) {
     if (!h || !t) return fail(LB_EINVAL, "NULL argument");
     *t = h->t;
@@ -815,7 +863,7 @@ lb_status lb_time(lb_handle* h, int64_t* t) {
 
 lb_status lb_state_bytes(lb_handle* h, size_t* bytes) {
     if (!h || !bytes) return fail(LB_EINVAL, "NULL argument");
-    *bytes = sizeof(StateHeader) + pop_bytes(h) + sold_bytes(h) + snap_bytes(h);
+    *bytes = sizeof(StateHeader) + pop_bytes(h) + sold_bytes(h) + snap_bytes(h) + pref_bytes(h);
     return LB_OK;
 }
 
@@ -824,7 +872,8 @@ lb_status lb_save(lb_handle* h, void* host_buf, size_t bytes) {
     lb_status st = lb_state_bytes(h, &need);
     if (st != LB_OK) return st;
     if (!host_buf || bytes < need) return fail(LB_EINVAL, "buffer of %zu bytes, %zu needed", bytes, need);
-    StateHeader hd{kMagic, h->t, h->parity, h->has_snapshot, fnv(&h->p, sizeof h->p), pop_bytes(h), sold_bytes(h), snap_bytes(h)};
+    StateHeader hd{kMagic, h->t, h->parity, h->has_snapshot, fnv(&h->p, sizeof h->p), pop_bytes(h), sold_bytes(h), snap_bytes(h),
+                   h->href};
     char* b = static_cast<char*>(host_buf);
     std::memcpy(b, &hd, sizeof hd);
     b += sizeof hd;
@@ -833,6 +882,9 @@ lb_status lb_save(lb_handle* h, void* host_buf, size_t bytes) {
     if (hd.sold_bytes) HIPCHK(hipMemcpyAsync(b, at(h->ws, h->L.sold_off), hd.sold_bytes, hipMemcpyDeviceToHost, h->stream));
     b += hd.sold_bytes;
     HIPCHK(hipMemcpyAsync(b, at(h->ws, h->L.snap_off), hd.snap_bytes, hipMemcpyDeviceToHost, h->stream));
+    b += hd.snap_bytes;
+    if (h->href) HIPCHK(hipMemcpyAsync(b, at(h->ws, h->L.pref_off), pref_bytes(h), hipMemcpyDeviceToHost, h->stream));
+    else std::memset(b, 0, pref_bytes(h));
     HIPCHK(hipStreamSynchronize(h->stream));
     return LB_OK;
 }
@@ -855,7 +907,10 @@ lb_status lb_load(lb_handle* h, const void* host_buf, size_t bytes) {
     if (hd.sold_bytes) HIPCHK(hipMemcpyAsync(at(h->ws, h->L.sold_off), b, hd.sold_bytes, hipMemcpyHostToDevice, h->stream));
     b += hd.sold_bytes;
     HIPCHK(hipMemcpyAsync(at(h->ws, h->L.snap_off), b, hd.snap_bytes, hipMemcpyHostToDevice, h->stream));
+    b += hd.snap_bytes;
+    if (hd.href) HIPCHK(hipMemcpyAsync(at(h->ws, h->L.pref_off), b, pref_bytes(h), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    if ((hd.href != 0) != (h->href != 0)) set_pref(h, hd.href != 0);
     h->t = hd.t;
     h->parity = (int)hd.parity;
     h->has_snapshot = (int)hd.has_snapshot;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>*
     T* sold = reinterpret_cast<T*>(ws + cr.sold_off);
 
     T h[9], f[M][5], Sold[M], Snew[M];
-    gather<S, M, ODD, NT>(kp, pop, x, y, h, f);
+    gather<S, M, ODD, NT, false>(kp, pop, x, y, h, f);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>*
 #pragma unroll
     for (int a = 0; a < M; ++a)
         if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold[(long long)(k++) * N + n]);
-    scatter<S, M, ODD, NT>(kp, pop, x, y, h, f, salt);
+    scatter<S, M, ODD, NT, false>(kp, pop, x, y, h, f, salt);
 }
 
 // the batched step kernel for a collision kind, parity and cache hint
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_breduce(const KParams<typename St<S>::T
         const S* pop = reinterpret_cast<const S*>(ws + cr.pop_off);
         double* snap = reinterpret_cast<double*>(ws + cr.snap_off);
         T h[9], f[M][5];
-        gather<S, M, ODD>(kp, pop, x, y, h, f);
+        gather<S, M, ODD, false, false>(kp, pop, x, y, h, f);
         Macro<T, M> mc;
         macro<T, M>(kp, h, f, mc);
         double q[Q];

@@ -273,7 +273,22 @@ struct WallFlags {
 // Canonical pre-collision populations of node (x, y).  PULL = false: the own
 // slots (state after an odd step or initialisation).  PULL = true: the state
 // left by an even step, read from the upstream neighbours with the wall rules.
-template <class S, int M, bool PULL, bool NT = false, class T>
+// Fluid reference pressure (kp.pref, REF kernels only): with a per-row reference P(y)
+// the stored fluid values of a node in row y are h_i - r_i(P(y)), r_i the
+// equilibrium at pressure P and rest (r_0 = -(5/3) P, r_i = 3 W_i P; sum_i r_i = 0),
+// so a value that streams between rows changes its reference by
+// r_i(P(y_from)) - r_i(P(y_to)) = 3 W_i (P(y_from) - P(y_to)).
+template <class T>
+__device__ __forceinline__ T href_r(int i, T P) {   // r_i(P)
+    return i == 0 ? -(T(5) / T(3)) * P : T(3) * w9<T>(i) * P;
+}
+template <class T>
+__device__ __forceinline__ T pref_at(const KParams<T>& kp, int y) {
+    return kp.pref[y];
+}
+__device__ __forceinline__ int wrap_row(int y, int ny) { return y < 0 ? y + ny : (y >= ny ? y - ny : y); }
+
+template <class S, int M, bool PULL, bool NT = false, bool REF = true, class T>
 __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict__ pop, int x, int y,
                                        T h[9], T f[M][5]) {
     const int nx = kp.nx;
@@ -296,6 +311,17 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
 #pragma unroll
                 for (int i = 0; i < 5; ++i)
                     f[a][i] = ld<NT>(pop + nb.at(-CX5[i], -CY5[i]) + ((long long)(9 + 5 * a + OPP5[i]) << kBlkShift), kp, false);
+            if (REF && kp.pref) {   // values pulled from rows y -+ 1, to this row's reference
+                const int ny = kp.ny;
+                const T P0 = pref_at(kp, y);
+                const T dm = T(3) * (pref_at(kp, y == 0 ? ny - 1 : y - 1) - P0);
+                const T dp = T(3) * (pref_at(kp, y == ny - 1 ? 0 : y + 1) - P0);
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    if (CY9[i] > 0) h[i] += w9<T>(i) * dm;
+                    if (CY9[i] < 0) h[i] += w9<T>(i) * dp;
+                }
+            }
             return;
         }
         // nodes next to a wall: every link resolved with selects (no load in a
@@ -309,9 +335,11 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
             const bool ox = wf.out_x(-cx), oy = wf.out_y(-cy);  // source x - c_i beyond a wall
             long long src = nb.at(-cx, -cy);
             int pl = OPP9[i];
+            int dys = -cy;  // row of the source relative to y
             if (ox || oy) {
                 src = nb.at(0, 0);  // bounce-back: the node's own reflected value (also corners)
                 pl = i;
+                dys = 0;
                 if (ox != oy && kp.fbc[ox ? (cx > 0 ? 0 : 1) : (cy > 0 ? 2 : 3)] == LB_BC_FREESLIP) {
                     if (oy) {  // specular across a y-wall: from (x - c_x, y), direction mirrored
                         src = nb.at(-cx, 0);
@@ -319,10 +347,13 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
                     } else {  // across an x-wall: from (x, y - c_y)
                         src = nb.at(0, -cy);
                         pl = OPP9[MIRX9[i]];
+                        dys = -cy;
                     }
                 }
             }
             h[i] = ld<NT>(pop + src + ((long long)(pl) << kBlkShift), kp, true);
+            if (REF && kp.pref && dys != 0)
+                h[i] += w9<T>(i) * (T(3) * (pref_at(kp, wrap_row(y + dys, kp.ny)) - pref_at(kp, y)));
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -342,7 +373,7 @@ __device__ __forceinline__ void gather(const KParams<T>& kp, const S* __restrict
 // ---- scatter ---------------------------------------------------------------
 // PUSH = false: even step, post-collision value of direction i to own slot
 // opp(i).  PUSH = true: odd step, to slot i of x + c_i, or by the wall rules.
-template <class S, int M, bool PUSH, bool NT = false, class T>
+template <class S, int M, bool PUSH, bool NT = false, bool REF = true, class T>
 __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ pop, int x, int y,
                                         const T h[9], const T f[M][5], uint32_t salt) {
     const int nx = kp.nx;
@@ -359,8 +390,19 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             const NbrE<M> nb(kp, x, y);
+            T dm = T(0), dp = T(0);   // reference changes towards rows y - 1, y + 1
+            if (REF && kp.pref) {
+                const int ny = kp.ny;
+                const T P0 = pref_at(kp, y);
+                dm = T(3) * (pref_at(kp, y == 0 ? ny - 1 : y - 1) - P0);
+                dp = T(3) * (pref_at(kp, y == ny - 1 ? 0 : y + 1) - P0);
+            }
 #pragma unroll
-            for (int i = 0; i < 9; ++i) st_r<NT>(pop + nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), h[i], kp, true, sr_word(rw, i));
+            for (int i = 0; i < 9; ++i) {
+                // a value pushed to row y + c_y is stored relative to that row's reference
+                const T v = CY9[i] > 0 ? h[i] - w9<T>(i) * dp : (CY9[i] < 0 ? h[i] - w9<T>(i) * dm : h[i]);
+                st_r<NT>(pop + nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), v, kp, true, sr_word(rw, i));
+            }
 #pragma unroll
             for (int a = 0; a < M; ++a)
 #pragma unroll
@@ -377,9 +419,11 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
             const bool ox = wf.out_x(cx), oy = wf.out_y(cy);  // target x + c_i beyond a wall
             long long dst = nb.at(cx, cy);
             int pl = i;
+            int dyd = cy;  // row of the destination relative to y
             if (ox || oy) {
                 dst = nb.at(0, 0);  // bounce-back into the node's own opposite slot (also corners)
                 pl = OPP9[i];
+                dyd = 0;
                 if (ox != oy && kp.fbc[ox ? (cx > 0 ? 1 : 0) : (cy > 0 ? 3 : 2)] == LB_BC_FREESLIP) {
                     if (oy) {
                         dst = nb.at(cx, 0);
@@ -387,10 +431,14 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
                     } else {
                         dst = nb.at(0, cy);
                         pl = MIRX9[i];
+                        dyd = cy;
                     }
                 }
             }
-            st_r<NT>(pop + dst + ((long long)(pl) << kBlkShift), h[i], kp, true, sr_word(rw, i));
+            T v = h[i];
+            if (REF && kp.pref && dyd != 0)
+                v -= w9<T>(i) * (T(3) * (pref_at(kp, wrap_row(y + dyd, kp.ny)) - pref_at(kp, y)));
+            st_r<NT>(pop + dst + ((long long)(pl) << kBlkShift), v, kp, true, sr_word(rw, i));
         }
 #pragma unroll
         for (int a = 0; a < M; ++a)

@@ -42,6 +42,7 @@ struct KParams {
     int gam_on;           // gamma != 0 in D-bar (Eq. evolution12) for a species with a source
     T gam12[LB_MAX_M];    // gamma_a / 12: the auxiliary-source vector gains gamma_a grad S_a / 6,
                           // with grad S_a = (S(x + e) - S(x - e)) / 2
+    const T* pref;        // fluid reference pressure per row, or NULL (lb_fluid_reference)
 };
 
 struct Layout {
@@ -55,6 +56,7 @@ struct Layout {
                                  // planes also when gamma != 0: the step reads the previous source
                                  // field at the neighbours while writing the new one)
     size_t naux, aux_off;        // no-fluid model: prescribed u (2 planes) and previous phi - phi_ref (m planes)
+    size_t pref_off;             // fluid reference pressure per row (ny values of the arithmetic type)
 };
 
 constexpr int kRedBlocks = 1024;   // blocks of the first reduction pass (upper bound)
@@ -74,6 +76,14 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
 // L.pop2_off / L.sold2_off at t + 2
 hipError_t launch_step2(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                         const KParams<float>& kf, int64_t step, hipStream_t s);
+// fluid reference pressure: row means of the pressure (FP64, ny values), and the
+// move of the stored fluid values from the reference in kp.pref to pnew (ny values of
+// the arithmetic type)
+hipError_t launch_row_pressure(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                               const KParams<float>& kf, bool odd, double* out, hipStream_t s);
+hipError_t launch_reref(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                        const KParams<float>& kf, const void* pnew, hipStream_t s);
+hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t s);
 hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                             const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out);
 int reduce_blocks(size_t N);

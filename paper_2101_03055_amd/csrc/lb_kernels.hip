@@ -278,7 +278,9 @@ __global__ __launch_bounds__(256) void k_init(KParams<typename St<S>::T> kp, S* 
     for (int a = 0; a < M; ++a) phi[a] = T(stage[a * N + n]);
     u[0] = T(stage[M * N + n]);
     u[1] = T(stage[(M + 1) * N + n]);
-    const T p = has_p0 ? T(stage[(M + 2) * N + n]) : T(0);
+    // the fluid values are stored relative to the row's reference equilibrium (pressure P(y)),
+    // and h^eq is linear in p: the stored equilibrium is h^eq at p - P(y)
+    const T p = (has_p0 ? T(stage[(M + 2) * N + n]) : T(0)) - (kp.pref ? kp.pref[n / kp.nx] : T(0));
     const uint32_t salt = 0x51ed270bu;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(256) void k_moments(KParams<typename St<S>::T> kp, 
         u[n] = double(mc.u[0]);
         u[N + n] = double(mc.u[1]);
     }
-    if (pr) pr[n] = double(mc.p);
+    if (pr) pr[n] = double(mc.p) + (kp.pref ? double(kp.pref[y]) : 0.0);
 }
 
 // raw canonical populations, planes [plane_begin, plane_begin + count) of the
@@ -368,6 +370,7 @@ __global__ __launch_bounds__(256) void k_export(KParams<typename St<S>::T> kp, c
         double v;
         if (k < 9) {
             v = double(h[k]) + (k == 0 ? double(kp.h0_shift) : 0.0);
+            if (kp.pref) v += double(href_r<T>(k, kp.pref[y]));
         } else {
             const int a = (k - 9) / 5, i = (k - 9) % 5;
             v = double(f[a][i]) + double(w5<T>(i)) * double(kp.phi_ref[a]);
@@ -390,11 +393,51 @@ __global__ __launch_bounds__(256) void k_import(KParams<typename St<S>::T> kp, S
         if (k < plane_begin || k >= plane_begin + count) continue;
         const double v = in[(long long)(k - plane_begin) * N + n];
         if (k < 9) {
-            st(pop, pidx<M>(k, n), T(v - (k == 0 ? double(kp.h0_shift) : 0.0)), kp, true, salt);
+            const double r = kp.pref ? double(href_r<T>(k, kp.pref[n / kp.nx])) : 0.0;
+            st(pop, pidx<M>(k, n), T(v - (k == 0 ? double(kp.h0_shift) : 0.0) - r), kp, true, salt);
         } else {
             const int a = (k - 9) / 5, i = (k - 9) % 5;
             st(pop, pidx<M>(k, n), T(v - double(w5<T>(i)) * double(kp.phi_ref[a])), kp, false, salt);
         }
+    }
+}
+
+// mean pressure of every row (one workgroup per row, fixed-order sums): the
+// reference that lb_fluid_reference sets
+template <class S, int M, bool ODD>
+__global__ __launch_bounds__(256) void k_row_pressure(KParams<typename St<S>::T> kp, const S* __restrict__ pop,
+                                                      double* __restrict__ out) {
+    using T = typename St<S>::T;
+    const int y = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int x = threadIdx.x; x < kp.nx; x += blockDim.x) {
+        T h[9], f[M][5];
+        gather<S, M, ODD>(kp, pop, x, y, h, f);
+        Macro<T, M> mc;
+        macro<T, M>(kp, h, f, mc);
+        acc[0] += double(mc.p) + (kp.pref ? double(kp.pref[y]) : 0.0);
+    }
+    block_sum<1>(acc, out + y);
+    if (threadIdx.x == 0) out[y] /= double(kp.nx);   // the thread that wrote the sum
+}
+
+// the stored fluid values of every node moved from the row reference in kp.pref
+// (NULL: none) to pnew: + r_i(P_old) - r_i(P_new), each slot by its own node's
+// row (in both AA layouts a slot's value is relative to the row of its node)
+template <class S, int M>
+__global__ __launch_bounds__(256) void k_reref(KParams<typename St<S>::T> kp, S* __restrict__ pop,
+                                               const typename St<S>::T* __restrict__ pnew) {
+    using T = typename St<S>::T;
+    const long long N = (long long)kp.nx * kp.ny;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int y = (int)(n / kp.nx);
+    const T d = (kp.pref ? kp.pref[y] : T(0)) - pnew[y];
+    const uint32_t salt = 0x7a3c9e21u;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        S* q = pop + pidx<M>(i, n);
+        st(pop, pidx<M>(i, n), ld(q, kp, true) + href_r<T>(i, d), kp, true, salt);
     }
 }
 
@@ -694,6 +737,34 @@ hipError_t launch_import(const lb_params& p, const Layout& L, void* ws, const KP
     return dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
         hipLaunchKernelGGL((k_import<S, M>), dim3(blocks_for(L.N)), dim3(256), 0, s, kpar<S>(kd, kf),
                            (S*)at(ws, L.pop_off), plane_begin, plane_count, in);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_row_pressure(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                               const KParams<float>& kf, bool odd, double* out, hipStream_t s) {
+    return dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
+        const S* pop = (const S*)at(ws, L.pop_off);
+        if (odd)
+            hipLaunchKernelGGL((k_row_pressure<S, M, true>), dim3((unsigned)p.ny), dim3(256), 0, s, kpar<S>(kd, kf), pop, out);
+        else
+            hipLaunchKernelGGL((k_row_pressure<S, M, false>), dim3((unsigned)p.ny), dim3(256), 0, s, kpar<S>(kd, kf), pop, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reref(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                        const KParams<float>& kf, const void* pnew, hipStream_t s) {
+    return dispatch(p, [&]<class S, int M, int MODEL>() -> hipError_t {
+        using T = typename St<S>::T;
+        hipLaunchKernelGGL((k_reref<S, M>), dim3(blocks_for(L.N)), dim3(256), 0, s, kpar<S>(kd, kf),
+                           (S*)at(ws, L.pop_off), (const T*)pnew);
         return hipGetLastError();
     });
 }

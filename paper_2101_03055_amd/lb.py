@@ -89,6 +89,7 @@ def lib():
             "lb_load": [vp, vp, sz],
             "lb_set_tile": [vp, C.c_int32, C.c_int32],
             "lb_copy_state": [vp, vp],
+            "lb_fluid_reference": [vp, C.c_int32],
             "lb_wall_flux": [vp, C.c_int32, vp],
             "lb_solve_steady": [vp, C.c_double, i64, i64, C.POINTER(i64), vp],
             "lb_free": [vp],
@@ -296,6 +297,10 @@ def lb_copy_state(dst, src):
     _check(lib().lb_copy_state(dst, src))
 
 
+def lb_fluid_reference(h, mode: int = 1):
+    _check(lib().lb_fluid_reference(h, int(mode)))
+
+
 def lb_set_tile(h, tile_x: int, tile_y: int):
     _check(lib().lb_set_tile(h, int(tile_x), int(tile_y)))
 
@@ -333,6 +338,11 @@ class Solver:
 
     def mass(self):
         return lb_mass(self.handle, self.m)
+
+    def fluid_reference(self, mode: int = 1):
+        """Store the fluid relative to the current row-mean pressure (mode 1) or
+        to no reference (mode 0); see lb_fluid_reference."""
+        lb_fluid_reference(self.handle, mode)
 
     def solve_steady(self, tol=1e-8, check_every=1000, max_steps=5_000_000):
         return lb_solve_steady(self.handle, self.m, tol, check_every, max_steps)
