@@ -390,18 +390,20 @@ __device__ __forceinline__ void scatter(const KParams<T>& kp, S* __restrict__ po
     } else {
         if (__all(no_wall_link(kp, x, y))) {  // wave-uniform choice: no lane pays for both paths
             const NbrE<M> nb(kp, x, y);
-            T dm = T(0), dp = T(0);   // reference changes towards rows y - 1, y + 1
-            if (REF && kp.pref) {
+            if (REF && kp.pref) {   // a value pushed to row y + c_y is stored relative to that row's reference
                 const int ny = kp.ny;
                 const T P0 = pref_at(kp, y);
-                dm = T(3) * (pref_at(kp, y == 0 ? ny - 1 : y - 1) - P0);
-                dp = T(3) * (pref_at(kp, y == ny - 1 ? 0 : y + 1) - P0);
-            }
+                const T dm = T(3) * (pref_at(kp, y == 0 ? ny - 1 : y - 1) - P0);
+                const T dp = T(3) * (pref_at(kp, y == ny - 1 ? 0 : y + 1) - P0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                // a value pushed to row y + c_y is stored relative to that row's reference
-                const T v = CY9[i] > 0 ? h[i] - w9<T>(i) * dp : (CY9[i] < 0 ? h[i] - w9<T>(i) * dm : h[i]);
-                st_r<NT>(pop + nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), v, kp, true, sr_word(rw, i));
+                for (int i = 0; i < 9; ++i) {
+                    const T v = CY9[i] > 0 ? h[i] - w9<T>(i) * dp : (CY9[i] < 0 ? h[i] - w9<T>(i) * dm : h[i]);
+                    st_r<NT>(pop + nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), v, kp, true, sr_word(rw, i));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    st_r<NT>(pop + nb.at(CX9[i], CY9[i]) + ((long long)(i) << kBlkShift), h[i], kp, true, sr_word(rw, i));
             }
 #pragma unroll
             for (int a = 0; a < M; ++a)
