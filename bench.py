@@ -282,18 +282,27 @@ def time_batch(b, steps, window=1000):
     return e0.elapsed_time(e1) / 1e3, n_res
 
 
+def tiles_by_width(b, cases):
+    """The autotuned tile shape of each cavity width ({nx: [tile_x, tile_y]})."""
+    out = {}
+    for i, c in enumerate(cases):
+        out[str(c[0]["nx"])] = list(b.cavity_tile(i))
+    return dict(sorted(out.items(), key=lambda kv: int(kv[0])))
+
+
 def batch_headline(W, lb, torch, steps, warmup):
     """The batched sweep: autotune, warm up, time `steps` steps, then the
     step kernel's mean launch duration and a 2000-step production run."""
     cases, nodes = sweep_cases(W)
     b = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
     tx, ty, us = b.autotune(10)
+    by_width = tiles_by_width(b, cases)
     b.step(warmup + (warmup & 1))
     el, n_res = time_batch(b, steps)
     kt = kernel_time(b.step, b.stream, 256)
     el_prod, n_prod = time_batch(b, 2000)
     st = [b.time(i)[1] for i in range(b.count)]
-    return b, {"cases": cases, "nodes": nodes, "tile": [tx, ty], "autotune_us": round(us, 2),
+    return b, {"cases": cases, "nodes": nodes, "tile": [tx, ty], "tiles_by_width": by_width, "autotune_us": round(us, 2),
                "elapsed": el, "residual_evals": n_res, "kernel_s": kt,
                "production_run": {"steps": 2000, "residual_windows": n_prod, "seconds": round(el_prod, 4),
                                   "MLUPS": round(nodes * 2000 / el_prod / 1e6, 1),
@@ -634,9 +643,11 @@ def main():
     if args.mode == "batch":
         cases, nodes = sweep_cases(W)
         b = lb.Batch(cases, storage="f32", phi_ref=[0.5, 0.5])
-        tx, ty, _ = b.autotune(10)  # 7 tile shapes x (2 + 10) steps
+        tx, ty, _ = b.autotune(10)  # 7 shapes for all cavities, then per width, each 2 + 10 steps
+        tuned = b.time(0)[0]
         kt = kernel_time(b.step, b.stream, 256)
-        print(json.dumps({"launches": 7 * 12 + 256, "timed_launches": 256, "tile": [tx, ty],
+        print(json.dumps({"launches": tuned + 256, "timed_launches": 256, "tile": [tx, ty],
+                          "tiles_by_width": tiles_by_width(b, cases),
                           "mean_launch_us": round(kt * 1e6, 2),
                           "bytes_per_launch": bytes_per_lu(2, "f32", 0) * nodes}), flush=True)
         return
@@ -667,7 +678,8 @@ def main():
         "config": {"workload": "ddc_sweep_256_cavities", "cavities": 256, "sides": "64..256 step 32",
                    "nodes": nodes, "state_MB": round(nodes * 19 * 4 / 1e6, 1), "m": 2,
                    "storage": "f32 deviations from phi_ref = (0.5, 0.5) and rho0", "collision": "bgk",
-                   "tile": r["tile"], "residual_every": 1000, "residual_evals_timed": r["residual_evals"]},
+                   "tile": r["tile"], "tiles_by_width": r["tiles_by_width"], "residual_every": 1000,
+                   "residual_evals_timed": r["residual_evals"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(tr["traffic_bytes_per_launch"]) if tr else None,

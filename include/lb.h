@@ -307,14 +307,25 @@ lb_status lbb_moments(lbb_handle* b, int32_t i, double* phi, double* u, double* 
 /* Steps taken by cavity i and its status. */
 lb_status lbb_time(lbb_handle* b, int32_t i, int64_t* steps, int32_t* status);
 
-/* Tile shape of the batched step: one of 32x4, 32x8, 64x2, 64x4, 128x1, 128x2, 256x1. */
+/* Tile shape of the batched step for every cavity: one of 32x4, 32x8, 64x2,
+ * 64x4, 128x1, 128x2, 256x1. */
 lb_status lbb_set_tile(lbb_handle* b, int32_t tile_x, int32_t tile_y);
 
 /* Autotuner: times trial_steps steps (rounded up to even, plus 2 warm-up steps)
- * of every supported tile shape on the live batch and keeps the fastest.  The
- * timed steps are real steps of every running cavity (counted in their step
- * totals; results do not depend on the tile shape).  Outputs may be NULL. */
+ * of every supported tile shape on the live batch and keeps the fastest for
+ * all cavities (tile_x, tile_y); then, one cavity width at a time, tries the
+ * other shapes of the same workgroup size for the cavities of that width and
+ * keeps one when it saves more than 1 % of the step time (lbb_cavity_tile reads
+ * the result).  The timed steps are real steps of every running cavity (counted
+ * in their step totals; results do not depend on the tile shapes).  us_per_step
+ * is the best step time seen.  Outputs may be NULL. */
 lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y, double* us_per_step);
+
+/* Tile shape of cavity i alone (one of the shapes above with the batch's
+ * workgroup size, tile_x * tile_y of the last lbb_set_tile; LB_EINVAL otherwise),
+ * and the shape in use for cavity i. */
+lb_status lbb_set_cavity_tile(lbb_handle* b, int32_t i, int32_t tile_x, int32_t tile_y);
+lb_status lbb_cavity_tile(lbb_handle* b, int32_t i, int32_t* tile_x, int32_t* tile_y);
 
 /* Releases the batch handle (never the workspace).  NULL is accepted. */
 lb_status lbb_free(lbb_handle* b);

@@ -993,6 +993,7 @@ struct lbb_handle {
     int64_t t;
     Launch lc;
     std::vector<int2> tiles;
+    std::vector<int2> ctile;         // tile shape of each cavity (all of lc's workgroup size)
     std::vector<int4> ranges;
     std::vector<double> out;
     int64_t tiles_gen = 0;           // bumped whenever the device tile list changes
@@ -1013,14 +1014,14 @@ bool same_template(const lb_params& a, const lb_params& b) {
 }
 
 size_t batch_max_tiles(const lb_params* params, int count) {
-    size_t best = 0;
-    for (const auto& tc : kTileCand) {
-        size_t t = 0;
-        for (int c = 0; c < count; ++c)
-            t += (size_t)((params[c].nx + tc[0] - 1) / tc[0]) * (size_t)((params[c].ny + tc[1] - 1) / tc[1]);
-        best = std::max(best, t);
+    size_t total = 0;   // each cavity may take any of the shapes
+    for (int c = 0; c < count; ++c) {
+        size_t most = 0;
+        for (const auto& tc : kTileCand)
+            most = std::max(most, (size_t)((params[c].nx + tc[0] - 1) / tc[0]) * (size_t)((params[c].ny + tc[1] - 1) / tc[1]));
+        total += most;
     }
-    return best;
+    return total;
 }
 
 // workspace plan: shared arrays first, then each cavity's own region
@@ -1066,10 +1067,13 @@ void batch_build_tiles(lbb_handle* b) {
     b->ranges.clear();
     for (int c = 0; c < b->count; ++c) {
         if (b->status[c] != kStatusRunning) continue;
-        const int tx = (b->p[c].nx + b->lc.tile_x - 1) / b->lc.tile_x;
-        const int ty = (b->p[c].ny + b->lc.tile_y - 1) / b->lc.tile_y;
+        const int2 sh = b->ctile[c];
+        const int tx = (b->p[c].nx + sh.x - 1) / sh.x;
+        const int ty = (b->p[c].ny + sh.y - 1) / sh.y;
         b->cav[c].tiles_x = tx;
         b->cav[c].tiles_y = ty;
+        b->cav[c].tile_x = sh.x;
+        b->cav[c].tile_y = sh.y;
         b->ranges.push_back(int4{c, (int)b->tiles.size(), tx * ty, 0});
         for (int k = 0; k < tx * ty; ++k) b->tiles.push_back(int2{c, k});
     }
@@ -1162,6 +1166,7 @@ lb_status lbb_init(const lb_params* params, int32_t count, void* dev_workspace, 
     size_t state = 0;
     for (int c = 0; c < count; ++c) state += b->L[c].npop * b->L[c].plane * b->L[c].elem;
     b->lc = Launch{64, 4, hint_bits(state)};
+    b->ctile.assign(count, int2{64, 4});
     char* w = static_cast<char*>(b->ws);
     for (int c = 0; c < count; ++c) {
         fill_kparams(b->p[c], b->L[c], b->kd[c]);
@@ -1317,8 +1322,29 @@ lb_status lbb_set_tile(lbb_handle* b, int32_t tile_x, int32_t tile_y) {
     for (const auto& tc : kTileCand) ok |= (tc[0] == tile_x && tc[1] == tile_y);
     if (!ok) return fail(LB_EINVAL, "tile %d x %d is not one of the supported batch tiles", tile_x, tile_y);
     b->lc = Launch{tile_x, tile_y, b->lc.nt};
+    b->ctile.assign(b->count, int2{tile_x, tile_y});
     batch_build_tiles(b);
     return batch_upload(b);
+}
+
+lb_status lbb_set_cavity_tile(lbb_handle* b, int32_t i, int32_t tile_x, int32_t tile_y) {
+    if (!b || i < 0 || i >= b->count) return fail(LB_EINVAL, "bad handle or cavity index");
+    bool ok = false;
+    for (const auto& tc : kTileCand) ok |= (tc[0] == tile_x && tc[1] == tile_y);
+    if (!ok) return fail(LB_EINVAL, "tile %d x %d is not one of the supported batch tiles", tile_x, tile_y);
+    if (tile_x * tile_y != b->lc.tile_x * b->lc.tile_y)
+        return fail(LB_EINVAL, "tile %d x %d: every cavity's tile has the batch's workgroup size, %d threads", tile_x,
+                    tile_y, b->lc.tile_x * b->lc.tile_y);
+    b->ctile[i] = int2{tile_x, tile_y};
+    batch_build_tiles(b);
+    return batch_upload(b);
+}
+
+lb_status lbb_cavity_tile(lbb_handle* b, int32_t i, int32_t* tile_x, int32_t* tile_y) {
+    if (!b || i < 0 || i >= b->count || !tile_x || !tile_y) return fail(LB_EINVAL, "bad handle, index or pointer");
+    *tile_x = b->ctile[i].x;
+    *tile_y = b->ctile[i].y;
+    return LB_OK;
 }
 
 lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int32_t* tile_y, double* us_per_step) {
@@ -1328,29 +1354,70 @@ lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int3
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    float best = 1e30f;
-    Launch best_lc = b->lc;
-    for (const auto& tc : kTileCand) {
-        lb_status st = lbb_set_tile(b, tc[0], tc[1]);
-        if (st != LB_OK) return st;
-        st = lbb_step(b, 2);  // warm-up: first launch of this shape
+    // wall time of trial_steps steps of the batch as it is set up (after two untimed ones)
+    auto trial = [&](float* ms) -> lb_status {
+        lb_status st = lbb_step(b, 2);
         if (st != LB_OK) return st;
         HIPCHK(hipEventRecord(e0, b->stream));
         st = lbb_step(b, trial_steps);
         if (st != LB_OK) return st;
         HIPCHK(hipEventRecord(e1, b->stream));
         HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(ms, e0, e1));
+        return LB_OK;
+    };
+    // 1. one shape for every cavity
+    float best = 1e30f;
+    Launch best_lc = b->lc;
+    for (const auto& tc : kTileCand) {
+        lb_status st = lbb_set_tile(b, tc[0], tc[1]);
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (st == LB_OK) st = trial(&ms);
+        if (st != LB_OK) return st;
         if (ms < best) {
             best = ms;
             best_lc = b->lc;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     lb_status st = lbb_set_tile(b, best_lc.tile_x, best_lc.tile_y);
     if (st != LB_OK) return st;
+    // 2. per cavity width, the other shapes of the same workgroup size, one width at a time
+    //    against a fresh timing of the current setting; a change is kept when it saves more
+    //    than 1 % of the batch's step time (below that the timings do not tell them apart)
+    std::vector<int> widths;
+    for (int c = 0; c < b->count; ++c)
+        if (b->status[c] == kStatusRunning && std::find(widths.begin(), widths.end(), b->p[c].nx) == widths.end())
+            widths.push_back(b->p[c].nx);
+    std::sort(widths.begin(), widths.end());
+    const int threads = best_lc.tile_x * best_lc.tile_y;
+    for (int w : widths) {
+        if (widths.size() < 2) break;
+        float cur = 0.f;
+        if ((st = trial(&cur)) != LB_OK) return st;
+        int2 keep = int2{best_lc.tile_x, best_lc.tile_y};
+        for (int c = 0; c < b->count; ++c)
+            if (b->p[c].nx == w) keep = b->ctile[c];
+        for (const auto& tc : kTileCand) {
+            if (tc[0] * tc[1] != threads || (tc[0] == keep.x && tc[1] == keep.y)) continue;
+            for (int c = 0; c < b->count; ++c)
+                if (b->p[c].nx == w) b->ctile[c] = int2{tc[0], tc[1]};
+            batch_build_tiles(b);
+            if ((st = batch_upload(b)) != LB_OK) return st;
+            float ms = 0.f;
+            if ((st = trial(&ms)) != LB_OK) return st;
+            if (ms < 0.99f * cur) {
+                cur = ms;
+                keep = int2{tc[0], tc[1]};
+            }
+        }
+        for (int c = 0; c < b->count; ++c)
+            if (b->p[c].nx == w) b->ctile[c] = keep;
+        batch_build_tiles(b);
+        if ((st = batch_upload(b)) != LB_OK) return st;
+        best = std::min(best, cur);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (tile_x) *tile_x = best_lc.tile_x;
     if (tile_y) *tile_y = best_lc.tile_y;
     if (us_per_step) *us_per_step = 1e3 * best / trial_steps;

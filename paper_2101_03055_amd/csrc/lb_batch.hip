@@ -18,17 +18,17 @@ namespace lbk {
 template <class S, int M, int MODEL, int COLL, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>* __restrict__ kps,
                                                const CavRec* __restrict__ cav, const int2* __restrict__ tiles,
-                                               int ntiles, char* __restrict__ ws, int tile_x, int tile_y,
-                                               uint32_t salt) {
+                                               int ntiles, char* __restrict__ ws, uint32_t salt) {
     using T = typename St<S>::T;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     if (b >= ntiles) return;
     const int2 t = tiles[b];
     const KParams<T>& kp = kps[t.x];
     const CavRec cr = cav[t.x];
+    // the cavity's own tile shape (every shape of a launch has blockDim.x threads)
     const int bx = t.y % cr.tiles_x, by = t.y / cr.tiles_x;
-    const int x = bx * tile_x + (int)(threadIdx.x % tile_x);
-    const int y = by * tile_y + (int)(threadIdx.x / tile_x);
+    const int x = bx * cr.tile_x + (int)(threadIdx.x % cr.tile_x);
+    const int y = by * cr.tile_y + (int)(threadIdx.x / cr.tile_x);
     if (x >= kp.nx || y >= kp.ny) return;
     const long long N = (long long)kp.nx * kp.ny;
     const long long n = (long long)y * kp.nx + x;
@@ -69,8 +69,7 @@ static const void* bstep_kernel(bool mrt, bool odd, bool nt) {
 template <class S, int M, bool ODD>
 __global__ __launch_bounds__(256) void k_breduce(const KParams<typename St<S>::T>* __restrict__ kps,
                                                  const CavRec* __restrict__ cav, const int2* __restrict__ tiles,
-                                                 int ntiles, char* __restrict__ ws, int tile_x, int tile_y,
-                                                 double* __restrict__ part, int mode) {
+                                                 int ntiles, char* __restrict__ ws, double* __restrict__ part, int mode) {
     using T = typename St<S>::T;
     constexpr int Q = M + 2;
     double acc[2 * Q + 1];
@@ -80,8 +79,8 @@ __global__ __launch_bounds__(256) void k_breduce(const KParams<typename St<S>::T
     const KParams<T>& kp = kps[t.x];
     const CavRec cr = cav[t.x];
     const int bx = t.y % cr.tiles_x, by = t.y / cr.tiles_x;
-    const int x = bx * tile_x + (int)(threadIdx.x % tile_x);
-    const int y = by * tile_y + (int)(threadIdx.x / tile_x);
+    const int x = bx * cr.tile_x + (int)(threadIdx.x % cr.tile_x);
+    const int y = by * cr.tile_y + (int)(threadIdx.x / cr.tile_x);
     if (x < kp.nx && y < kp.ny) {
         const long long N = (long long)kp.nx * kp.ny;
         const long long n = (long long)y * kp.nx + x;
@@ -154,9 +153,9 @@ hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, cons
         char* w = static_cast<char*>(ws);
         const CavRec* cv = cav;
         const int2* tl = tiles;
-        int nt = ntiles, tx = lc.tile_x, ty = lc.tile_y;
+        int nt = ntiles;
         uint32_t sl = salt;
-        void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &sl};
+        void* args[] = {&kp, &cv, &tl, &nt, &w, &sl};
         const void* fn = bstep_kernel<S, M, MODEL>(p0.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
@@ -177,9 +176,9 @@ hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams,
         char* w = static_cast<char*>(ws);
         const CavRec* cv = cav;
         const int2* tl = tiles;
-        int nt = ntiles, tx = lc.tile_x, ty = lc.tile_y;
+        int nt = ntiles;
         uint32_t salt = 0;
-        void* args[] = {&kp, &cv, &tl, &nt, &w, &tx, &ty, &salt};
+        void* args[] = {&kp, &cv, &tl, &nt, &w, &salt};
         const bool mrt = p0.collision == LB_COLL_MRT;
         void* fe = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0));
         void* fo = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0));
@@ -217,11 +216,9 @@ hipError_t launch_breduce(const lb_params& p0, void* ws, const void* kparams, co
         const KParams<T>* kp = static_cast<const KParams<T>*>(kparams);
         char* w = static_cast<char*>(ws);
         if (odd)
-            hipLaunchKernelGGL((k_breduce<S, M, true>), grid, block, 0, s, kp, cav, tiles, ntiles, w, lc.tile_x,
-                               lc.tile_y, part, mode);
+            hipLaunchKernelGGL((k_breduce<S, M, true>), grid, block, 0, s, kp, cav, tiles, ntiles, w, part, mode);
         else
-            hipLaunchKernelGGL((k_breduce<S, M, false>), grid, block, 0, s, kp, cav, tiles, ntiles, w, lc.tile_x,
-                               lc.tile_y, part, mode);
+            hipLaunchKernelGGL((k_breduce<S, M, false>), grid, block, 0, s, kp, cav, tiles, ntiles, w, part, mode);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_bfinal<M + 2>), dim3((unsigned)nranges), dim3(256), 0, s, ranges, part, out, mode);

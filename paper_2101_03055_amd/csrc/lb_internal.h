@@ -131,6 +131,7 @@ hipError_t launch_reduce(const lb_params& p, const Layout& L, void* ws, const KP
 struct CavRec {
     long long pop_off, sold_off, snap_off;
     int tiles_x, tiles_y;
+    int tile_x, tile_y;   // the cavity's tile shape (tile_x * tile_y = the launch's workgroup size)
 };
 
 // one step of every listed tile: tiles[k] = (cavity, tile index in the cavity)

@@ -109,6 +109,8 @@ def lib():
             "lbb_copy_cavity": [vp, C.c_int32, vp, C.c_int32],
             "lbb_set_tile": [vp, C.c_int32, C.c_int32],
             "lbb_autotune": [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)],
+            "lbb_cavity_tile": [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+            "lbb_set_cavity_tile": [vp, C.c_int32, C.c_int32, C.c_int32],
             "lbb_free": [vp],
         }
         for name, args in bsig.items():
@@ -452,6 +454,16 @@ def lbb_autotune(b, trial_steps: int = 20):
     return tx.value, ty.value, us.value
 
 
+def lbb_set_cavity_tile(b, i: int, tile_x: int, tile_y: int):
+    _check(lib().lbb_set_cavity_tile(b, int(i), int(tile_x), int(tile_y)))
+
+
+def lbb_cavity_tile(b, i: int):
+    tx, ty = C.c_int32(), C.c_int32()
+    _check(lib().lbb_cavity_tile(b, int(i), C.byref(tx), C.byref(ty)))
+    return tx.value, ty.value
+
+
 def lbb_free(b):
     lib().lbb_free(b)
 
@@ -490,6 +502,10 @@ class Batch:
 
     def autotune(self, trial_steps: int = 20):
         return lbb_autotune(self.handle, trial_steps)
+
+    def cavity_tile(self, i: int):
+        """Tile shape (tile_x, tile_y) the batched step uses for cavity i."""
+        return lbb_cavity_tile(self.handle, i)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -106,12 +106,35 @@ def test_autotune_picks_a_supported_tile_and_keeps_results():
     tx, ty, us = b.autotune(10)
     assert (tx, ty) in [(32, 4), (32, 8), (64, 2), (64, 4), (128, 1), (128, 2), (256, 1)]
     assert us > 0
+    shapes = [b.cavity_tile(i) for i in range(len(cases))]
+    assert all(sx * sy == tx * ty for sx, sy in shapes), shapes
     taken = b.time(0)[0]
-    assert taken == 7 * (10 + 2)
+    # 7 shapes for all cavities, then per width a fresh timing and the other shapes of the
+    # same workgroup size, each 10 + 2 steps
+    assert taken >= 7 * (10 + 2) and taken % 12 == 0
     b.step(6)
     for i, c in enumerate(cases):
         got = b.moments(i)
         want = single(c, taken + 6)
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w), i
+
+
+def test_per_cavity_tiles_keep_results():
+    """Each cavity with its own tile shape (all of one workgroup size): every cavity
+    still matches its single-domain run bit for bit; a shape of another size is refused."""
+    cases = mixed_cases()
+    b = lb.Batch(cases)
+    lb.lbb_set_tile(b.handle, 64, 4)
+    for i, sh in enumerate([(256, 1), (32, 8), (128, 2), (64, 4), (256, 1)]):
+        lb.lbb_set_cavity_tile(b.handle, i, *sh)
+        assert b.cavity_tile(i) == sh
+    with pytest.raises(lb.LBError):
+        lb.lbb_set_cavity_tile(b.handle, 0, 64, 2)
+    b.step(41)
+    for i, c in enumerate(cases):
+        got = b.moments(i)
+        want = single(c, 41)
         for g, w in zip(got, want):
             assert np.array_equal(g, w), i
 
