@@ -1351,7 +1351,15 @@ lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int3
     if (!b) return fail(LB_EINVAL, "handle is NULL");
     if (trial_steps < 2) trial_steps = 2;
     trial_steps += trial_steps & 1;
-    hipEvent_t e0, e1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct EventPair {   // released on every return path
+        hipEvent_t* a;
+        hipEvent_t* b;
+        ~EventPair() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } events{&e0, &e1};
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     // wall time of trial_steps steps of the batch as it is set up (after two untimed ones)
@@ -1416,8 +1424,6 @@ lb_status lbb_autotune(lbb_handle* b, int32_t trial_steps, int32_t* tile_x, int3
         if ((st = batch_upload(b)) != LB_OK) return st;
         best = std::min(best, cur);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (tile_x) *tile_x = best_lc.tile_x;
     if (tile_y) *tile_y = best_lc.tile_y;
     if (us_per_step) *us_per_step = 1e3 * best / trial_steps;
