@@ -78,9 +78,13 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ para
     for (int c = 0; c < kCinPad[0]; ++c) o[c] = bf16(c < kFeat ? f[c] : 0.0f);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with gfx950's 1-ulp reciprocal instead of a correctly
+// rounded division: the results are stored in bfloat16 (8 mantissa bits), and the
+// division's scale/fixup sequence was ~10 % of the convolutions' time (forward
+// 42 -> 39 us, data gradient 39 -> 35 us at 64 channels, 16 x 128^2)
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(256) void k_conv(const bf16* __restrict__ X, const 
                 if constexpr (MODE == 0) {
                     const float z = v + bias[n];
                     if (Zout) Zout[o] = z;
-                    Yout[o] = bf16(act ? silu(z) : z);
+                    if (Yout) Yout[o] = bf16(act ? silu(z) : z);
                 } else {
                     Yout[o] = bf16(v * silu_grad(Zprev[o]));
                 }
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
                 if constexpr (MODE == 0) {
                     const float z = v + bias[n];
                     if (Zout) Zout[o] = z;
-                    Yout[o] = bf16(act ? silu(z) : z);
+                    if (Yout) Yout[o] = bf16(act ? silu(z) : z);
                 } else {
                     Yout[o] = bf16(v * silu_grad(Zprev[o]));
                 }
@@ -407,9 +411,12 @@ __global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X
                 }
         }
         // input row R + 1 has landed (this wave's loads are older than the previous
-        // row's stores -- 12 with z, 4 without -- and, for the data gradient, the 8
-        // pre-activation loads just issued), then every wave's
-        if (MODE == 1 || Zout) wait_vm<12>(); else wait_vm<4>();
+        // row's stores -- 8 of z, 4 of y, whichever are stored -- and, for the data
+        // gradient, the 8 pre-activation loads just issued), then every wave's
+        if (MODE == 1 || (Zout && Yout)) wait_vm<12>();
+        else if (Zout) wait_vm<8>();
+        else if (Yout) wait_vm<4>();
+        else wait_vm<0>();
         __syncthreads();
         load_row(R + 2);   // into the slot of row R - 2, which no wave reads any more
 
@@ -506,7 +513,7 @@ __global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X
 #pragma unroll
                     for (int e = 0; e < 8; ++e) yv[e] = bf16(v[e] * silu_grad(zp[g2][i][e]));
                 }
-                *reinterpret_cast<bf16x8*>(Yout + o) = yv;
+                if (Yout) *reinterpret_cast<bf16x8*>(Yout + o) = yv;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -1251,9 +1258,11 @@ lb_status forward(sg_handle* h, const float* d_params, int nb, bool keep_z = tru
     const bf16* x = ptr<bf16>(h, h->pl.x0_off);
     for (int l = 0; l < kLayers; ++l) {
         float* z = keep_z || l + 1 == kLayers ? ptr<float>(h, h->pl.z_off[l]) : nullptr;
-        lb_status st = launch_conv(h, l, 0, P, x, nullptr, z, ptr<bf16>(h, h->pl.y_off[l]));
+        // the output layer's BF16 copy feeds nothing (the loss and the prediction read z)
+        bf16* y = l + 1 < kLayers ? ptr<bf16>(h, h->pl.y_off[l]) : nullptr;
+        lb_status st = launch_conv(h, l, 0, P, x, nullptr, z, y);
         if (st != LB_OK) return st;
-        x = ptr<bf16>(h, h->pl.y_off[l]);
+        x = y;
     }
     h->nb_last = nb;
     h->z_valid = keep_z;
