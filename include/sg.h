@@ -4,7 +4,7 @@
  * learned component; the network maps the parameters of a double-diffusive
  * cavity (Sec. 3.2: Ra, Le, Nc, Sr = S_TC, Df = D_CT) plus the grid
  * coordinates to the steady fields (u, v, T, C), and the LB iteration remains
- * the judge of its error.
+ * what decides its error.
  *
  * Network (fixed): six 3x3 convolutions, zero padding, channels-last
  *   15 -> 64 -> 128 -> 64 -> 64 -> 64 -> 4, SiLU after each hidden layer.

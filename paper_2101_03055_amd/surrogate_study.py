@@ -137,7 +137,7 @@ def solve_path(cases, init_fields, tol32=1e-5, tol=1e-8, max_steps=1_500_000, la
     """Batched FP32 phase then batched FP64 finish; init_fields None = from rest.
     A warm-started cavity that diverges in the FP32 phase falls back to a cold
     start: its FP64 phase begins from rest instead of from the copied state
-    (the LB iteration stays the judge of the prediction)."""
+    (the LB iteration decides the prediction's error)."""
     cold_cases = cases
     if init_fields is not None:
         cases = [(wl, np.stack([f[2], f[3]]), np.stack([f[0], f[1]]) * U_LAT, None)
