@@ -30,7 +30,9 @@
 namespace lbk {
 
 // ---- kernels ------------------------------------------------------------------
-template <class S, int M, int MODEL, int COLL, bool ODD, bool NT>
+// REF: the odd (streaming) parity re-references fluid values that cross rows
+// to a per-row pressure (kp.pref non-null); the even parity never crosses rows
+template <class S, int M, int MODEL, int COLL, bool ODD, bool NT, bool REF>
 __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* __restrict__ pop,
                                               const typename St<S>::T* sold, typename St<S>::T* sold_out,
                                               int tile_x, int tile_y, int tiles_x, uint32_t salt) {
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
 
     const long long N = (long long)kp.nx * kp.ny;
     T h[9], f[M][5], Sold[M], Snew[M];
-    gather<S, M, ODD, NT>(kp, pop, x, y, h, f);
+    gather<S, M, ODD, NT, REF>(kp, pop, x, y, h, f);
     int k = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -77,21 +79,26 @@ __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* 
 #pragma unroll
     for (int a = 0; a < M; ++a)
         if (kp.src_mask >> a & 1) store_raw<NT>(Snew[a], &sold_out[(long long)(k++) * N + n]);
-    scatter<S, M, ODD, NT>(kp, pop, x, y, h, f, salt);
+    scatter<S, M, ODD, NT, REF>(kp, pop, x, y, h, f, salt);
 }
 
-// the step kernel for a collision kind, parity and cache hint
+// the step kernel for a collision kind, parity, cache hint and fluid reference
 template <class S, int M, int MODEL>
-static const void* step_kernel(bool mrt, bool odd, bool nt) {
-    const void* const fns[8] = {
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false, false>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false, true>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, false>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, true>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false, false>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false, true>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, false>),
-        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, true>)};
+static const void* step_kernel(bool mrt, bool odd, bool nt, bool ref) {
+    const void* const fns[12] = {
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false, false, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, false, true, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, false, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, true, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false, false, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, false, true, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, false, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, true, false>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, false, true>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_BGK, true, true, true>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, false, true>),
+        reinterpret_cast<const void*>(&k_step<S, M, MODEL, LB_COLL_MRT, true, true, true>)};
+    if (odd && ref) return fns[8 + (mrt ? 2 : 0) + (nt ? 1 : 0)];
     return fns[(mrt ? 4 : 0) + (odd ? 2 : 0) + (nt ? 1 : 0)];
 }
 
@@ -613,7 +620,8 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
         int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
         uint32_t sl = salt;
         void* args[] = {&kp, &pop, &sold, &sold_out, &tx, &ty, &tsx, &sl};
-        const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0);
+        const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0,
+                                                  kp.pref != nullptr);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
 }
@@ -643,8 +651,9 @@ hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const
         void* args[2][8] = {{&kp, &pop, &sbuf[0], &sbuf[1], &tx, &ty, &tsx, &salt},
                             {&kp, &pop, &sbuf[1], &sbuf[0], &tx, &ty, &tsx, &salt}};
         const bool mrt = p.collision == LB_COLL_MRT;
-        void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0));
-        void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0));
+        const bool ref = kp.pref != nullptr;
+        void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0, ref));
+        void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0, ref));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
             hipKernelNodeParams np{};
