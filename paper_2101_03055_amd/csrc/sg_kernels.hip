@@ -26,6 +26,7 @@
 #include <numeric>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sg.h"
@@ -48,6 +49,7 @@ constexpr int kMaxC = 128;
 constexpr int kFeat = 15;
 constexpr int kSplit = 128;     // split-K factor of the weight gradient
 constexpr int kRed = 256;       // blocks of the first pass of small reductions
+constexpr int kIdxSteps = 256;  // batches of sample indices the workspace holds (training epochs upload them at once)
 constexpr int LDSK = 32;        // LDS row pitch in bf16 of the convolution tiles (32 channels, no pad)
 
 // Offset (bf16) of the 16-byte segment seg (8 channels) of row `row` in a
@@ -312,216 +314,200 @@ __global__ __launch_bounds__(256) void k_conv128(const bf16* __restrict__ X, con
 }
 
 // ---- persistent row-streaming convolution (width 128, K channels 32 or 64) ----
-// One workgroup (4 wavefronts) owns 64 output channels and a run of whole image
-// rows of 128 pixels.  Its weights (all 9 taps) stay in LDS for the whole run;
-// the input rows pass through a ring of 4 LDS slots filled by LDS DMA, the
-// next row loading while the current one is computed, so each input row
-// crosses from L2 once per workgroup and there is one barrier per output row.
-// Wavefront w computes pixels 32 w .. 32 w + 31 x 64 channels on the 32x32x16
-// bf16 MFMA (twice the rate of the 16x16x32 form on gfx950); the outputs leave
-// through per-wavefront LDS staging as whole 16-byte stores.
-constexpr int kRowW = 128;       // image width handled by the row kernel
+// One workgroup owns 64 output channels and a run of whole image rows of 128
+// pixels.  Its weights (all 9 taps) stay in LDS for the whole run; the input
+// rows pass through a ring of 4 LDS slots.  Eight wavefronts form two groups of
+// four that take alternate output rows, out of phase: in each step group A
+// computes row Ra and then stores it, while group B first stores its row of the
+// previous step and then computes row Ra + 1, so that one group's epilogue
+// (bias, SiLU, BF16 conversion, stores) runs beside the other group's matrix
+// work.  Wavefront w of a group computes pixels 32 w .. 32 w + 31 x 64 channels
+// on the 32x32x16 bf16 MFMA, its operand reads issued two K steps ahead of the
+// MFMAs that take them; the outputs leave straight from the accumulator layout
+// (per element, two runs of 32 consecutive channels).  The rows of the next
+// step come in through plain loads held in registers during the step and are
+// written to the two slots that the step has finished with (two barriers per
+// step of two rows).
+constexpr int kRowW = 128;       // image width handled by the row kernels
 constexpr int kRowPx = kRowW + 2;   // an input row with its two halo pixels
-constexpr int kStagePitch = 68;  // floats per pixel row of the epilogue staging (64 + 4: no bank aliasing)
 // 16-byte segment swizzle of LDS rows of CK bf16 (pixels of an input row, or output channels of a
 // weight tap): consecutive rows that would start on the same banks get different segments, so that
 // 16 lanes reading one logical segment of 16 consecutive rows hit 64 distinct banks
 template <int CK> __device__ __forceinline__ int swz(int row) { return (row / (128 / CK)) & (CK / 8 - 1); }
 
-template <int MODE, int CK>
-__global__ __launch_bounds__(256, 1) void k_conv_rows(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
+// MODE 0 (forward): z = acc + bias, stored when ZO; y = bf16(act ? SiLU(z) : z), stored when YO.
+// MODE 1 (data gradient): y = bf16(acc * SiLU'(Zprev)) (ZO false, YO true).
+template <int MODE, int CK, bool ZO, bool YO>
+__global__ __launch_bounds__(512, 1) void k_conv_rows(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
         const float* __restrict__ bias, const float* __restrict__ Zprev, float* __restrict__ Zout,
         bf16* __restrict__ Yout, int H, int rows_total, int rows_per_wg, int Cout, int act) {
+    static_assert(CK == 32 || CK == 64, "the K channels of a tap are 32 or 64");
+    static_assert(MODE == 0 || (!ZO && YO), "the data gradient stores y only");
     constexpr int S = CK / 8;                       // 16-byte segments per pixel / per weight row
-    static_assert(CK == 32 || CK == 64, "the operand read blocks are written for 32 and 64 K channels");
     constexpr int kWts = 9 * 64 * CK;               // bf16 of the workgroup's weights
     constexpr int kSlot = kRowPx * CK;              // bf16 per ring slot
-    constexpr int kRowPieces = kRowPx * S;          // 16-byte pieces per input row
-    constexpr int kFull = kRowPieces / 256, kRem = kRowPieces - 256 * kFull;
-    static_assert(kRem % 4 == 0 && kRem > 0 && kRem / 4 <= 64, "remainder pieces split over the four wavefronts");
-    constexpr int kRowLoads = kFull + 1;            // DMA instructions per input row and wavefront
-    static_assert(kWts % (256 * 8) == 0, "weight pieces fill whole rounds");
+    constexpr int kPieces = kRowPx * S;             // 16-byte pieces per input row
+    constexpr int kPer = (kPieces + 255) / 256;     // pieces per thread of a group (the last round partial)
     __shared__ __attribute__((aligned(16))) bf16 Wts[kWts];
     __shared__ __attribute__((aligned(16))) bf16 Ring[4 * kSlot];
-    __shared__ __attribute__((aligned(16))) float Stage[4 * 16 * kStagePitch];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = wave >> 2, pw = wave & 3, gtid = tid & 255;
     const int n0 = blockIdx.y << 6;
     const int R0 = blockIdx.x * rows_per_wg;
     const int R1 = min(R0 + rows_per_wg, rows_total);
     if (R0 >= R1) return;
-    float* stage = Stage + wave * 16 * kStagePitch;
 
-    // weights of this workgroup's 64 output channels: piece q = (tap 64 + co) S + s, segment
-    // s holding the 8 channels (s ^ (co & (S - 1))) so that the operand reads spread over the banks
-    // the rounds in an order rotated per workgroup: all workgroups read the same weights, and
-    // all of them starting on the first line would queue on the same L2 channels
-    constexpr int kWRounds = kWts / (256 * 8);
+    // weights of the workgroup's 64 output channels: piece q = (tap 64 + co) S + s holds the
+    // 8 channels (s ^ swz(co)); the rounds in an order rotated per workgroup, since all
+    // workgroups read the same weights and starting on the same lines would queue on the same
+    // L2 channels
+    constexpr int kWPieces = kWts / 8, kWRounds = (kWPieces + 511) / 512;
     for (int rr = 0; rr < kWRounds; ++rr) {
         const int r = (rr + (int)blockIdx.x) % kWRounds;
-        const int q = (r * 4 + wave) * 64 + lane;
-        const int tap = q / (64 * S), co = (q / S) % 64, ps = q % S;
-        const int ls = ps ^ swz<CK>(co);
-        __builtin_amdgcn_global_load_lds((const void*)(Wk + ((long long)(n0 + co) * 9 + tap) * CK + 8 * ls),
-                                         (lds_void*)(Wts + (size_t)(r * 4 + wave) * 64 * 8), 16, 0, 0);
+        const int q = r * 512 + tid;
+        if (q < kWPieces) {
+            const int tap = q / (64 * S), co = (q / S) % 64, ps = q % S;
+            const int ls = ps ^ swz<CK>(co);
+            *reinterpret_cast<uint4*>(Wts + (size_t)q * 8) =
+                *reinterpret_cast<const uint4*>(Wk + ((long long)(n0 + co) * 9 + tap) * CK + 8 * ls);
+        }
     }
-    // input row Rg (global row index) into ring slot Rg & 3: piece q = px S + s, pixel px of the
-    // row with halo (image column px - 1), segment s holding the channels (s ^ (px & (S - 1)));
-    // every wavefront issues kRowLoads instructions (the last round spread over all four)
-    auto load_row = [&](int Rg) {
-        bf16* slot = Ring + (size_t)(Rg & 3) * kSlot;
+    // input row Rg (zero outside 0..rows_total-1) by one group: piece q = px S + s, pixel px
+    // of the row with halo (image column px - 1), segment s holding the channels (s ^ swz(px))
+    auto fetch_row = [&](int Rg, uint4 (&v)[kPer]) {
         const bool rin = Rg >= 0 && Rg < rows_total;
 #pragma unroll
-        for (int r = 0; r < kRowLoads; ++r) {
-            const bool last = r == kFull;
-            const int base = last ? kFull * 256 + wave * (kRem / 4) : (r * 4 + wave) * 64;
-            const bool on = !last || lane < kRem / 4;
-            const int q = base + lane;
-            const int px = q / S, ps = q % S;
-            const int ls = ps ^ swz<CK>(px);
+        for (int r = 0; r < kPer; ++r) {
+            const int q = r * 256 + gtid;
+            const int px = q / S, ls = (q % S) ^ swz<CK>(px);
             const int x = px - 1;
-            const bool in = rin && on && x >= 0 && x < kRowW;
-            const void* src = in ? (const void*)(X + ((long long)Rg * kRowW + x) * CK + 8 * ls) : (const void*)&kZero16;
-            if (on) __builtin_amdgcn_global_load_lds(src, (lds_void*)(slot + (size_t)base * 8), 16, 0, 0);
+            const bool in = rin && q < kPieces && x >= 0 && x < kRowW;
+            v[r] = in ? *reinterpret_cast<const uint4*>(X + ((long long)Rg * kRowW + x) * CK + 8 * ls)
+                      : make_uint4(0u, 0u, 0u, 0u);
         }
     };
-    load_row(R0 - 1);
-    load_row(R0);
-    load_row(R0 + 1);
-    wait_vm<0>();
+    auto put_row = [&](int Rg, const uint4 (&v)[kPer]) {   // into ring slot Rg & 3
+        bf16* slot = Ring + (size_t)(Rg & 3) * kSlot;
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int q = r * 256 + gtid;
+            if (q < kPieces) *reinterpret_cast<uint4*>(slot + (size_t)q * 8) = v[r];
+        }
+    };
+    {
+        uint4 v[kPer];
+        fetch_row(R0 - 1 + grp, v);
+        put_row(R0 - 1 + grp, v);
+        fetch_row(R0 + 1 + grp, v);
+        put_row(R0 + 1 + grp, v);
+    }
     __syncthreads();
 
-    auto lds_addr = [](const void* p) { return (uint32_t)(uintptr_t)p; };
     const int l32 = lane & 31, kg = lane >> 5;
     const int swzw = swz<CK>(l32);   // weight-row swizzle (output channels l32 and 32 + l32 alike)
-    for (int R = R0; R < R1; ++R) {
-        const int y = R % H;
-        float zp[2][2][8];
-        if constexpr (MODE == 1) {
-            // pre-activations of this row in the epilogue's piece order (pixel q >> 3, channels 8 (q & 7))
-#pragma unroll
-            for (int g2 = 0; g2 < 2; ++g2)
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const int q = lane + 64 * i;
-                    const long long o = ((long long)R * kRowW + 32 * wave + 16 * g2 + (q >> 3)) * Cout + n0 + 8 * (q & 7);
-                    const float4 a = *reinterpret_cast<const float4*>(Zprev + o);
-                    const float4 b = *reinterpret_cast<const float4*>(Zprev + o + 4);
-                    zp[g2][i][0] = a.x; zp[g2][i][1] = a.y; zp[g2][i][2] = a.z; zp[g2][i][3] = a.w;
-                    zp[g2][i][4] = b.x; zp[g2][i][5] = b.y; zp[g2][i][6] = b.z; zp[g2][i][7] = b.w;
-                }
-        }
-        // input row R + 1 has landed (this wave's loads are older than the previous
-        // row's stores -- 8 of z, 4 of y, whichever are stored -- and, for the data
-        // gradient, the 8 pre-activation loads just issued), then every wave's
-        if (MODE == 1 || (Zout && Yout)) wait_vm<12>();
-        else if (Zout) wait_vm<8>();
-        else if (Yout) wait_vm<4>();
-        else wait_vm<0>();
-        __syncthreads();
-        load_row(R + 2);   // into the slot of row R - 2, which no wave reads any more
-
-        floatx16 acc0, acc1;
+    const float bc0 = MODE == 0 ? bias[n0 + l32] : 0.f, bc1 = MODE == 0 ? bias[n0 + 32 + l32] : 0.f;
+    // accumulator element j of lane l: output pixel 32 pw + 8 (j >> 2) + 4 kg + (j & 3) of the
+    // row, channels l32 (first accumulator) and 32 + l32 (second)
+    auto out_off = [&](int Rp, int j) {
+        return ((long long)Rp * kRowW + 32 * pw + 8 * (j >> 2) + 4 * kg + (j & 3)) * Cout + n0 + l32;
+    };
+    auto compute = [&](int R, floatx16& acc0, floatx16& acc1) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc0[e] = acc1[e] = 0.f;
-#pragma unroll
-        for (int dyi = 0; dyi < 3; ++dyi) {
-            const int yy = y + dyi - 1;
-            if (yy < 0 || yy >= H) continue;   // zero padding: the tap row contributes nothing
+        constexpr int PD = 2;                        // operand reads run PD K steps ahead
+        constexpr int HS = CK / 16, NS = 9 * HS;     // K steps per tap, per row
+        auto ld = [&](int st, bf16x8& a, bf16x8& b0, bf16x8& b1) {
+            const int t = st / HS, h = st % HS, dyi = t / 3, dxi = t % 3;
             const bf16* slot = Ring + (size_t)((R + dyi - 1) & 3) * kSlot;
+            const int pxi = 32 * pw + l32 + dxi;    // pixel (with halo) feeding output pixel 32 pw + l32
+            a = *reinterpret_cast<const bf16x8*>(slot + (size_t)pxi * CK + 8 * ((2 * h + kg) ^ swz<CK>(pxi)));
+            const bf16* brow0 = Wts + (size_t)(t * 64 + l32) * CK;
+            b0 = *reinterpret_cast<const bf16x8*>(brow0 + 8 * ((2 * h + kg) ^ swzw));
+            b1 = *reinterpret_cast<const bf16x8*>(brow0 + (size_t)32 * CK + 8 * ((2 * h + kg) ^ swzw));
+        };
+        const int y = R % H;
+        if (y > 0 && y < H - 1) {
+            bf16x8 A[PD + 1], B0[PD + 1], B1[PD + 1];
 #pragma unroll
-            for (int dxi = 0; dxi < 3; ++dxi) {
-                const int tap = 3 * dyi + dxi;
-                const int pxi = 32 * wave + l32 + dxi;       // pixel (with halo) feeding output pixel 32 w + l32
-                const bf16* arow = slot + (size_t)pxi * CK;
-                const bf16* brow0 = Wts + (size_t)(tap * 64 + l32) * CK;
-                const bf16* brow1 = brow0 + (size_t)32 * CK;
-                // every operand of the tap in one asm block that waits for its own LDS reads
-                // (as plain loads the compiler would also wait for the row DMA still in flight
-                // to another ring slot); the next tap's reads overlap this tap's MFMAs
-                auto at = [&](const bf16* row, int h, int sw) { return lds_addr(row + 8 * ((2 * h + kg) ^ sw)); };
-                const int swa = swz<CK>(pxi);
-                if constexpr (CK == 64) {
-                    bf16x8 a[4], b0[4], b1[4];
-                    asm volatile(
-                        "ds_read_b128 %0, %12\n\tds_read_b128 %1, %13\n\tds_read_b128 %2, %14\n\tds_read_b128 %3, %15\n\t"
-                        "ds_read_b128 %4, %16\n\tds_read_b128 %5, %17\n\tds_read_b128 %6, %18\n\tds_read_b128 %7, %19\n\t"
-                        "ds_read_b128 %8, %20\n\tds_read_b128 %9, %21\n\tds_read_b128 %10, %22\n\tds_read_b128 %11, %23\n\t"
-                        "s_waitcnt lgkmcnt(0)"
-                        : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3]), "=&v"(b0[0]), "=&v"(b0[1]), "=&v"(b0[2]),
-                          "=&v"(b0[3]), "=&v"(b1[0]), "=&v"(b1[1]), "=&v"(b1[2]), "=&v"(b1[3])
-                        : "v"(at(arow, 0, swa)), "v"(at(arow, 1, swa)), "v"(at(arow, 2, swa)), "v"(at(arow, 3, swa)),
-                          "v"(at(brow0, 0, swzw)), "v"(at(brow0, 1, swzw)), "v"(at(brow0, 2, swzw)), "v"(at(brow0, 3, swzw)),
-                          "v"(at(brow1, 0, swzw)), "v"(at(brow1, 1, swzw)), "v"(at(brow1, 2, swzw)), "v"(at(brow1, 3, swzw))
-                        : "memory");
+            for (int st = 0; st < PD; ++st) ld(st, A[st], B0[st], B1[st]);
+            __builtin_amdgcn_sched_group_barrier(0x100, 3 * PD, 0);   // the first PD steps' LDS reads
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b0[h], acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b1[h], acc1, 0, 0, 0);
-                    }
-                } else {
-                    bf16x8 a[2], b0[2], b1[2];
-                    asm volatile(
-                        "ds_read_b128 %0, %6\n\tds_read_b128 %1, %7\n\tds_read_b128 %2, %8\n\t"
-                        "ds_read_b128 %3, %9\n\tds_read_b128 %4, %10\n\tds_read_b128 %5, %11\n\t"
-                        "s_waitcnt lgkmcnt(0)"
-                        : "=&v"(a[0]), "=&v"(a[1]), "=&v"(b0[0]), "=&v"(b0[1]), "=&v"(b1[0]), "=&v"(b1[1])
-                        : "v"(at(arow, 0, swa)), "v"(at(arow, 1, swa)), "v"(at(brow0, 0, swzw)), "v"(at(brow0, 1, swzw)),
-                          "v"(at(brow1, 0, swzw)), "v"(at(brow1, 1, swzw))
-                        : "memory");
+            for (int st = 0; st < NS; ++st) {
+                constexpr int NB = PD + 1;
+                if (st + PD < NS) ld(st + PD, A[(st + PD) % NB], B0[(st + PD) % NB], B1[(st + PD) % NB]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[st % NB], B0[st % NB], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[st % NB], B1[st % NB], acc1, 0, 0, 0);
+                // keep the order: the reads of step st + PD, then the two MFMAs of step st
+                if (st + PD < NS) __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            }
+        } else {   // first or last row of an image: the tap row outside contributes nothing
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b0[h], acc0, 0, 0, 0);
-                        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h], b1[h], acc1, 0, 0, 0);
-                    }
-                }
+            for (int st = 0; st < NS; ++st) {
+                const int dyi = (st / HS) / 3;
+                if ((dyi == 0 && y == 0) || (dyi == 2 && y == H - 1)) continue;
+                bf16x8 a, b0, b1;
+                ld(st, a, b0, b1);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
             }
         }
-        // epilogue in two halves of 16 pixels through this wave's staging rows:
-        // acc element j of lane l is output pixel 8 (j >> 2) + 4 kg + (j & 3), channel l32 (+32)
+    };
+    auto load_z = [&](int Rp, float (&z0)[16], float (&z1)[16]) {   // pre-activations of row Rp
 #pragma unroll
-        for (int g2 = 0; g2 < 2; ++g2) {
-#pragma unroll
-            for (int j = 8 * g2; j < 8 * g2 + 8; ++j) {
-                const int m = 8 * ((j >> 2) - 2 * g2) + 4 * kg + (j & 3);
-                float v0 = acc0[j], v1 = acc1[j];
-                if constexpr (MODE == 0) {
-                    v0 += bias[n0 + l32];
-                    v1 += bias[n0 + 32 + l32];
-                }
-                stage[m * kStagePitch + l32] = v0;
-                stage[m * kStagePitch + 32 + l32] = v1;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int q = lane + 64 * i, pl = q >> 3, cg = q & 7;
-                const float4 a = *reinterpret_cast<const float4*>(&stage[pl * kStagePitch + 8 * cg]);
-                const float4 b = *reinterpret_cast<const float4*>(&stage[pl * kStagePitch + 8 * cg + 4]);
-                float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-                const long long o = ((long long)R * kRowW + 32 * wave + 16 * g2 + pl) * Cout + n0 + 8 * cg;
-                bf16x8 yv;
-                if constexpr (MODE == 0) {
-                    if (Zout) {
-                        *reinterpret_cast<float4*>(Zout + o) = a;
-                        *reinterpret_cast<float4*>(Zout + o + 4) = b;
-                    }
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) yv[e] = bf16(act ? silu(v[e]) : v[e]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) yv[e] = bf16(v[e] * silu_grad(zp[g2][i][e]));
-                }
-                if (Yout) *reinterpret_cast<bf16x8*>(Yout + o) = yv;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int j = 0; j < 16; ++j) {
+            const long long o = out_off(Rp, j);
+            z0[j] = Zprev[o];
+            z1[j] = Zprev[o + 32];
         }
-    }
-}
+    };
+    auto epi = [&](int Rp, const floatx16& a0, const floatx16& a1, const float (&z0)[16], const float (&z1)[16]) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const long long o = out_off(Rp, j);
+            if constexpr (MODE == 0) {
+                const float v0 = a0[j] + bc0, v1 = a1[j] + bc1;
+                if constexpr (ZO) {
+                    Zout[o] = v0;
+                    Zout[o + 32] = v1;
+                }
+                if constexpr (YO) {
+                    Yout[o] = bf16(act ? silu(v0) : v0);
+                    Yout[o + 32] = bf16(act ? silu(v1) : v1);
+                }
+            } else {
+                Yout[o] = bf16(a0[j] * silu_grad(z0[j]));
+                Yout[o + 32] = bf16(a1[j] * silu_grad(z1[j]));
+            }
+        }
+    };
 
+    floatx16 acc0, acc1;   // group A: this step's row; group B: its row, stored at the next step
+    float z0[16], z1[16];  // data gradient: the pre-activations of the same row
+    for (int Ra = R0; Ra < R1; Ra += 2) {
+        const int Rb = Ra + 1;
+        // rows Ra + 3 (group A) and Ra + 4 (group B) for the next step, which reads rows
+        // Ra + 1 .. Ra + 4; loaded now, written after every wave is done with rows Ra - 1, Ra
+        const int Rn = Ra + 3 + grp;
+        uint4 pre[kPer];
+        fetch_row(Ra + 2 < R1 ? Rn : -1, pre);
+        if (grp == 0) {
+            if constexpr (MODE == 1) load_z(Ra, z0, z1);
+            compute(Ra, acc0, acc1);
+            epi(Ra, acc0, acc1, z0, z1);
+        } else {
+            if (Ra > R0) epi(Ra - 1, acc0, acc1, z0, z1);
+            if (Rb < R1) {
+                if constexpr (MODE == 1) load_z(Rb, z0, z1);
+                compute(Rb, acc0, acc1);
+            }
+        }
+        __syncthreads();
+        put_row(Rn, pre);   // into the slots of rows Ra - 1 and Ra
+        __syncthreads();
+    }
+    if (grp == 1 && ((R1 - R0) & 1) == 0) epi(R1 - 1, acc0, acc1, z0, z1);
+}
 
 // ---- weight gradient: split-K implicit GEMM -------------------------------
 // part[s][tap][co][ci] = sum over the 64-pixel chunks of split s of dZ[p][co] x[p + off(tap)][ci].
@@ -951,7 +937,9 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Z, const 
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
-__global__ void k_mse_final(const double* __restrict__ part, int nb, double count, float* __restrict__ loss) {
+// the batch loss; with acc, also acc += the loss (as rounded to FP32), a running sum over steps
+__global__ void k_mse_final(const double* __restrict__ part, int nb, double count, float* __restrict__ loss,
+                            double* __restrict__ acc) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s = 0.0;
     for (int b = 0; b < nb; b += 16) {
@@ -961,7 +949,9 @@ __global__ void k_mse_final(const double* __restrict__ part, int nb, double coun
 #pragma unroll
         for (int k = 0; k < 16; ++k) s += v[k];
     }
-    *loss = (float)(s / count);
+    const float l = (float)(s / count);
+    *loss = l;
+    if (acc) *acc += (double)l;
 }
 
 // Adam (bias-corrected), FP32 master weights
@@ -1090,7 +1080,7 @@ struct Plan {
     size_t P;
     long long nw[kLayers], woff[kLayers], boff[kLayers], npacked;
     size_t w_off, m_off, v_off, g_off, wk_off[kLayers], wt_off[kLayers], x0_off, z_off[kLayers], y_off[kLayers],
-        dz_off[2], part_off, bpart_off, lpart_off, loss_off, idx_off, total;
+        dz_off[2], part_off, bpart_off, lpart_off, loss_off, lsum_off, idx_off, total;
 };
 
 Plan make_plan(const sg_config& c) {
@@ -1130,7 +1120,8 @@ Plan make_plan(const sg_config& c) {
     pl.bpart_off = take(4ull * kRed * kMaxC);
     pl.lpart_off = take(8ull * kRed);
     pl.loss_off = take(8);
-    pl.idx_off = take(4ull * c.batch);
+    pl.lsum_off = take(8);
+    pl.idx_off = take(4ull * c.batch * kIdxSteps);
     pl.total = o;
     return pl;
 }
@@ -1171,22 +1162,37 @@ lb_status launch_conv(sg_handle* h, int l, int mode, long long P, const bf16* x,
     const bf16* wk = ptr<bf16>(h, mode == 0 ? h->pl.wk_off[l] : h->pl.wt_off[l]);
     const float* bias = mode == 0 ? ptr<float>(h, h->pl.w_off) + h->pl.boff[l] : nullptr;
     const int act = mode == 0 && l + 1 < kLayers ? 1 : 0;
+    if (!y && (mode == 1 || !z)) return sgfail(LB_EINVAL, "launch_conv: no output");
     if (W == kRowW && (Ci == 32 || Ci == 64)) {
         const int rows_total = (int)(P / W);
         const int nblk = Co / 64;
         const int nwg = std::max(1, std::min(rows_total, 256 / nblk));   // one workgroup per CU
         const int rpw = (rows_total + nwg - 1) / nwg;
         const dim3 grid((unsigned)nwg, (unsigned)nblk);
+        // z and y, y only (prediction) or z only (the output layer)
+        auto fwd = [&](auto ck) {
+            constexpr int CK = decltype(ck)::value;
+            if (z && y)
+                hipLaunchKernelGGL((k_conv_rows<0, CK, true, true>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
+                                   rows_total, rpw, Co, act);
+            else if (y)
+                hipLaunchKernelGGL((k_conv_rows<0, CK, false, true>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
+                                   rows_total, rpw, Co, act);
+            else
+                hipLaunchKernelGGL((k_conv_rows<0, CK, true, false>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
+                                   rows_total, rpw, Co, act);
+        };
+        auto bwd = [&](auto ck) {
+            constexpr int CK = decltype(ck)::value;
+            hipLaunchKernelGGL((k_conv_rows<1, CK, false, true>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
+                               rows_total, rpw, Co, act);
+        };
         if (mode == 0) {
-            if (Ci == 32)
-                hipLaunchKernelGGL((k_conv_rows<0, 32>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
-            else
-                hipLaunchKernelGGL((k_conv_rows<0, 64>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
+            if (Ci == 32) fwd(std::integral_constant<int, 32>{});
+            else fwd(std::integral_constant<int, 64>{});
         } else {
-            if (Ci == 32)
-                hipLaunchKernelGGL((k_conv_rows<1, 32>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
-            else
-                hipLaunchKernelGGL((k_conv_rows<1, 64>), grid, dim3(256), 0, h->s, x, wk, bias, zprev, z, y, H, rows_total, rpw, Co, act);
+            if (Ci == 32) bwd(std::integral_constant<int, 32>{});
+            else bwd(std::integral_constant<int, 64>{});
         }
     } else if (W % 128 == 0) {
         const dim3 grid((unsigned)(P / 128), (unsigned)(Co / 64));
@@ -1249,11 +1255,12 @@ lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const b
 // forward pass of nb samples listed in the device index array; keep_z = false
 // (prediction) skips the FP32 pre-activation store of the hidden layers, which
 // only the backward pass reads
-lb_status forward(sg_handle* h, const float* d_params, int nb, bool keep_z = true) {
+lb_status forward(sg_handle* h, const float* d_params, int nb, bool keep_z = true, const int* idx = nullptr) {
+    if (!idx) idx = ptr<int>(h, h->pl.idx_off);
     const int H = h->c.height, W = h->c.width;
     const long long P = (long long)nb * H * W;
     hipLaunchKernelGGL(k_features, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, h->s, d_params,
-                       ptr<int>(h, h->pl.idx_off), nb, H, W, ptr<bf16>(h, h->pl.x0_off));
+                       idx, nb, H, W, ptr<bf16>(h, h->pl.x0_off));
     SGCHK(hipGetLastError());
     const bf16* x = ptr<bf16>(h, h->pl.x0_off);
     for (int l = 0; l < kLayers; ++l) {
@@ -1275,16 +1282,20 @@ lb_status set_indices(sg_handle* h, const int32_t* host_idx, int nb) {
 }
 
 // loss + gradients of every layer into the packed gradient vector
-lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host) {
+// loss_host: the batch loss, read back (synchronising); lsum: device running sum of the
+// batch losses (no synchronisation)
+lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host, const int* idx = nullptr,
+                   double* lsum = nullptr) {
+    if (!idx) idx = ptr<int>(h, h->pl.idx_off);
     const int H = h->c.height, W = h->c.width;
     const long long P = (long long)nb * H * W;
     const int L = kLayers - 1;
     bf16* dz = ptr<bf16>(h, h->pl.dz_off[0]);
     hipLaunchKernelGGL(k_mse, dim3(kRed), dim3(256), 0, h->s, ptr<float>(h, h->pl.z_off[L]), d_fields,
-                       ptr<int>(h, h->pl.idx_off), nb, H, W, kCoutPad[L], dz, ptr<double>(h, h->pl.lpart_off));
+                       idx, nb, H, W, kCoutPad[L], dz, ptr<double>(h, h->pl.lpart_off));
     SGCHK(hipGetLastError());
     hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, h->s, ptr<double>(h, h->pl.lpart_off), kRed,
-                       (double)(P * SG_OUTPUTS), ptr<float>(h, h->pl.loss_off));
+                       (double)(P * SG_OUTPUTS), ptr<float>(h, h->pl.loss_off), lsum);
     SGCHK(hipGetLastError());
     float* grads = ptr<float>(h, h->pl.g_off);
     for (int l = L; l >= 0; --l) {
@@ -1426,24 +1437,37 @@ lb_status sg_train_step(sg_handle* h, const float* d_params, const float* d_fiel
 
 lb_status sg_train_epochs(sg_handle* h, const float* d_params, const float* d_fields, int32_t n, int32_t epochs,
                           uint64_t seed, float* losses_out) {
-    if (!h || n < h->c.batch || epochs < 0) return sgfail(LB_EINVAL, "need n >= batch and epochs >= 0");
+    if (!h || !d_params || !d_fields || n < h->c.batch || epochs < 0)
+        return sgfail(LB_EINVAL, "need the parameter and field arrays, n >= batch and epochs >= 0");
     std::vector<int32_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::mt19937_64 rng(seed);
-    const int nbatch = n / h->c.batch;
-    std::vector<float> losses((size_t)nbatch);
+    const int B = h->c.batch, nbatch = n / B;
+    int* idx = ptr<int>(h, h->pl.idx_off);
+    double* lsum = ptr<double>(h, h->pl.lsum_off);
     for (int e = 0; e < epochs; ++e) {
         for (int k = n - 1; k > 0; --k) {  // Fisher-Yates with the seeded generator
             const int j = (int)(rng() % (uint64_t)(k + 1));
             std::swap(order[k], order[j]);
         }
-        double sum = 0.0;
-        for (int b = 0; b < nbatch; ++b) {
-            float loss = 0.f;
-            lb_status st = sg_train_step(h, d_params, d_fields, order.data() + (size_t)b * h->c.batch, &loss);
-            if (st != LB_OK) return st;
-            sum += loss;
+        // the steps run back to back: the indices go up kIdxSteps batches at a time (stream
+        // ordered after the steps that read the previous ones) and the batch losses are summed
+        // on the device, in step order, and read once per epoch
+        SGCHK(hipMemsetAsync(lsum, 0, sizeof(double), h->s));
+        for (int b0 = 0; b0 < nbatch; b0 += kIdxSteps) {
+            const int nb = std::min(kIdxSteps, nbatch - b0);
+            SGCHK(hipMemcpyAsync(idx, order.data() + (size_t)b0 * B, 4ull * B * nb, hipMemcpyHostToDevice, h->s));
+            for (int b = 0; b < nb; ++b) {
+                const int* ib = idx + (size_t)b * B;
+                lb_status st = forward(h, d_params, B, true, ib);
+                if (st == LB_OK) st = backward(h, d_fields, B, nullptr, ib, lsum);
+                if (st == LB_OK) st = adam(h);
+                if (st != LB_OK) return st;
+            }
         }
+        double sum = 0.0;
+        SGCHK(hipMemcpyAsync(&sum, lsum, sizeof(double), hipMemcpyDeviceToHost, h->s));
+        SGCHK(hipStreamSynchronize(h->s));
         if (losses_out) losses_out[e] = (float)(sum / nbatch);
     }
     SGCHK(hipStreamSynchronize(h->s));

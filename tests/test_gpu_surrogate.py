@@ -164,3 +164,30 @@ def test_destagger_matches_oracle():
     assert np.abs(got - want).max() <= 2e-6
     sy = ((-1.0) ** np.arange(128))[:, None]
     assert np.abs((got[:, 1] * sy).mean(axis=(1, 2))).max() <= 1e-7
+
+
+def test_train_epochs_equals_its_steps():
+    """sg_train_epochs (steps back to back, indices uploaded per block of steps, batch
+    losses summed on the device) against the same steps one sg_train_step call at a
+    time in the order its shuffle draws (host copy of its generator): weights and
+    epoch losses bitwise equal."""
+    from tests.mt64 import shuffled_epochs
+
+    batch, n, epochs, seed = 4, 12, 2, 5
+    rng = np.random.default_rng(8)
+    dp = torch.tensor(rng.uniform(0, 1, (n, 5)), dtype=torch.float32, device="cuda")
+    df = torch.tensor(rng.uniform(-1, 1, (n, 4, H, W)), dtype=torch.float32, device="cuda")
+    a, w0, _, _, _ = setup(batch=batch)
+    la = a.train_epochs(dp, df, n, epochs, seed=seed)
+    wa = a.get_weights()
+    b = sg.Surrogate(batch, H, W, lr=1e-3)
+    b.set_weights(w0)
+    lb_ = []
+    for order in shuffled_epochs(n, epochs, seed):
+        s = 0.0
+        for k in range(n // batch):
+            s += float(b.train_step(dp, df, np.array(order[k * batch:(k + 1) * batch], dtype=np.int32)))
+        lb_.append(np.float32(s / (n // batch)))
+    wb = b.get_weights()
+    assert np.array_equal(wa, wb)
+    assert np.array_equal(la, np.array(lb_, dtype=np.float32))
