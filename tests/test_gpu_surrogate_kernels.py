@@ -67,7 +67,12 @@ def check_bf16_output(got, want, label, rel=1e-5):
     assert exact > 0.98, label
 
 
-@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (1, 64, 256)])
+# at width 128 the row kernels give each workgroup a run of rows, worked in steps of two
+# rows by two groups of wavefronts: 2 x 128 rows over 256 workgroups is one row each (the
+# second group idle), 5 x 128 = 640 rows is three (two steps, the last with one row; the
+# last workgroup has a single row) or five for the 128-channel outputs, and runs cross
+# image boundaries
+@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (5, 128, 128), (1, 64, 256)])
 def test_forward_convolutions_match_oracle(B, H, W):
     net, _, layers = make_net(B, H, W, seed=1)
     rng = np.random.default_rng(2)
@@ -85,9 +90,14 @@ def test_forward_convolutions_match_oracle(B, H, W):
         assert e < 1e-5, l
         act = S.silu(want) if l + 1 < len(layers) else want
         check_bf16_output(to_np(dy), act, f"layer {l} activation")
+        # without the pre-activation store (the prediction's kernels): the same activation
+        dy2 = torch.empty_like(dy)
+        net.conv(l, 0, B, dx, dy2)
+        torch.cuda.synchronize()
+        assert torch.equal(dy, dy2), l
 
 
-@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (1, 64, 256)])
+@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (5, 128, 128), (1, 64, 256)])
 def test_data_gradient_convolutions_match_oracle(B, H, W):
     net, _, layers = make_net(B, H, W, seed=3)
     rng = np.random.default_rng(4)
