@@ -49,6 +49,7 @@ constexpr int kMaxC = 128;
 constexpr int kFeat = 15;
 constexpr int kSplit = 128;     // split-K factor of the weight gradient
 constexpr int kRed = 256;       // blocks of the first pass of small reductions
+constexpr int kMseBlocks = 1024;  // blocks of the loss pass (four per CU: its loads need the parallelism)
 constexpr int kIdxSteps = 256;  // batches of sample indices the workspace holds (training epochs upload them at once)
 constexpr int LDSK = 32;        // LDS row pitch in bf16 of the convolution tiles (32 channels, no pad)
 
@@ -823,9 +824,26 @@ __global__ __launch_bounds__(64 * kWgWaves, 1) void k_wgrad_rows(const bf16* __r
 // dW = sum over the ns partials, in a fixed order: a workgroup covers 64
 // outputs, its wave g sums partials [g ns / 4, (g + 1) ns / 4) of them, then
 // the four wave sums are added in wave order
+// dW[co][tap][ci] = the fixed-order sum of the ns split partials (four quarters, added in
+// order); the grid's last workgroup adds up the bias partials instead: db[co] = the sum of
+// bpart[0 .. nb-1][co], in two halves added in order
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int ns, int Ci, int Co,
-                                                      float* __restrict__ dW) {
-    __shared__ float red[3][64];
+                                                      float* __restrict__ dW, const float* __restrict__ bpart, int nb,
+                                                      float* __restrict__ db) {
+    __shared__ float red[3][kMaxC];
+    if (blockIdx.x == gridDim.x - 1) {
+        const int co = (int)threadIdx.x % kMaxC, g = (int)threadIdx.x / kMaxC;
+        const int b0 = g * nb / 2, b1 = (g + 1) * nb / 2;
+        float t = 0.f;
+        if (co < Co) {
+#pragma unroll 8
+            for (int q = b0; q < b1; ++q) t += bpart[(long long)q * kMaxC + co];
+        }
+        if (g == 1) red[0][co] = t;
+        __syncthreads();
+        if (g == 0 && co < Co) db[co] = t + red[0][co];
+        return;
+    }
     const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
     const long long k = ((long long)blockIdx.x << 6) + j;
     const long long n = 9ll * Co * Ci;
@@ -877,28 +895,6 @@ __global__ __launch_bounds__(256) void k_bgrad_part(const bf16* __restrict__ dZ,
     }
 }
 
-// db[co] = sum over the nb first-pass partials, in a fixed order: thread
-// (co, g) sums the g-th eighth of them, then the eight sums are added in g order
-__global__ __launch_bounds__(8 * kMaxC) void k_bgrad_final(const float* __restrict__ part, int nb, int Co,
-                                                     float* __restrict__ db) {
-    __shared__ float red[8][kMaxC];
-    const int co = (int)threadIdx.x % kMaxC, g = (int)threadIdx.x / kMaxC;
-    const int b0 = g * nb / 8, b1 = (g + 1) * nb / 8;
-    float s = 0.f;
-    if (co < Co) {
-#pragma unroll 8
-        for (int b = b0; b < b1; ++b) s += part[(long long)b * kMaxC + co];
-    }
-    red[g][co] = s;
-    __syncthreads();
-    if (g == 0 && co < Co) {
-        float t = red[0][co];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) t += red[k][co];
-        db[co] = t;
-    }
-}
-
 // MSE over the SG_OUTPUTS real channels: dZ = 2 (z - t) / count (bf16, zero on
 // padded channels); per-block partial sums of (z - t)^2 in FP64
 static_assert(SG_OUTPUTS <= 8, "k_mse keeps the real output channels in the first 8-channel group");
@@ -937,27 +933,57 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Z, const 
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
-// the batch loss; with acc, also acc += the loss (as rounded to FP32), a running sum over steps
-__global__ void k_mse_final(const double* __restrict__ part, int nb, double count, float* __restrict__ loss,
-                            double* __restrict__ acc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// the batch loss; with acc, also acc += the loss (as rounded to FP32), a running sum over steps.
+// One workgroup of 64 threads: thread t sums the t-th run of nb / 64 partials in order, thread 0
+// adds the 64 run sums in order (fixed order, deterministic)
+__global__ __launch_bounds__(64) void k_mse_final(const double* __restrict__ part, int nb, double count,
+                                                  float* __restrict__ loss, double* __restrict__ acc) {
+    __shared__ double red[64];
+    const int t = (int)threadIdx.x;
+    const int b0 = t * nb / 64, b1 = (t + 1) * nb / 64;
     double s = 0.0;
-    for (int b = 0; b < nb; b += 16) {
-        double v[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = b + k < nb ? part[b + k] : 0.0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) s += v[k];
-    }
+    for (int b = b0; b < b1; ++b) s += part[b];
+    red[t] = s;
+    __syncthreads();
+    if (t != 0) return;
+    s = 0.0;
+    for (int k = 0; k < 64; ++k) s += red[k];
     const float l = (float)(s / count);
     *loss = l;
     if (acc) *acc += (double)l;
 }
 
-// Adam (bias-corrected), FP32 master weights
+// where each layer's weights sit in the packed vector and their two BF16 copies
+struct PackMap {
+    long long woff[kLayers];
+    int ci[kLayers], co[kLayers];
+    bf16* wk[kLayers];
+    bf16* wt[kLayers];
+};
+
+// weight k of the packed vector (value v) into the BF16 copies of its layer: the forward
+// GEMM's [co][tap][ci] and the data-gradient GEMM's [ci][8 - tap][co] (transposed and
+// flipped); biases have no copy
+__device__ __forceinline__ void pack_one(const PackMap& pm, long long k, float v) {
+#pragma unroll
+    for (int l = 0; l < kLayers; ++l) {
+        const long long r = k - pm.woff[l];
+        const int Ci = pm.ci[l], Co = pm.co[l];
+        if (r >= 0 && r < 9ll * Co * Ci) {
+            const int co = (int)(r / (9ll * Ci));
+            const long long rem = r % (9ll * Ci);
+            const int tap = (int)(rem / Ci), ci = (int)(rem % Ci);
+            const bf16 b = bf16(v);
+            pm.wk[l][r] = b;
+            pm.wt[l][((long long)ci * 9 + (8 - tap)) * Co + co] = b;
+        }
+    }
+}
+
+// Adam (bias-corrected) on the FP32 master weights, then their BF16 copies
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                                               float* __restrict__ v, long long n, float lr, float b1, float b2,
-                                              float eps, float c1, float c2) {
+                                              float eps, float c1, float c2, PackMap pm) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const float gk = g[k];
@@ -965,21 +991,15 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float
     const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
     m[k] = mk;
     v[k] = vk;
-    w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    const float wk = w[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    w[k] = wk;
+    pack_one(pm, k, wk);
 }
 
-// bf16 weights for the forward GEMM ([co][tap][ci]) and the data-gradient GEMM
-// ([ci][8 - tap][co]: transposed and flipped)
-__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, int Ci, int Co, bf16* __restrict__ wk,
-                                              bf16* __restrict__ wt) {
+// the BF16 copies of every layer's weights (after weights are set)
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, long long n, PackMap pm) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= 9ll * Co * Ci) return;
-    const int co = (int)(k / (9ll * Ci));
-    const long long rem = k % (9ll * Ci);
-    const int tap = (int)(rem / Ci), ci = (int)(rem % Ci);
-    const bf16 v = bf16(w[k]);
-    wk[k] = v;
-    wt[((long long)ci * 9 + (8 - tap)) * Co + co] = v;
+    if (k < n) pack_one(pm, k, w[k]);
 }
 
 // [p][Co] (first SG_OUTPUTS channels) -> out[b][c][y][x]
@@ -1118,7 +1138,7 @@ Plan make_plan(const sg_config& c) {
     pl.dz_off[1] = take(2 * pl.P * kMaxC);
     pl.part_off = take(4ull * kSplit * 9 * kMaxC * kMaxC);
     pl.bpart_off = take(4ull * kRed * kMaxC);
-    pl.lpart_off = take(8ull * kRed);
+    pl.lpart_off = take(8ull * kMseBlocks);
     pl.loss_off = take(8);
     pl.lsum_off = take(8);
     pl.idx_off = take(4ull * c.batch * kIdxSteps);
@@ -1141,14 +1161,23 @@ namespace {
 template <class T>
 T* ptr(sg_handle* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
 
-lb_status pack_weights(sg_handle* h) {
+PackMap pack_map(sg_handle* h) {
+    PackMap pm{};
     for (int l = 0; l < kLayers; ++l) {
-        const long long n = h->pl.nw[l];
-        hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s,
-                           ptr<float>(h, h->pl.w_off) + h->pl.woff[l], kCinPad[l], kCoutPad[l],
-                           ptr<bf16>(h, h->pl.wk_off[l]), ptr<bf16>(h, h->pl.wt_off[l]));
-        SGCHK(hipGetLastError());
+        pm.woff[l] = h->pl.woff[l];
+        pm.ci[l] = kCinPad[l];
+        pm.co[l] = kCoutPad[l];
+        pm.wk[l] = ptr<bf16>(h, h->pl.wk_off[l]);
+        pm.wt[l] = ptr<bf16>(h, h->pl.wt_off[l]);
     }
+    return pm;
+}
+
+lb_status pack_weights(sg_handle* h) {
+    const long long n = h->pl.npacked;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s, ptr<float>(h, h->pl.w_off), n,
+                       pack_map(h));
+    SGCHK(hipGetLastError());
     return LB_OK;
 }
 
@@ -1234,20 +1263,18 @@ lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const b
         else
             hipLaunchKernelGGL(k_wgrad_rows<64>, grid, dim3(64 * kWgWaves), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
         SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s, part, ns, Ci, Co, dw);
-        SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, bpart, nwg, Co, db);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64 + 1)), dim3(256), 0, h->s, part, ns, Ci, Co, dw,
+                           bpart, nwg, db);
         SGCHK(hipGetLastError());
         return LB_OK;
     }
     hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(Co / 64), (unsigned)((Ci + 63) / 64), 3u * kSplit), dim3(256), 0, h->s,
                        dz, xin, part, H, W, (int)P, Ci, Co);
     SGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, h->s, part, kSplit, Ci, Co, dw);
-    SGCHK(hipGetLastError());
     hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, bpart);
     SGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_bgrad_final, dim3(1), dim3(8 * kMaxC), 0, h->s, bpart, kRed, Co, db);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64 + 1)), dim3(256), 0, h->s, part, kSplit, Ci, Co, dw,
+                       bpart, kRed, db);
     SGCHK(hipGetLastError());
     return LB_OK;
 }
@@ -1291,10 +1318,10 @@ lb_status backward(sg_handle* h, const float* d_fields, int nb, float* loss_host
     const long long P = (long long)nb * H * W;
     const int L = kLayers - 1;
     bf16* dz = ptr<bf16>(h, h->pl.dz_off[0]);
-    hipLaunchKernelGGL(k_mse, dim3(kRed), dim3(256), 0, h->s, ptr<float>(h, h->pl.z_off[L]), d_fields,
+    hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, h->s, ptr<float>(h, h->pl.z_off[L]), d_fields,
                        idx, nb, H, W, kCoutPad[L], dz, ptr<double>(h, h->pl.lpart_off));
     SGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, h->s, ptr<double>(h, h->pl.lpart_off), kRed,
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, h->s, ptr<double>(h, h->pl.lpart_off), kMseBlocks,
                        (double)(P * SG_OUTPUTS), ptr<float>(h, h->pl.loss_off), lsum);
     SGCHK(hipGetLastError());
     float* grads = ptr<float>(h, h->pl.g_off);
@@ -1322,9 +1349,9 @@ lb_status adam(sg_handle* h) {
     const long long n = h->pl.npacked;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->s, ptr<float>(h, h->pl.w_off),
                        ptr<float>(h, h->pl.g_off), ptr<float>(h, h->pl.m_off), ptr<float>(h, h->pl.v_off), n, h->c.lr,
-                       h->c.beta1, h->c.beta2, h->c.eps, c1, c2);
+                       h->c.beta1, h->c.beta2, h->c.eps, c1, c2, pack_map(h));
     SGCHK(hipGetLastError());
-    return pack_weights(h);
+    return LB_OK;
 }
 
 lb_status check_idx(sg_handle* h, const int32_t* idx) {
