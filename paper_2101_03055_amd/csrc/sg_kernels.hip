@@ -338,12 +338,19 @@ template <int CK> __device__ __forceinline__ int swz(int row) { return (row / (1
 
 // MODE 0 (forward): z = acc + bias, stored when ZO; y = bf16(act ? SiLU(z) : z), stored when YO.
 // MODE 1 (data gradient): y = bf16(acc * SiLU'(Zprev)) (ZO false, YO true).
-template <int MODE, int CK, bool ZO, bool YO>
+// The K channels of a tap are X's channels koff .. koff + CK - 1 of xcs (the weights' K stride
+// is xcs too).  KS = 0: all of them in one launch.  With more K channels than the LDS holds
+// beside the ring, two forward launches: KS = 1 stores the raw sums of the first CK channels
+// to Zpart (FP32, [pixel][Cout]); KS = 2 adds them to its own before the bias.
+template <int MODE, int CK, bool ZO, bool YO, int KS>
 __global__ __launch_bounds__(512, 1) void k_conv_rows(const bf16* __restrict__ X, const bf16* __restrict__ Wk,
         const float* __restrict__ bias, const float* __restrict__ Zprev, float* __restrict__ Zout,
-        bf16* __restrict__ Yout, int H, int rows_total, int rows_per_wg, int Cout, int act) {
+        bf16* __restrict__ Yout, float* __restrict__ Zpart, int H, int rows_total, int rows_per_wg, int Cout, int act,
+        int xcs, int koff) {
     static_assert(CK == 32 || CK == 64, "the K channels of a tap are 32 or 64");
     static_assert(MODE == 0 || (!ZO && YO), "the data gradient stores y only");
+    static_assert(KS != 1 || (!ZO && !YO), "the first of two K launches stores the partial sums only");
+    static_assert(KS == 0 || MODE == 0, "two K launches for the forward only");
     constexpr int S = CK / 8;                       // 16-byte segments per pixel / per weight row
     constexpr int kWts = 9 * 64 * CK;               // bf16 of the workgroup's weights
     constexpr int kSlot = kRowPx * CK;              // bf16 per ring slot
@@ -370,7 +377,7 @@ __global__ __launch_bounds__(512, 1) void k_conv_rows(const bf16* __restrict__ X
             const int tap = q / (64 * S), co = (q / S) % 64, ps = q % S;
             const int ls = ps ^ swz<CK>(co);
             *reinterpret_cast<uint4*>(Wts + (size_t)q * 8) =
-                *reinterpret_cast<const uint4*>(Wk + ((long long)(n0 + co) * 9 + tap) * CK + 8 * ls);
+                *reinterpret_cast<const uint4*>(Wk + ((long long)(n0 + co) * 9 + tap) * xcs + koff + 8 * ls);
         }
     }
     // input row Rg (zero outside 0..rows_total-1) by one group: piece q = px S + s, pixel px
@@ -383,7 +390,7 @@ __global__ __launch_bounds__(512, 1) void k_conv_rows(const bf16* __restrict__ X
             const int px = q / S, ls = (q % S) ^ swz<CK>(px);
             const int x = px - 1;
             const bool in = rin && q < kPieces && x >= 0 && x < kRowW;
-            v[r] = in ? *reinterpret_cast<const uint4*>(X + ((long long)Rg * kRowW + x) * CK + 8 * ls)
+            v[r] = in ? *reinterpret_cast<const uint4*>(X + ((long long)Rg * kRowW + x) * xcs + koff + 8 * ls)
                       : make_uint4(0u, 0u, 0u, 0u);
         }
     };
@@ -454,20 +461,26 @@ __global__ __launch_bounds__(512, 1) void k_conv_rows(const bf16* __restrict__ X
             }
         }
     };
-    auto load_z = [&](int Rp, float (&z0)[16], float (&z1)[16]) {   // pre-activations of row Rp
+    // pre-activations of row Rp (data gradient), or the first K launch's sums (forward, KS = 2)
+    auto load_z = [&](int Rp, float (&z0)[16], float (&z1)[16]) {
+        const float* src = MODE == 1 ? Zprev : Zpart;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const long long o = out_off(Rp, j);
-            z0[j] = Zprev[o];
-            z1[j] = Zprev[o + 32];
+            z0[j] = src[o];
+            z1[j] = src[o + 32];
         }
     };
+    constexpr bool kLoadZ = MODE == 1 || KS == 2;
     auto epi = [&](int Rp, const floatx16& a0, const floatx16& a1, const float (&z0)[16], const float (&z1)[16]) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const long long o = out_off(Rp, j);
-            if constexpr (MODE == 0) {
-                const float v0 = a0[j] + bc0, v1 = a1[j] + bc1;
+            if constexpr (KS == 1) {
+                Zpart[o] = a0[j];
+                Zpart[o + 32] = a1[j];
+            } else if constexpr (MODE == 0) {
+                const float v0 = (KS == 2 ? a0[j] + z0[j] : a0[j]) + bc0, v1 = (KS == 2 ? a1[j] + z1[j] : a1[j]) + bc1;
                 if constexpr (ZO) {
                     Zout[o] = v0;
                     Zout[o + 32] = v1;
@@ -493,13 +506,13 @@ __global__ __launch_bounds__(512, 1) void k_conv_rows(const bf16* __restrict__ X
         uint4 pre[kPer];
         fetch_row(Ra + 2 < R1 ? Rn : -1, pre);
         if (grp == 0) {
-            if constexpr (MODE == 1) load_z(Ra, z0, z1);
+            if constexpr (kLoadZ) load_z(Ra, z0, z1);
             compute(Ra, acc0, acc1);
             epi(Ra, acc0, acc1, z0, z1);
         } else {
             if (Ra > R0) epi(Ra - 1, acc0, acc1, z0, z1);
             if (Rb < R1) {
-                if constexpr (MODE == 1) load_z(Rb, z0, z1);
+                if constexpr (kLoadZ) load_z(Rb, z0, z1);
                 compute(Rb, acc0, acc1);
             }
         }
@@ -1192,36 +1205,47 @@ lb_status launch_conv(sg_handle* h, int l, int mode, long long P, const bf16* x,
     const float* bias = mode == 0 ? ptr<float>(h, h->pl.w_off) + h->pl.boff[l] : nullptr;
     const int act = mode == 0 && l + 1 < kLayers ? 1 : 0;
     if (!y && (mode == 1 || !z)) return sgfail(LB_EINVAL, "launch_conv: no output");
-    if (W == kRowW && (Ci == 32 || Ci == 64)) {
-        const int rows_total = (int)(P / W);
+    const int rows_total = (int)(P / W);
+    // forward with 128 K channels: two K launches of 64 channels through the FP32 partial buffer
+    // (free outside the weight gradient) when the partial sums fit.  Not for the data gradient:
+    // there the second launch holds the pre-activations and the partial sums at once and
+    // spills (measured 89 -> 102 us against the tile kernel, where the forward gains 90 -> 75 us)
+    const bool ksplit = mode == 0 && W == kRowW && Ci == 128 && Co == 64 &&
+                        4ull * (size_t)P * Co <= 4ull * kSplit * 9 * kMaxC * kMaxC;
+    if (W == kRowW && (Ci == 32 || Ci == 64 || ksplit)) {
         const int nblk = Co / 64;
         const int nwg = std::max(1, std::min(rows_total, 256 / nblk));   // one workgroup per CU
         const int rpw = (rows_total + nwg - 1) / nwg;
         const dim3 grid((unsigned)nwg, (unsigned)nblk);
-        // z and y, y only (prediction) or z only (the output layer)
-        auto fwd = [&](auto ck) {
-            constexpr int CK = decltype(ck)::value;
-            if (z && y)
-                hipLaunchKernelGGL((k_conv_rows<0, CK, true, true>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
-                                   rows_total, rpw, Co, act);
-            else if (y)
-                hipLaunchKernelGGL((k_conv_rows<0, CK, false, true>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
-                                   rows_total, rpw, Co, act);
-            else
-                hipLaunchKernelGGL((k_conv_rows<0, CK, true, false>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
-                                   rows_total, rpw, Co, act);
+        float* zpart = ptr<float>(h, h->pl.part_off);
+        auto go = [&](auto kern, int koff) {
+            hipLaunchKernelGGL(kern, grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, zpart, H, rows_total, rpw, Co, act,
+                               Ci, koff);
         };
-        auto bwd = [&](auto ck) {
-            constexpr int CK = decltype(ck)::value;
-            hipLaunchKernelGGL((k_conv_rows<1, CK, false, true>), grid, dim3(512), 0, h->s, x, wk, bias, zprev, z, y, H,
-                               rows_total, rpw, Co, act);
-        };
-        if (mode == 0) {
-            if (Ci == 32) fwd(std::integral_constant<int, 32>{});
-            else fwd(std::integral_constant<int, 64>{});
+        if (ksplit) {
+            go(k_conv_rows<0, 64, false, false, 1>, 0);
+            if (z && y) go(k_conv_rows<0, 64, true, true, 2>, 64);
+            else if (y) go(k_conv_rows<0, 64, false, true, 2>, 64);
+            else go(k_conv_rows<0, 64, true, false, 2>, 64);
         } else {
-            if (Ci == 32) bwd(std::integral_constant<int, 32>{});
-            else bwd(std::integral_constant<int, 64>{});
+            // z and y, y only (prediction) or z only (the output layer)
+            auto fwd = [&](auto ck) {
+                constexpr int CK = decltype(ck)::value;
+                if (z && y) go(k_conv_rows<0, CK, true, true, 0>, 0);
+                else if (y) go(k_conv_rows<0, CK, false, true, 0>, 0);
+                else go(k_conv_rows<0, CK, true, false, 0>, 0);
+            };
+            auto bwd = [&](auto ck) {
+                constexpr int CK = decltype(ck)::value;
+                go(k_conv_rows<1, CK, false, true, 0>, 0);
+            };
+            if (mode == 0) {
+                if (Ci == 32) fwd(std::integral_constant<int, 32>{});
+                else fwd(std::integral_constant<int, 64>{});
+            } else {
+                if (Ci == 32) bwd(std::integral_constant<int, 32>{});
+                else bwd(std::integral_constant<int, 64>{});
+            }
         }
     } else if (W % 128 == 0) {
         const dim3 grid((unsigned)(P / 128), (unsigned)(Co / 64));
