@@ -1208,8 +1208,9 @@ lb_status launch_conv(sg_handle* h, int l, int mode, long long P, const bf16* x,
     const int rows_total = (int)(P / W);
     // forward with 128 K channels: two K launches of 64 channels through the FP32 partial buffer
     // (free outside the weight gradient) when the partial sums fit.  Not for the data gradient:
-    // there the second launch holds the pre-activations and the partial sums at once and
-    // spills (measured 89 -> 102 us against the tile kernel, where the forward gains 90 -> 75 us)
+    // against its tile kernel's 86-89 us the two launches took 102 us with the pre-activations
+    // held beside the partial sums (spilled) and 94-98 us with both read in the epilogue
+    // (where the forward gains 90 -> 75 us)
     const bool ksplit = mode == 0 && W == kRowW && Ci == 128 && Co == 64 &&
                         4ull * (size_t)P * Co <= 4ull * kSplit * 9 * kMaxC * kMaxC;
     if (W == kRowW && (Ci == 32 || Ci == 64 || ksplit)) {

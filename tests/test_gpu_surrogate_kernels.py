@@ -71,8 +71,9 @@ def check_bf16_output(got, want, label, rel=1e-5):
 # rows by two groups of wavefronts: 2 x 128 rows over 256 workgroups is one row each (the
 # second group idle), 5 x 128 = 640 rows is three (two steps, the last with one row; the
 # last workgroup has a single row) or five for the 128-channel outputs, and runs cross
-# image boundaries
-@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (5, 128, 128), (1, 64, 256)])
+# image boundaries; 7 x 37 = 259 rows gives runs of two rows with an image boundary every
+# 37 rows (first and last rows of an image inside a step) and a last workgroup of one row
+@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (5, 128, 128), (7, 37, 128), (1, 64, 256)])
 def test_forward_convolutions_match_oracle(B, H, W):
     net, _, layers = make_net(B, H, W, seed=1)
     rng = np.random.default_rng(2)
@@ -97,7 +98,7 @@ def test_forward_convolutions_match_oracle(B, H, W):
         assert torch.equal(dy, dy2), l
 
 
-@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (5, 128, 128), (1, 64, 256)])
+@pytest.mark.parametrize("B, H, W", [(2, 128, 128), (5, 128, 128), (7, 37, 128), (1, 64, 256)])
 def test_data_gradient_convolutions_match_oracle(B, H, W):
     net, _, layers = make_net(B, H, W, seed=3)
     rng = np.random.default_rng(4)
