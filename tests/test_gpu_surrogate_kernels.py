@@ -183,6 +183,32 @@ def test_benchmark_shape_layers_match_oracle():
         assert ew < 1e-4 and eb < 1e-4
 
 
+def test_128_channel_forward_beyond_the_partial_buffer():
+    """Layer 2's forward (128 K channels) at 128^2 runs as two 64-channel launches through the
+    weight gradient's FP32 partial buffer while the partial sums fit (up to 18 samples); a
+    batch of 19 takes the 128-pixel tile kernel instead.  Both against the oracle on the first
+    and last image (images are independent)."""
+    H = W = 128
+    for B in (18, 19):
+        net, _, layers = make_net(B, H, W, seed=9)
+        rng = np.random.default_rng(10 + B)
+        w, b = layers[2]
+        _, _, ci, co = sg.layer_info(2)
+        dx, x = bf16_pair(rng.uniform(-1, 1, (B, H, W, ci)))
+        dz = torch.empty((B, H, W, co), dtype=torch.float32, device="cuda")
+        dy = torch.empty((B, H, W, co), dtype=torch.bfloat16, device="cuda")
+        net.conv(2, 0, B, dx, dy, d_z=dz)
+        torch.cuda.synchronize()
+        for img in (0, B - 1):
+            want = S.conv_forward(x[img:img + 1], w, b)
+            z = dz[img:img + 1].cpu().numpy().astype(np.float64)
+            e = np.abs(z - want).max() / np.abs(want).max()
+            print(f"B = {B}, image {img}: forward z rel err {e:.2e}", flush=True)
+            assert e < 1e-5
+            check_bf16_output(to_np(dy[img:img + 1]), S.silu(want), f"layer 2 activation (B = {B}, image {img})")
+        del net
+
+
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
