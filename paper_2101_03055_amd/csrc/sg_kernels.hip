@@ -837,24 +837,30 @@ __global__ __launch_bounds__(64 * kWgWaves, 1) void k_wgrad_rows(const bf16* __r
 // dW = sum over the ns partials, in a fixed order: a workgroup covers 64
 // outputs, its wave g sums partials [g ns / 4, (g + 1) ns / 4) of them, then
 // the four wave sums are added in wave order
-// dW[co][tap][ci] = the fixed-order sum of the ns split partials (four quarters, added in
-// order); the grid's last workgroup adds up the bias partials instead: db[co] = the sum of
-// bpart[0 .. nb-1][co], in two halves added in order
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int ns, int Ci, int Co,
-                                                      float* __restrict__ dW, const float* __restrict__ bpart, int nb,
-                                                      float* __restrict__ db) {
-    __shared__ float red[3][kMaxC];
+// dW[co][tap][ci] = the fixed-order sum of the ns split partials (eight runs, one per wavefront,
+// added in order); the grid's last workgroup adds up the bias partials instead: db[co] = the sum
+// of bpart[0 .. nb-1][co], in four runs added in order
+constexpr int kRedWaves = 8;
+__global__ __launch_bounds__(64 * kRedWaves) void k_wgrad_reduce(const float* __restrict__ part, int ns, int Ci, int Co,
+                                                                 float* __restrict__ dW, const float* __restrict__ bpart,
+                                                                 int nb, float* __restrict__ db) {
+    __shared__ float red[kRedWaves - 1][kMaxC];
     if (blockIdx.x == gridDim.x - 1) {
+        constexpr int G = 64 * kRedWaves / kMaxC;   // runs of the bias partials
         const int co = (int)threadIdx.x % kMaxC, g = (int)threadIdx.x / kMaxC;
-        const int b0 = g * nb / 2, b1 = (g + 1) * nb / 2;
+        const int b0 = g * nb / G, b1 = (g + 1) * nb / G;
         float t = 0.f;
         if (co < Co) {
 #pragma unroll 8
             for (int q = b0; q < b1; ++q) t += bpart[(long long)q * kMaxC + co];
         }
-        if (g == 1) red[0][co] = t;
+        if (g > 0) red[g - 1][co] = t;
         __syncthreads();
-        if (g == 0 && co < Co) db[co] = t + red[0][co];
+        if (g == 0 && co < Co) {
+#pragma unroll
+            for (int k = 0; k < G - 1; ++k) t += red[k][co];
+            db[co] = t;
+        }
         return;
     }
     const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -863,7 +869,7 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     const bool live = k < n;
     float s = 0.f;
     if (live) {
-        const int q0 = g * ns / 4, q1 = (g + 1) * ns / 4;
+        const int q0 = g * ns / kRedWaves, q1 = (g + 1) * ns / kRedWaves;
         const float* src = part + k;
 #pragma unroll 8
         for (int q = q0; q < q1; ++q) s += src[(long long)q * n];
@@ -871,7 +877,8 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     if (g > 0) red[g - 1][j] = s;
     __syncthreads();
     if (g == 0 && live) {
-        s = ((s + red[0][j]) + red[1][j]) + red[2][j];
+#pragma unroll
+        for (int w = 0; w < kRedWaves - 1; ++w) s += red[w][j];
         const int tap = (int)(k / ((long long)Co * Ci));
         const long long rem = k % ((long long)Co * Ci);
         const int co = (int)(rem / Ci), ci = (int)(rem % Ci);
@@ -1288,7 +1295,7 @@ lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const b
         else
             hipLaunchKernelGGL(k_wgrad_rows<64>, grid, dim3(64 * kWgWaves), 0, h->s, dz, xin, part, bpart, H, rows_total, rpw, Ci, Co);
         SGCHK(hipGetLastError());
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64 + 1)), dim3(256), 0, h->s, part, ns, Ci, Co, dw,
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64 + 1)), dim3(64 * kRedWaves), 0, h->s, part, ns, Ci, Co, dw,
                            bpart, nwg, db);
         SGCHK(hipGetLastError());
         return LB_OK;
@@ -1298,7 +1305,7 @@ lb_status launch_wgrad(sg_handle* h, int l, long long P, const bf16* dz, const b
     SGCHK(hipGetLastError());
     hipLaunchKernelGGL(k_bgrad_part, dim3(kRed), dim3(256), 0, h->s, dz, P, Co, bpart);
     SGCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64 + 1)), dim3(256), 0, h->s, part, kSplit, Ci, Co, dw,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64 + 1)), dim3(64 * kRedWaves), 0, h->s, part, kSplit, Ci, Co, dw,
                        bpart, kRed, db);
     SGCHK(hipGetLastError());
     return LB_OK;
