@@ -166,14 +166,14 @@ def test_destagger_matches_oracle():
     assert np.abs((got[:, 1] * sy).mean(axis=(1, 2))).max() <= 1e-7
 
 
-def test_train_epochs_equals_its_steps():
-    """sg_train_epochs (steps back to back, indices uploaded per block of steps, batch
-    losses summed on the device) against the same steps one sg_train_step call at a
-    time in the order its shuffle draws (host copy of its generator): weights and
-    epoch losses bitwise equal."""
+@pytest.mark.parametrize("batch, n, epochs, seed", [(4, 12, 2, 5), (1, 300, 1, 6)])
+def test_train_epochs_equals_its_steps(batch, n, epochs, seed):
+    """sg_train_epochs (steps back to back, indices uploaded per block of 256 steps,
+    batch losses summed on the device) against the same steps one sg_train_step call
+    at a time in the order its shuffle draws (host copy of its generator): weights and
+    epoch losses bitwise equal; 300 steps of one sample cross an index block."""
     from tests.mt64 import shuffled_epochs
 
-    batch, n, epochs, seed = 4, 12, 2, 5
     rng = np.random.default_rng(8)
     dp = torch.tensor(rng.uniform(0, 1, (n, 5)), dtype=torch.float32, device="cuda")
     df = torch.tensor(rng.uniform(-1, 1, (n, 4, H, W)), dtype=torch.float32, device="cuda")
