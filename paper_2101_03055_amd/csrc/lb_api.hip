@@ -97,6 +97,8 @@ Layout make_layout(const lb_params& p) {
     off += 256 * 8;
     L.pref_off = off;
     off += round_up((size_t)p.ny * 8, 256);
+    L.tstep_off = off;
+    off += 256;
     L.pop2_off = L.pop_off;
     L.sold2_off = L.sold_off;
     if (gamma_on(p) && p.fused_steps != 2) {
@@ -389,8 +391,8 @@ struct lb_handle {
     int has_snapshot;
     int device;          // device current at lb_init (the workspace's)
     Launch lc;
-    // cached graph of kGraphSteps single-step launches (FP32/FP64, one step
-    // per launch); rebuilt when the tile shape changes
+    // cached graph of kGraphSteps single-step launches (one step per launch);
+    // rebuilt when the tile shape changes
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     Launch glc{0, 0};
@@ -607,7 +609,7 @@ lb_status lb_step(lb_handle* h, int64_t n) {
     // long runs of single steps: replay a prebuilt graph of kGraphSteps
     // launches (one host call instead of kGraphSteps), which keeps small grids
     // from being limited by the host's launch rate
-    if (h->p.fused_steps != 2 && h->p.storage != LB_STORE_F16 && n >= kGraphSteps + (h->parity ? 1 : 0)) {
+    if (h->p.fused_steps != 2 && n >= kGraphSteps + (h->parity ? 1 : 0)) {
         if (h->parity) {
             hipError_t e = launch_step(h->p, h->L, h->ws, h->kd, h->kf, true, h->lc, h->t, h->stream);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
@@ -622,14 +624,18 @@ lb_status lb_step(lb_handle* h, int64_t n) {
             if (h->graph) (void)hipGraphDestroy(h->graph);
             h->gexec = nullptr;
             h->graph = nullptr;
-            hipError_t e = build_step_graph(h->p, h->L, h->ws, h->kd, h->kf, h->lc, kGraphSteps, &h->graph);
+            hipError_t e = build_step_graph(h->p, h->L, h->ws, h->kd, h->kf, h->lc, kGraphSteps,
+                                            (const long long*)at(h->ws, h->L.tstep_off), &h->graph);
             if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph: %s", hipGetErrorString(e));
             h->glc = h->lc;
             h->gsold = h->L.sold_off;
         }
         for (; n >= kGraphSteps; n -= kGraphSteps) {
-            hipError_t e = hipGraphLaunch(h->gexec, h->stream);
+            hipError_t e = hipSuccess;
+            if (h->p.storage == LB_STORE_F16)   // the replay's stochastic-rounding salts follow the step count
+                e = launch_set_step((long long*)at(h->ws, h->L.tstep_off), h->t, h->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(h->gexec, h->stream);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph launch: %s", hipGetErrorString(e));
             h->t += kGraphSteps;
         }
@@ -986,7 +992,7 @@ struct lbb_handle {
     void* ws;
     size_t ws_bytes;
     hipStream_t stream;
-    size_t kp_off, cav_off, tiles_off, ranges_off, part_off, out_off, stage_off, max_tiles;
+    size_t kp_off, cav_off, tiles_off, ranges_off, part_off, out_off, stage_off, tstep_off, max_tiles;
     std::vector<int> status, parity, has_snap;
     std::vector<int64_t> steps;
     int cur_parity;
@@ -1040,9 +1046,11 @@ size_t batch_plan(const lb_params* params, int count, lbb_handle* b) {
     const size_t tiles_off = take(sizeof(int2) * maxt), ranges_off = take(sizeof(int4) * count);
     const size_t part_off = take(sizeof(double) * kRedWidth * maxt), out_off = take(sizeof(double) * 64 * count);
     const size_t stage_off = take(sizeof(double) * (params[0].m + 3) * N_max);
+    const size_t tstep_off = take(sizeof(long long));   // step count read by replayed FP16 step graphs
     if (b) {
         b->kp_off = kp_off; b->cav_off = cav_off; b->tiles_off = tiles_off; b->ranges_off = ranges_off;
-        b->part_off = part_off; b->out_off = out_off; b->stage_off = stage_off; b->max_tiles = maxt;
+        b->part_off = part_off; b->out_off = out_off; b->stage_off = stage_off; b->tstep_off = tstep_off;
+        b->max_tiles = maxt;
     }
     for (int c = 0; c < count; ++c) {
         Layout Lc = make_layout(params[c]);
@@ -1209,7 +1217,7 @@ lb_status lbb_step(lbb_handle* b, int64_t n) {
     int64_t left = n;
     // long runs: replay a prebuilt graph of kGraphSteps launches (rebuilt when
     // the tile list or the tile shape changes)
-    if (b->p0.storage != LB_STORE_F16 && !b->tiles.empty() && left >= kGraphSteps + (b->cur_parity ? 1 : 0)) {
+    if (!b->tiles.empty() && left >= kGraphSteps + (b->cur_parity ? 1 : 0)) {
         if (b->cur_parity) {
             hipError_t e = launch_bstep(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
                                         (const int2*)(w + b->tiles_off), (int)b->tiles.size(), true, b->lc, b->t,
@@ -1226,14 +1234,17 @@ lb_status lbb_step(lbb_handle* b, int64_t n) {
             b->graph = nullptr;
             hipError_t e = build_bstep_graph(b->p0, b->ws, batch_kparams(b), (const CavRec*)(w + b->cav_off),
                                              (const int2*)(w + b->tiles_off), (int)b->tiles.size(), b->lc, kGraphSteps,
-                                             &b->graph);
+                                             (const long long*)(w + b->tstep_off), &b->graph);
             if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_step graph: %s", hipGetErrorString(e));
             b->g_gen = b->tiles_gen;
             b->g_lc = b->lc;
         }
         for (; left >= kGraphSteps; left -= kGraphSteps) {
-            hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+            hipError_t e = hipSuccess;
+            if (b->p0.storage == LB_STORE_F16)   // the replay's stochastic-rounding salts follow the step count
+                e = launch_set_step((long long*)(w + b->tstep_off), b->t, b->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(b->gexec, b->stream);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lbb_step graph launch: %s", hipGetErrorString(e));
             b->t += kGraphSteps;
         }

@@ -18,8 +18,10 @@ namespace lbk {
 template <class S, int M, int MODEL, int COLL, bool ODD, bool NT>
 __global__ __launch_bounds__(256) void k_bstep(const KParams<typename St<S>::T>* __restrict__ kps,
                                                const CavRec* __restrict__ cav, const int2* __restrict__ tiles,
-                                               int ntiles, char* __restrict__ ws, uint32_t salt) {
+                                               int ntiles, char* __restrict__ ws, uint32_t salt,
+                                               const long long* __restrict__ tstep) {
     using T = typename St<S>::T;
+    salt = launch_salt<S>(salt, tstep);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     if (b >= ntiles) return;
     const int2 t = tiles[b];
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256) void k_bfinal(const int4* __restrict__ ranges,
 hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
                         int ntiles, bool odd, Launch lc, int64_t step, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    const uint32_t salt = mix32((uint32_t)step ^ (uint32_t)(step >> 32) * 0x632be5abu);
+    const uint32_t salt = step_salt(step);
     const dim3 grid((unsigned)ntiles), block((unsigned)(lc.tile_x * lc.tile_y));
     return dispatch(p0, [&]<class S, int M, int MODEL>() -> hipError_t {
         using T = typename St<S>::T;
@@ -155,17 +157,19 @@ hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, cons
         const int2* tl = tiles;
         int nt = ntiles;
         uint32_t sl = salt;
-        void* args[] = {&kp, &cv, &tl, &nt, &w, &sl};
+        const long long* tsp = nullptr;
+        void* args[] = {&kp, &cv, &tl, &nt, &w, &sl, &tsp};
         const void* fn = bstep_kernel<S, M, MODEL>(p0.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     });
 }
 
 // Graph of `steps` (even) batched single-step launches, even parity first,
-// chained; same arguments as launch_bstep.  FP32/FP64 only.
+// chained; same arguments as launch_bstep.  FP16: launch k of a replay takes
+// the stochastic-rounding salt of step *tstep + k (*tstep set before each replay).
 hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
-                             int ntiles, Launch lc, int steps, hipGraph_t* out) {
-    if (p0.storage == LB_STORE_F16 || steps < 2 || steps % 2 || ntiles <= 0) return hipErrorInvalidValue;
+                             int ntiles, Launch lc, int steps, const long long* tstep, hipGraph_t* out) {
+    if (steps < 2 || steps % 2 || ntiles <= 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)ntiles), block((unsigned)(lc.tile_x * lc.tile_y));
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
@@ -177,13 +181,15 @@ hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams,
         const CavRec* cv = cav;
         const int2* tl = tiles;
         int nt = ntiles;
-        uint32_t salt = 0;
-        void* args[] = {&kp, &cv, &tl, &nt, &w, &salt};
+        uint32_t salt = 0;   // launch k: its offset k from *tstep (FP16)
+        const long long* tsp = p0.storage == LB_STORE_F16 ? tstep : nullptr;
+        void* args[] = {&kp, &cv, &tl, &nt, &w, &salt, &tsp};
         const bool mrt = p0.collision == LB_COLL_MRT;
         void* fe = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0));
         void* fo = const_cast<void*>(bstep_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
+            salt = (uint32_t)k;   // the node copies the argument values
             hipKernelNodeParams np{};
             np.func = (k & 1) ? fo : fe;
             np.gridDim = grid;

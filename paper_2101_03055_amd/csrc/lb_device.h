@@ -102,6 +102,19 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
     return x;
 }
+// the stochastic-rounding salt of time step `step` (one value per launch)
+__host__ __device__ __forceinline__ uint32_t step_salt(long long step) {
+    return mix32((uint32_t)step ^ (uint32_t)(step >> 32) * 0x632be5abu);
+}
+// the salt of a launch: given directly, or (tstep non-null: launches replayed from a graph,
+// whose arguments are fixed) as the offset of the launch from the step count in *tstep
+template <class S>
+__device__ __forceinline__ uint32_t launch_salt(uint32_t salt, const long long* tstep) {
+    if constexpr (St<S>::scaled) {
+        if (tstep) return step_salt(*tstep + (long long)salt);
+    }
+    return salt;
+}
 
 // binary16 with stochastic rounding: adding uniform random bits below the 10
 // kept mantissa bits to the magnitude and truncating rounds up with

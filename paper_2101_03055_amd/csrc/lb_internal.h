@@ -57,6 +57,7 @@ struct Layout {
                                  // field at the neighbours while writing the new one)
     size_t naux, aux_off;        // no-fluid model: prescribed u (2 planes) and previous phi - phi_ref (m planes)
     size_t pref_off;             // fluid reference pressure per row (ny values of the arithmetic type)
+    size_t tstep_off;            // step count read by replayed FP16 step graphs (one int64)
 };
 
 constexpr int kRedBlocks = 1024;   // blocks of the first reduction pass (upper bound)
@@ -85,7 +86,9 @@ hipError_t launch_reref(const lb_params& p, const Layout& L, void* ws, const KPa
                         const KParams<float>& kf, const void* pnew, hipStream_t s);
 hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t s);
 hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                            const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out);
+                            const KParams<float>& kf, Launch lc, int steps, const long long* tstep, hipGraph_t* out);
+// *tstep = step (a one-thread kernel: ordered on the stream before a graph replay)
+hipError_t launch_set_step(long long* tstep, long long step, hipStream_t s);
 int reduce_blocks(size_t N);
 hipError_t launch_reduce_final(int Q, const double* part, int nblocks, double* out, int mode, hipStream_t s);
 // no-fluid model (lb_cde.hip)
@@ -136,7 +139,7 @@ struct CavRec {
 
 // one step of every listed tile: tiles[k] = (cavity, tile index in the cavity)
 hipError_t build_bstep_graph(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
-                             int ntiles, Launch lc, int steps, hipGraph_t* out);
+                             int ntiles, Launch lc, int steps, const long long* tstep, hipGraph_t* out);
 hipError_t launch_bstep(const lb_params& p0, void* ws, const void* kparams, const CavRec* cav, const int2* tiles,
                         int ntiles, bool odd, Launch lc, int64_t step, hipStream_t s);
 // per-tile partial sums (mode 0 residual + snapshot, 1 snapshot only, 2 mass),

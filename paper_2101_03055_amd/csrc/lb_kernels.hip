@@ -35,8 +35,10 @@ namespace lbk {
 template <class S, int M, int MODEL, int COLL, bool ODD, bool NT, bool REF>
 __global__ __launch_bounds__(256) void k_step(KParams<typename St<S>::T> kp, S* __restrict__ pop,
                                               const typename St<S>::T* sold, typename St<S>::T* sold_out,
-                                              int tile_x, int tile_y, int tiles_x, uint32_t salt) {
+                                              int tile_x, int tile_y, int tiles_x, uint32_t salt,
+                                              const long long* __restrict__ tstep) {
     using T = typename St<S>::T;
+    salt = launch_salt<S>(salt, tstep);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bx = b % tiles_x, by = b / tiles_x;
     const int x = bx * tile_x + (int)(threadIdx.x % tile_x);
@@ -605,7 +607,7 @@ hipError_t launch_init(const lb_params& p, const Layout& L, void* ws, const KPar
 
 hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                        const KParams<float>& kf, bool odd, Launch lc, int64_t step, hipStream_t s) {
-    const uint32_t salt = mix32((uint32_t)step ^ (uint32_t)(step >> 32) * 0x632be5abu);
+    const uint32_t salt = step_salt(step);
     const int tiles_x = (p.nx + lc.tile_x - 1) / lc.tile_x;
     const int tiles_y = (p.ny + lc.tile_y - 1) / lc.tile_y;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)(lc.tile_x * lc.tile_y));
@@ -619,7 +621,8 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
         T* sold_out = kp.gam_on ? (T*)at(ws, L.sold2_off) : sold;
         int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
         uint32_t sl = salt;
-        void* args[] = {&kp, &pop, &sold, &sold_out, &tx, &ty, &tsx, &sl};
+        const long long* tsp = nullptr;
+        void* args[] = {&kp, &pop, &sold, &sold_out, &tx, &ty, &tsx, &sl, &tsp};
         const void* fn = step_kernel<S, M, MODEL>(p.collision == LB_COLL_MRT, odd, (lc.nt >> (odd ? 1 : 0) & 1) != 0,
                                                   kp.pref != nullptr);
         return hipLaunchKernel(fn, grid, block, args, 0, s);
@@ -629,10 +632,11 @@ hipError_t launch_step(const lb_params& p, const Layout& L, void* ws, const KPar
 // A graph of `steps` (even) single-step launches, even parity first, each
 // node depending on the previous one.  Built node by node (no stream
 // capture), so it can be launched on any stream, including the null stream.
-// FP32/FP64 only: the FP16 stochastic-rounding salt changes every step.
+// FP16: launch k of a replay takes the stochastic-rounding salt of step
+// *tstep + k, *tstep set to the step count before each replay (launch_set_step).
 hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
-                            const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out) {
-    if (p.storage == LB_STORE_F16 || steps < 2 || steps % 2) return hipErrorInvalidValue;
+                            const KParams<float>& kf, Launch lc, int steps, const long long* tstep, hipGraph_t* out) {
+    if (steps < 2 || steps % 2) return hipErrorInvalidValue;
     const int tiles_x = (p.nx + lc.tile_x - 1) / lc.tile_x;
     const int tiles_y = (p.ny + lc.tile_y - 1) / lc.tile_y;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)(lc.tile_x * lc.tile_y));
@@ -647,15 +651,17 @@ hipError_t build_step_graph(const lb_params& p, const Layout& L, void* ws, const
         KParams<T> kp = kpar<S>(kd, kf);
         T* sbuf[2] = {(T*)at(ws, L.sold_off), (T*)at(ws, kp.gam_on ? L.sold2_off : L.sold_off)};
         int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
-        uint32_t salt = 0;
-        void* args[2][8] = {{&kp, &pop, &sbuf[0], &sbuf[1], &tx, &ty, &tsx, &salt},
-                            {&kp, &pop, &sbuf[1], &sbuf[0], &tx, &ty, &tsx, &salt}};
+        uint32_t salt = 0;   // launch k: its offset k from *tstep (FP16)
+        const long long* tsp = p.storage == LB_STORE_F16 ? tstep : nullptr;
+        void* args[2][9] = {{&kp, &pop, &sbuf[0], &sbuf[1], &tx, &ty, &tsx, &salt, &tsp},
+                            {&kp, &pop, &sbuf[1], &sbuf[0], &tx, &ty, &tsx, &salt, &tsp}};
         const bool mrt = p.collision == LB_COLL_MRT;
         const bool ref = kp.pref != nullptr;
         void* fe = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, false, (lc.nt & 1) != 0, ref));
         void* fo = const_cast<void*>(step_kernel<S, M, MODEL>(mrt, true, (lc.nt & 2) != 0, ref));
         hipGraphNode_t prev = nullptr;
         for (int k = 0; k < steps; ++k) {
+            salt = (uint32_t)k;   // the node copies the argument values
             hipKernelNodeParams np{};
             np.func = (k & 1) ? fo : fe;
             np.gridDim = grid;
@@ -760,6 +766,15 @@ hipError_t launch_row_pressure(const lb_params& p, const Layout& L, void* ws, co
             hipLaunchKernelGGL((k_row_pressure<S, M, false>), dim3((unsigned)p.ny), dim3(256), 0, s, kpar<S>(kd, kf), pop, out);
         return hipGetLastError();
     });
+}
+
+__global__ void k_set_step(long long* __restrict__ tstep, long long step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tstep = step;
+}
+
+hipError_t launch_set_step(long long* tstep, long long step, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, tstep, step);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t s) {

@@ -1,7 +1,9 @@
-"""lb_step replays a prebuilt graph of 64 single-step launches for long runs
-(FP32/FP64).  Every replay must equal the plain launch path bit for bit, with
-the program's own eager work and synchronisations between replays, across a
-tile change (graph rebuilt) and from either AA parity."""
+"""lb_step replays a prebuilt graph of 64 single-step launches for long runs.
+Every replay must equal the plain launch path bit for bit, with the program's
+own eager work and synchronisations between replays, across a tile change
+(graph rebuilt) and from either AA parity.  FP16 included: a replayed launch
+takes its stochastic-rounding salt from the step count the host sets before
+the replay, so the dither equals that of the plain launches."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,10 @@ def eager(s, n):
         s.step(1)  # below the graph threshold: one launch per call
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+F16 = {"storage": "f16", "phi_ref": [1.0, 1.0], "fp16_scale": 100.0, "fp16_scale_h": 1000.0}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("kind", ["walls", "chemotaxis"])
 def test_graph_replays_equal_plain_launches(storage, kind):
     if kind == "walls":
@@ -24,7 +29,7 @@ def test_graph_replays_equal_plain_launches(storage, kind):
     else:
         case = W.random_case(64, 40, seed=62, model="chemotaxis", fluid_bc=["periodic", "periodic", "noslip", "freeslip"],
                              scalar_bc=[["periodic"] * 2, ["periodic"] * 2, ["noflux"] * 2, ["noflux", "dirichlet"]])
-    kw = {"storage": storage, "phi_ref": [1.0, 1.0]} if storage == "f32" else {}
+    kw = {"f32": {"storage": "f32", "phi_ref": [1.0, 1.0]}, "f16": F16}.get(storage, {})
     g = lb.Solver(*case, **kw)
     e = lb.Solver(*case, **kw)
     for n, tile in ((64, None), (65, None), (130, (128, 1)), (64, (64, 2)), (193, None)):
@@ -35,7 +40,7 @@ def test_graph_replays_equal_plain_launches(storage, kind):
         eager(e, n)
         assert g.t == e.t
         for x, y in zip(g.moments(), e.moments()):
-            assert np.array_equal(x, y), (n, tile)
+            assert np.all(np.isfinite(x)) and np.array_equal(x, y), (n, tile)
         g.residual()
         e.residual()
     fg, hg = lb.lb_populations(g.handle, g.m, g.ny, g.nx)
@@ -48,8 +53,9 @@ def test_batched_graph_replays_equal_plain_launches():
              W.random_case(50, 61, seed=42, source=True, fluid_bc=["periodic", "periodic", "noslip", "noslip"],
                            scalar_bc=[["periodic"] * 2, ["periodic"] * 2, ["noflux"] * 2, ["dirichlet"] * 2]),
              W.ddc(32, Ra=1e3, Pr=0.71, Le=1.5, Nc=0.5, Sr=0.0, Df=0.3, A=2.0)]
-    for storage in ("f64", "f32"):
-        kw = {"storage": storage, "phi_ref": [0.5, 0.5]} if storage == "f32" else {"storage": storage}
+    for storage in ("f64", "f32", "f16"):
+        kw = {"f32": {"storage": "f32", "phi_ref": [0.5, 0.5]},
+              "f16": {"storage": "f16", "phi_ref": [0.5, 0.5], "fp16_scale": 1e3, "fp16_scale_h": 1e4}}.get(storage, {"storage": storage})
         g = lb.Batch(cases, **kw)
         e = lb.Batch(cases, **kw)
         for n in (64, 131, 70):
@@ -58,4 +64,4 @@ def test_batched_graph_replays_equal_plain_launches():
                 e.step(1)
             for i in range(len(cases)):
                 for x, y in zip(g.moments(i), e.moments(i)):
-                    assert np.array_equal(x, y), (storage, n, i)
+                    assert np.all(np.isfinite(x)) and np.array_equal(x, y), (storage, n, i)
