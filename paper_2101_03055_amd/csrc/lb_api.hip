@@ -581,6 +581,31 @@ lb_status lb_step(lb_handle* h, int64_t n) {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (n < 0) return fail(LB_EINVAL, "n = %lld < 0", (long long)n);
     if (h->p.model == LB_MODEL_CDE) {
+        // long runs: replay a prebuilt graph of kGraphSteps launches, as for the fluid model
+        if (n >= kGraphSteps + (h->parity ? 1 : 0)) {
+            if (h->parity) {
+                hipError_t e = launch_cde_step(h->p, h->L, h->ws, h->kd, h->kf, true, h->lc, h->stream);
+                if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));
+                h->t += 1;
+                h->parity = 0;
+                n -= 1;
+            }
+            if (!h->gexec || h->glc.tile_x != h->lc.tile_x || h->glc.tile_y != h->lc.tile_y) {
+                if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+                if (h->graph) (void)hipGraphDestroy(h->graph);
+                h->gexec = nullptr;
+                h->graph = nullptr;
+                hipError_t e = build_cde_step_graph(h->p, h->L, h->ws, h->kd, h->kf, h->lc, kGraphSteps, &h->graph);
+                if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph: %s", hipGetErrorString(e));
+                h->glc = h->lc;
+            }
+            for (; n >= kGraphSteps; n -= kGraphSteps) {
+                hipError_t e = hipGraphLaunch(h->gexec, h->stream);
+                if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step graph launch: %s", hipGetErrorString(e));
+                h->t += kGraphSteps;
+            }
+        }
         for (int64_t s = 0; s < n; ++s) {
             hipError_t e = launch_cde_step(h->p, h->L, h->ws, h->kd, h->kf, h->parity != 0, h->lc, h->stream);
             if (e != hipSuccess) return fail(LB_EDEVICE, "lb_step launch: %s", hipGetErrorString(e));

@@ -391,6 +391,52 @@ hipError_t launch_cde_step(const lb_params& p, const Layout& L, void* ws, const 
     });
 }
 
+// A graph of `steps` (even) no-fluid step launches, even parity first, chained; built node
+// by node like the fluid model's step graph (the arguments are the same for every launch of
+// a parity: the previous-phi planes are updated in place)
+hipError_t build_cde_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                                const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out) {
+    if (steps < 2 || steps % 2) return hipErrorInvalidValue;
+    const int tiles_x = (p.nx + lc.tile_x - 1) / lc.tile_x;
+    const int tiles_y = (p.ny + lc.tile_y - 1) / lc.tile_y;
+    const dim3 grid((unsigned)(tiles_x * tiles_y)), block((unsigned)(lc.tile_x * lc.tile_y));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    e = dispatch_cde(p, [&]<class S, int M>() -> hipError_t {
+        using T = typename St<S>::T;
+        S* pop = (S*)at(ws, L.pop_off);
+        T* sold = (T*)at(ws, L.sold_off);
+        T* aux = (T*)at(ws, L.aux_off);
+        KParams<T> kp = kpar<S>(kd, kf);
+        int tx = lc.tile_x, ty = lc.tile_y, tsx = tiles_x;
+        void* args[] = {&kp, &pop, &sold, &aux, &tx, &ty, &tsx};
+        void* fe = reinterpret_cast<void*>((lc.nt & 1) ? &k_cde_step<S, M, false, true> : &k_cde_step<S, M, false, false>);
+        void* fo = reinterpret_cast<void*>((lc.nt & 2) ? &k_cde_step<S, M, true, true> : &k_cde_step<S, M, true, false>);
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < steps; ++k) {
+            hipKernelNodeParams np{};
+            np.func = (k & 1) ? fo : fe;
+            np.gridDim = grid;
+            np.blockDim = block;
+            np.sharedMemBytes = 0;
+            np.kernelParams = args;
+            np.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t ee = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            if (ee != hipSuccess) return ee;
+            prev = node;
+        }
+        return hipSuccess;
+    });
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    *out = g;
+    return hipSuccess;
+}
+
 hipError_t launch_cde_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                               const KParams<float>& kf, bool odd, double* phi, double* u, double* pr, hipStream_t s) {
     return dispatch_cde(p, [&]<class S, int M>() -> hipError_t {

@@ -96,6 +96,8 @@ hipError_t launch_cde_init(const lb_params& p, const Layout& L, void* ws, const 
                            const KParams<float>& kf, hipStream_t s);
 hipError_t launch_cde_step(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                            const KParams<float>& kf, bool odd, Launch lc, hipStream_t s);
+hipError_t build_cde_step_graph(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
+                                const KParams<float>& kf, Launch lc, int steps, hipGraph_t* out);
 hipError_t launch_cde_moments(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,
                               const KParams<float>& kf, bool odd, double* phi, double* u, double* pr, hipStream_t s);
 hipError_t launch_cde_export(const lb_params& p, const Layout& L, void* ws, const KParams<double>& kd,

@@ -65,3 +65,23 @@ def test_batched_graph_replays_equal_plain_launches():
             for i in range(len(cases)):
                 for x, y in zip(g.moments(i), e.moments(i)):
                     assert np.all(np.isfinite(x)) and np.array_equal(x, y), (storage, n, i)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_no_fluid_graph_replays_equal_plain_launches(storage):
+    """The no-fluid model (prescribed flow) replays its step graph the same way."""
+    case = W.cde_case(67, 45, m=2, seed=5, walls=True, source=True)
+    kw = {"storage": "f32", "phi_ref": [1.0, 1.0]} if storage == "f32" else {}
+    g = lb.Solver(*case, **kw)
+    e = lb.Solver(*case, **kw)
+    for n, tile in ((64, None), (65, None), (130, (64, 2)), (193, None)):
+        if tile:
+            lb.lb_set_tile(g.handle, *tile)
+            lb.lb_set_tile(e.handle, *tile)
+        g.step(n)
+        eager(e, n)
+        assert g.t == e.t
+        for x, y in zip(g.moments(), e.moments()):
+            assert np.all(np.isfinite(x)) and np.array_equal(x, y), (n, tile)
+        g.residual()
+        e.residual()
