@@ -732,6 +732,15 @@ struct lb3_handle {
     int tile_x, tile_y;
     int nt_bits;  // bit 0: hint on even steps, bit 1: on odd steps
     std::vector<double> part_host;  // per-block totals of lb3_mass
+    // cached graph of kGraphSteps3 step launches (even parity first) for long runs; rebuilt
+    // when the tile shape changes
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_tx = 0, g_ty = 0;
+    ~lb3_handle() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
 };
 
 namespace {
@@ -779,6 +788,48 @@ hipError_t launch3_step(lb3_handle* h, bool odd) {
         }
         return hipGetLastError();
     });
+}
+
+// a graph of `steps` (even) step launches, even parity first, chained, built node by node
+// (the launches of one parity have the same arguments: populations and sources in place)
+constexpr int kGraphSteps3 = 64;
+hipError_t build3_step_graph(lb3_handle* h, int steps, hipGraph_t* out) {
+    const Geo g = geo_of(h);
+    const dim3 grid(grid_of(h, g)), block((unsigned)(h->tile_x * h->tile_y));
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipGraphCreate(&gr, 0);
+    if (e != hipSuccess) return e;
+    e = dispatch3(h->p, [&]<class S, int M>() -> hipError_t {
+        using T = typename St<S>::T;
+        S* pop = (S*)at3(h->ws, h->L.pop_off);
+        T* sold = (T*)at3(h->ws, h->L.sold_off);
+        K3<T> kp = kpar3<S>(h);
+        Geo geo = g;
+        void* args[] = {&kp, &pop, &sold, &geo};
+        void* fe = reinterpret_cast<void*>((h->nt_bits & 1) ? &k3_step<S, M, false, true> : &k3_step<S, M, false, false>);
+        void* fo = reinterpret_cast<void*>((h->nt_bits & 2) ? &k3_step<S, M, true, true> : &k3_step<S, M, true, false>);
+        hipGraphNode_t prev = nullptr;
+        for (int k = 0; k < steps; ++k) {
+            hipKernelNodeParams np{};
+            np.func = (k & 1) ? fo : fe;
+            np.gridDim = grid;
+            np.blockDim = block;
+            np.sharedMemBytes = 0;
+            np.kernelParams = args;
+            np.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t ee = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &np);
+            if (ee != hipSuccess) return ee;
+            prev = node;
+        }
+        return hipSuccess;
+    });
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return e;
+    }
+    *out = gr;
+    return hipSuccess;
 }
 
 lb_status check_handle(lb3_handle* h) {
@@ -855,6 +906,28 @@ lb_status lb3_init(const lb3_params* params, void* ws, size_t ws_bytes, void* st
 lb_status lb3_step(lb3_handle* h, int64_t n) {
     if (lb_status s = check_handle(h); s != LB_OK) return s;
     if (n < 0) return fail3(LB_EINVAL, "n = %lld < 0", (long long)n);
+    // long runs: replay a prebuilt graph of kGraphSteps3 launches (one host call each)
+    if (n >= kGraphSteps3 + (h->t & 1)) {
+        if (h->t & 1) {
+            HIP3(launch3_step(h, true));
+            ++h->t;
+            --n;
+        }
+        if (!h->gexec || h->g_tx != h->tile_x || h->g_ty != h->tile_y) {
+            if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+            if (h->graph) (void)hipGraphDestroy(h->graph);
+            h->gexec = nullptr;
+            h->graph = nullptr;
+            HIP3(build3_step_graph(h, kGraphSteps3, &h->graph));
+            HIP3(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+            h->g_tx = h->tile_x;
+            h->g_ty = h->tile_y;
+        }
+        for (; n >= kGraphSteps3; n -= kGraphSteps3) {
+            HIP3(hipGraphLaunch(h->gexec, h->stream));
+            h->t += kGraphSteps3;
+        }
+    }
     for (int64_t k = 0; k < n; ++k) {
         HIP3(launch3_step(h, (h->t & 1) != 0));
         ++h->t;

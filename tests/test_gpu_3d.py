@@ -121,3 +121,27 @@ def test_larger_box_against_oracle(oracle3_mod):
     o, g = run3(oracle3_mod, case, 12)
     ef, eh, em = errors3(o, g)
     assert ef <= TOL64 and eh <= TOL64 and em <= TOL64
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_graph_replays_equal_plain_launches(storage):
+    """Long runs replay a graph of 64 step launches: bitwise equal to one launch per call,
+    from either parity and across a tile change (graph rebuilt)."""
+    fb, sb = BC3["box_walls"]
+    case = W.random_case3(21, 13, 11, m=2, seed=7, fluid_bc=fb, scalar_bc=sb, source=True)
+    kw = {"phi_ref": [1.0, 1.0]} if storage == "f32" else {}
+    g = lb3.Solver3(*case, storage=storage, **kw)
+    e = lb3.Solver3(*case, storage=storage, **kw)
+    for n, tile in ((64, None), (65, None), (130, (64, 2)), (193, None)):
+        if tile:
+            g.set_tile(*tile)
+            e.set_tile(*tile)
+        g.step(n)
+        for _ in range(n):
+            e.step(1)
+        assert g.t == e.t
+        for x, y in zip(g.moments(), e.moments()):
+            assert np.all(np.isfinite(x)) and np.array_equal(x, y), (n, tile)
+    fg, hg = g.populations()
+    fe, he = e.populations()
+    assert np.array_equal(fg, fe) and np.array_equal(hg, he)
